@@ -1,0 +1,244 @@
+#!/usr/bin/env python3
+"""Benchmark of the FLR hot path on one MI355X.
+
+Workload: one 1920x1080 RGB frame per step (8 guides + the implied constant,
+window radius 8, regulariser 1e-3, coefficients window-averaged), the whole
+path fused into one kernel launch through the C ABI. Inputs are seeded
+synthetic frames resident in HBM before timing starts; several distinct
+input/output buffer sets (more than the 256 MB Infinity Cache in total) are
+used in rotation so that repeated steps cannot be served from that cache.
+
+Prints one JSON line. Besides throughput it reports the dominant kernel's
+roofline figures (algorithmic FP64 flops per launch over the launch's
+average duration from HIP events recorded on the launch stream) and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+H, W, Q, C, R, EPS = 1080, 1920, 8, 3, 8, 1e-3
+PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (= 256 CU x 64 lanes x 2 x 2.4 GHz)
+PEAK_HBM_GBPS = 8000.0       # MI355X HBM3E
+ALGO_BYTES_PER_PX = 4 * (Q + C) + 4 * C   # read guides + noisy, write output: 56 B
+
+
+def algo_flops_per_px(Q: int, C: int) -> int:
+    """Algorithmic flops per output pixel (FMA = 2), excluding halo recompute.
+
+    Counted term by term for one pixel of the fused path; the derivation is
+    written out next to the roofline in the design notes.
+    """
+    NP = Q * (Q + 1) // 2
+    NS = Q + C + NP + Q * C
+    FC = (Q + 1) * C
+    moments = 4 * (NP + Q * C) + 2 * (Q + C) + 2 * NS       # vertical slide of products, horizontal slide
+    centre = (Q + C) + 3 * (NP + Q * C)                      # means, covariances
+    regul = Q
+    chol = 2 * sum(j * (Q - j) for j in range(Q)) + Q * (Q - 1) // 2 + Q   # FMAs, scalings, rsqrt
+    subst = 2 * (2 * (Q * (Q - 1) // 2) * C) + 2 * Q * C     # two triangular solves, C RHS
+    bias = 2 * Q * C
+    average = 4 * FC + C                                     # vertical + horizontal slide, scale
+    recon = 2 * Q * C + C
+    return moments + centre + regul + chol + subst + bias + average + recon
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2410_11625_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hpp")) + [os.path.join(csrc, "flr_q08.hip")]):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "flr_fused_1080p_rgb_q8_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_source_digest") != kernel_source_digest():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline_child() -> None:
+    """Runs in a child process with one BLAS/OpenMP thread: the oracle on a
+    256x256 crop of the 1080p workload frame."""
+    import numpy as np
+    from oracle import flr_ref
+    from synth import make_config
+    fr = make_config(1)
+    y0, x0 = 412, 832
+    noisy = np.ascontiguousarray(fr["noisy"][:, y0:y0 + 256, x0:x0 + 256])
+    guides = np.ascontiguousarray(fr["guides"][:, y0:y0 + 256, x0:x0 + 256])
+    times = []
+    for _ in range(2):
+        t = time.perf_counter()
+        flr_ref.flr_reference(noisy, guides, R, EPS)
+        times.append(time.perf_counter() - t)
+    print(json.dumps({"seconds": min(times), "pixels": 256 * 256, "runs": len(times)}))
+
+
+def cpu_baseline():
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
+        env[k] = "1"
+    res = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child"],
+                         stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env,
+                         timeout=600, cwd=ROOT)
+    if res.returncode != 0:
+        print(res.stderr[-2000:], file=sys.stderr)
+        return None
+    d = json.loads(res.stdout.strip().splitlines()[-1])
+    return {"value": round(d["pixels"] / d["seconds"] / 1e6, 5), "unit": "Mpixel/s", "cores": 1,
+            "kind": "oracle",
+            "sample": (f"FP64 NumPy oracle (window sums as shifted adds, batched solves), one "
+                       f"256x256 crop of the 1080p workload frame, same guides/radius/eps, best "
+                       f"of {d['runs']} runs ({d['seconds']:.1f} s each), 1 thread")}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--unfused", action="store_true", help="time the three-stage path instead")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
+    args = ap.parse_args(argv)
+
+    if args.cpu_baseline_child:
+        cpu_baseline_child()
+        return 0
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (a frame is not split across GPUs; "
+              "independent frames would be distributed one per GPU). Run with --gpus 1.",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2410_11625_amd as flr
+    from synth import make_config
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    # Input/output sets: >= 4 and > 256 MB in total.
+    per_set = (Q + 2 * C) * H * W * 4
+    nsets = max(4, -(-300_000_000 // per_set))
+    sets = []
+    for s in range(nsets):
+        fr = make_config(1, seed=1 + 1000 * s) if s < 2 else None
+        if fr is None:   # remaining sets: permuted copies (distinct memory, same statistics)
+            base = sets[s % 2]
+            sets.append((base[0].roll(s, dims=2).contiguous(), base[1].roll(s, dims=2).contiguous(),
+                         torch.empty((C, H, W), dtype=torch.float32, device=dev)))
+            continue
+        sets.append((torch.from_numpy(fr["noisy"]).to(dev), torch.from_numpy(fr["guides"]).to(dev),
+                     torch.empty((C, H, W), dtype=torch.float32, device=dev)))
+    fused = not args.unfused
+    p = flr.make_params(H, W, Q, C, R, eps=EPS, average=True, fused=fused)
+    ws_bytes = flr.workspace_bytes(p)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+
+    def step(k):
+        noisy, guides, out = sets[k % nsets]
+        flr.denoise(noisy, guides, radius=R, eps=EPS, average=True, fused=fused, out=out,
+                    workspace=ws)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream(dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    t_all0 = torch.cuda.Event(enable_timing=True)
+    t_all1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_all0.record(stream)
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        step(k)
+        ev[k][1].record(stream)
+    t_all1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t_all0.elapsed_time(t_all1)
+    per = np.array([a.elapsed_time(b) for a, b in ev])
+    ms_per_step = total_ms / args.steps
+
+    pix = H * W
+    mpix_s = pix / (ms_per_step / 1e3) / 1e6
+    kern_ms = float(np.mean(per))
+    flops = algo_flops_per_px(Q, C) * pix
+    achieved_tflops = flops / (kern_ms / 1e3) / 1e12
+    hbm_gbps = ALGO_BYTES_PER_PX * pix / (kern_ms / 1e3) / 1e9
+    traffic = load_traffic()
+
+    # parity of the timed launches' output against the oracle on sampled blocks
+    from oracle import flr_ref
+    fr0 = make_config(1, seed=1)
+    got = sets[0][2].cpu().numpy()
+    errs = []
+    for (y0, y1, x0, x1) in [(0, 16, 0, 32), (520, 540, 940, 972), (H - 16, H, W - 32, W)]:
+        want = flr_ref.flr_reference_block(fr0["noisy"], fr0["guides"], R, EPS, y0, y1, x0, x1)
+        rms = np.sqrt(np.mean(want ** 2))
+        errs.append(float(np.max(np.abs(got[:, y0:y1, x0:x1] - want) /
+                              np.maximum(np.abs(want), 1e-3 * rms))))
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline()
+    line = {
+        "metric": "Mpixel/s at 1080p (FLR, fused), ms/frame, % roofline, err vs FP64",
+        "value": round(mpix_s, 2),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "FLR 1920x1080 RGB frame, 8 guides + constant, radius 8, "
+                               "eps 1e-3, ridge, window-averaged coefficients",
+                   "path": "fused" if fused else "unfused (moments -> solve -> apply)",
+                   "io_dtype": "f32", "accumulate_dtype": "f64", "buffer_sets": nsets,
+                   "ms_per_frame_p10_p50_p90": [round(float(np.percentile(per, q)), 5)
+                                                for q in (10, 50, 90)],
+                   "max_rel_err_vs_fp64_sampled": max(errs)},
+        "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3),
+                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved_tflops / PEAK_FP64_TFLOPS, 4),
+                     "traffic": traffic,
+                     "algo_flops_per_px": algo_flops_per_px(Q, C),
+                     "hbm_algo_GBps": round(hbm_gbps, 1),
+                     "hbm_frac": round(hbm_gbps / PEAK_HBM_GBPS, 4)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,155 @@
+/*
+ * flr.h - C ABI of the Fast Local Regression (FLR) library for AMD MI355X (gfx950).
+ *
+ * FLR fits, for every pixel k, a regularised affine model from a set of
+ * noise-free guide images to a noisy image over the square window T_k of
+ * radius r centred on k, and evaluates it at k (Sec. 3.1, Eqs. matX, matY,
+ * closed_form; Sec. 3.2). The window is clipped to the image, so it holds
+ * n_k = (rows of T_k inside the image) x (columns inside) pixels.
+ *
+ * The path has four stages, each with its own entry point, plus a fused one:
+ *   flr_moments  window moments of the guides and the noisy image (Sec. 3.2:
+ *                box-filtering the outer-product tensors gives X_k^T X_k and
+ *                X_k^T Y_k exactly), returned as central moments;
+ *   flr_solve    the regularised small SPD solve per pixel (Eq. closed_form
+ *                with Eq. tikhonov, or the Appendix normalisation);
+ *   flr_apply    optional window-average of the coefficients, then the
+ *                reconstruction I_k = x_k A_k (Sec. 3.1);
+ *   flr_denoise  all of the above, fused into one kernel or as three stages.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Arrays are planar float32, each plane dense row-major [H][W] with the
+ * planes back to back (plane stride H*W elements):
+ *   guides  [Q][H][W]   the Q guide images, WITHOUT the constant-1 guide,
+ *                       which is always implied (Sec. 3.1: the first column
+ *                       of X_k is all ones);
+ *   noisy   [C][H][W]   the noisy channels (Y);
+ *   out     [C][H][W]   the reconstruction;
+ *   moments [M][H][W]   M = flr_num_moment_planes(Q, C) planes, in order
+ *                       n | mu_g[Q] | nu_y[C] | Wcov upper triangle row-major
+ *                       [Q(Q+1)/2] | Vcov[q][c] row-major [Q*C], where mu, nu
+ *                       are window means, Wcov = S/n - mu mu^T (the
+ *                       Appendix's W) and Vcov = X^T Y / n - mu nu^T;
+ *   coeffs  [F*C][H][W] F = Q+1 planes per channel, in order b[c] for every
+ *                       c, then a[q][c] row-major: the model at pixel k is
+ *                       y_c = b[c] + sum_q g_q a[q][c] in original units.
+ *
+ * Regulariser (eps is added in covariance scale, i.e. to moments divided by
+ * n, so its meaning does not depend on the window size):
+ *   FLR_REG_RIDGE  (Wcov + eps I) a = Vcov, b = nu - a^T mu: Eq. tikhonov
+ *                  with the bias coefficient left unpenalised;
+ *   FLR_REG_PAPER  the Appendix normalisation: W^ = Wcov + eps_mul (mu mu^T +
+ *                  diag(mu o mu)) + eps I, then the correlation-matrix solve
+ *                  (C^ + eps I) A^ = B^, which equals
+ *                  (W^ + eps diag(W^)) a = Vcov.
+ *
+ * Ownership: every pointer is caller-owned DEVICE memory (e.g. the data
+ * pointer of a torch tensor on the current GPU); the library never
+ * allocates, keeps no per-call state and is reentrant. `stream` is a
+ * hipStream_t (NULL = the default stream). Pointers must be 16-byte aligned.
+ * Outputs may not overlap inputs.
+ *
+ * Errors: arguments are validated on the host before any HIP call; a
+ * non-zero flr_status is returned and nothing is launched. A launch failure
+ * returns FLR_ERR_HIP. Kernels run asynchronously on `stream`; faults
+ * surface at the caller's next synchronisation. NaN/Inf inputs propagate to
+ * the outputs; nothing is clamped except Cholesky pivots, which are kept
+ * >= 1e-30 so that a singular system (eps = 0, flat window) stays finite.
+ */
+#ifndef FLR_H
+#define FLR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FLR_MAX_GUIDES 12   /* Q: 1..12 guides, plus the implied constant */
+#define FLR_MAX_CHANNELS 4  /* C: 1..4 noisy channels */
+#define FLR_MAX_RADIUS 32   /* r: 0..32, window (2r+1)^2 */
+#define FLR_MAX_DIM 32768   /* H, W: 1..32768 */
+
+typedef enum {
+  FLR_OK = 0,
+  FLR_ERR_NULL = 1,       /* a required pointer is NULL */
+  FLR_ERR_SHAPE = 2,      /* height/width outside 1..FLR_MAX_DIM */
+  FLR_ERR_RADIUS = 3,     /* radius outside 0..FLR_MAX_RADIUS */
+  FLR_ERR_EPS = 4,        /* eps or eps_mul negative or not finite */
+  FLR_ERR_CHANNELS = 5,   /* num_guides or num_channels out of range */
+  FLR_ERR_ALIAS = 6,      /* an output overlaps an input */
+  FLR_ERR_ALIGN = 7,      /* a pointer is not 16-byte aligned */
+  FLR_ERR_WORKSPACE = 8,  /* workspace missing or smaller than required */
+  FLR_ERR_MODE = 9,       /* reg_mode / flags / boolean field invalid */
+  FLR_ERR_HIP = 10        /* a HIP launch failed */
+} flr_status;
+
+typedef enum { FLR_REG_RIDGE = 0, FLR_REG_PAPER = 1 } flr_reg_mode;
+
+/* flags */
+#define FLR_FLAG_RAW_MOMENTS 1u /* flr_moments only: write raw window sums
+                                   n | sum g | sum y | sum g_p g_q | sum g_q y_c
+                                   (same plane order, nothing centred or divided).
+                                   Exact for small-integer inputs. */
+
+typedef struct {
+  int32_t height, width;   /* H, W in pixels */
+  int32_t num_guides;      /* Q, excluding the implied constant guide */
+  int32_t num_channels;    /* C */
+  int32_t radius;          /* r */
+  float eps;               /* additive regulariser, finite, >= 0 */
+  float eps_mul;           /* FLR_REG_PAPER multiplicative term, finite, >= 0 */
+  int32_t reg_mode;        /* flr_reg_mode */
+  int32_t average_coeffs;  /* 1: average (b, a) over the window before
+                              reconstruction; 0: use the pixel's own model */
+  int32_t fused;           /* flr_denoise: 1 = one fused kernel,
+                              0 = flr_moments -> flr_solve -> flr_apply */
+  uint32_t flags;          /* FLR_FLAG_* */
+  int32_t tile_rows;       /* rows per workgroup segment; 0 = automatic */
+} flr_params;
+
+/* Number of moment planes M = 1 + Q + C + Q(Q+1)/2 + Q*C (0 if out of range). */
+size_t flr_num_moment_planes(int32_t num_guides, int32_t num_channels);
+/* Number of coefficient planes (Q+1)*C (0 if out of range). */
+size_t flr_num_coeff_planes(int32_t num_guides, int32_t num_channels);
+
+/* Workspace bytes flr_denoise needs for these parameters (0 if invalid):
+ * unfused: the moment and coefficient images, (M + F*C)*H*W floats;
+ * fused with averaging: a per-workgroup ring of 2r+1 coefficient rows;
+ * fused without averaging: 0. Depends on the launch geometry only. */
+size_t flr_denoise_workspace_bytes(const flr_params* p);
+
+/* Window moments (Sec. 3.2). Reads guides, noisy; writes moments [M][H][W]. */
+flr_status flr_moments(const flr_params* p, const float* guides, const float* noisy,
+                       float* moments, void* stream);
+
+/* Per-pixel regularised solve (Eq. closed_form with Eq. tikhonov / Appendix).
+ * Reads central moments [M][H][W] as written by flr_moments; writes coeffs
+ * [F*C][H][W] in original units. Uses reg_mode, eps, eps_mul. */
+flr_status flr_solve(const flr_params* p, const float* moments, float* coeffs, void* stream);
+
+/* Window-average of the coefficients if p->average_coeffs (same clipped
+ * window as the moments), then reconstruction out_c = b_c + sum_q g_q a_qc
+ * (Sec. 3.1). Reads guides and coeffs; writes out [C][H][W]. */
+flr_status flr_apply(const flr_params* p, const float* guides, const float* coeffs,
+                     float* out, void* stream);
+
+/* The whole path. workspace must hold flr_denoise_workspace_bytes(p) bytes
+ * (NULL allowed when that is 0). Concurrent calls must use distinct
+ * workspaces. */
+flr_status flr_denoise(const flr_params* p, const float* guides, const float* noisy,
+                       float* out, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Static description of a status code. */
+const char* flr_status_str(flr_status s);
+
+/* Host-only argument check used by every entry point (no HIP call). */
+flr_status flr_validate_params(const flr_params* p);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLR_H */

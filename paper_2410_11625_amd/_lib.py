@@ -1,0 +1,105 @@
+"""ctypes view of ``libflr.so`` (the C ABI in ``include/flr.h``).
+
+Only argument marshalling happens here; every step of the path runs in the
+library's HIP kernels. The library must have been built in-tree (see
+``paper_2410_11625_amd/build.py``); if it is missing, loading fails loudly
+and nothing falls back to any other implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libflr.so")
+
+FLR_OK = 0
+FLR_REG_RIDGE = 0
+FLR_REG_PAPER = 1
+FLR_FLAG_RAW_MOMENTS = 1
+FLR_MAX_GUIDES = 12
+FLR_MAX_CHANNELS = 4
+FLR_MAX_RADIUS = 32
+
+STATUS_NAMES = {
+    0: "FLR_OK", 1: "FLR_ERR_NULL", 2: "FLR_ERR_SHAPE", 3: "FLR_ERR_RADIUS", 4: "FLR_ERR_EPS",
+    5: "FLR_ERR_CHANNELS", 6: "FLR_ERR_ALIAS", 7: "FLR_ERR_ALIGN", 8: "FLR_ERR_WORKSPACE",
+    9: "FLR_ERR_MODE", 10: "FLR_ERR_HIP",
+}
+
+# Every symbol include/flr.h declares.
+EXPORTED = ("flr_num_moment_planes", "flr_num_coeff_planes", "flr_denoise_workspace_bytes",
+            "flr_moments", "flr_solve", "flr_apply", "flr_denoise", "flr_status_str",
+            "flr_validate_params")
+
+
+class FlrParams(ctypes.Structure):
+    _fields_ = [
+        ("height", ctypes.c_int32),
+        ("width", ctypes.c_int32),
+        ("num_guides", ctypes.c_int32),
+        ("num_channels", ctypes.c_int32),
+        ("radius", ctypes.c_int32),
+        ("eps", ctypes.c_float),
+        ("eps_mul", ctypes.c_float),
+        ("reg_mode", ctypes.c_int32),
+        ("average_coeffs", ctypes.c_int32),
+        ("fused", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+        ("tile_rows", ctypes.c_int32),
+    ]
+
+
+class FLRError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = int(status)
+        name = STATUS_NAMES.get(self.status, str(status))
+        msg = f"{name}: {status_str(self.status)}"
+        super().__init__(f"{what}: {msg}" if what else msg)
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load the library once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libflr.so not found at {LIB_PATH}; build it with "
+                          "`python -m paper_2410_11625_amd.build` (there is no fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER(FlrParams)
+    vp = ctypes.c_void_p
+    L.flr_num_moment_planes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    L.flr_num_moment_planes.restype = ctypes.c_size_t
+    L.flr_num_coeff_planes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    L.flr_num_coeff_planes.restype = ctypes.c_size_t
+    L.flr_denoise_workspace_bytes.argtypes = [P]
+    L.flr_denoise_workspace_bytes.restype = ctypes.c_size_t
+    L.flr_validate_params.argtypes = [P]
+    L.flr_validate_params.restype = ctypes.c_int
+    L.flr_moments.argtypes = [P, vp, vp, vp, vp]
+    L.flr_moments.restype = ctypes.c_int
+    L.flr_solve.argtypes = [P, vp, vp, vp]
+    L.flr_solve.restype = ctypes.c_int
+    L.flr_apply.argtypes = [P, vp, vp, vp, vp]
+    L.flr_apply.restype = ctypes.c_int
+    L.flr_denoise.argtypes = [P, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    L.flr_denoise.restype = ctypes.c_int
+    L.flr_status_str.argtypes = [ctypes.c_int]
+    L.flr_status_str.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def status_str(status: int) -> str:
+    try:
+        return lib().flr_status_str(int(status)).decode()
+    except ImportError:
+        return STATUS_NAMES.get(int(status), "unknown")
+
+
+def check(status: int, what: str = "") -> None:
+    if status != FLR_OK:
+        raise FLRError(status, what)

@@ -1,0 +1,144 @@
+"""Python mirror of the C ABI on torch tensors.
+
+Tensors are float32, contiguous, on a HIP device; they only provide memory
+and the current stream. Every computation runs in ``libflr.so``.
+Shapes: ``guides`` [Q,H,W] (without the implied constant guide), ``noisy``
+[C,H,W], moments [M,H,W], coefficients [(Q+1)*C,H,W], output [C,H,W].
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from ._lib import (FLR_FLAG_RAW_MOMENTS, FLR_REG_PAPER, FLR_REG_RIDGE, FLRError, FlrParams,
+                   check, lib)
+
+_MODES = {"ridge": FLR_REG_RIDGE, "paper": FLR_REG_PAPER}
+
+
+def _need(t: torch.Tensor, name: str, ndim: int = 3) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32, got {t.dtype}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a HIP device (no CPU path exists)")
+    if t.dim() != ndim:
+        raise ValueError(f"{name} must have {ndim} dims, got shape {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _stream(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def make_params(H: int, W: int, Q: int, C: int, radius: int, eps: float = 1e-3,
+                mode: str = "ridge", eps_mul: float = 0.0, average: bool = True,
+                fused: bool = True, raw: bool = False, tile_rows: int = 0) -> FlrParams:
+    if mode not in _MODES:
+        raise ValueError(f"mode must be one of {sorted(_MODES)}")
+    return FlrParams(height=H, width=W, num_guides=Q, num_channels=C, radius=radius,
+                     eps=eps, eps_mul=eps_mul, reg_mode=_MODES[mode],
+                     average_coeffs=int(bool(average)), fused=int(bool(fused)),
+                     flags=FLR_FLAG_RAW_MOMENTS if raw else 0, tile_rows=tile_rows)
+
+
+def num_moment_planes(Q: int, C: int) -> int:
+    return int(lib().flr_num_moment_planes(Q, C))
+
+
+def num_coeff_planes(Q: int, C: int) -> int:
+    return int(lib().flr_num_coeff_planes(Q, C))
+
+
+def workspace_bytes(p: FlrParams) -> int:
+    return int(lib().flr_denoise_workspace_bytes(ctypes.byref(p)))
+
+
+def moments(guides: torch.Tensor, noisy: torch.Tensor, radius: int, *, raw: bool = False,
+            tile_rows: int = 0, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Window moments (central, or raw sums with ``raw``) as [M,H,W]."""
+    _need(guides, "guides")
+    _need(noisy, "noisy")
+    Q, H, W = guides.shape
+    C = noisy.shape[0]
+    p = make_params(H, W, Q, C, radius, raw=raw, tile_rows=tile_rows)
+    M = num_moment_planes(Q, C)
+    if out is None:
+        out = torch.empty((M, H, W), dtype=torch.float32, device=guides.device)
+    _need(out, "out")
+    check(lib().flr_moments(ctypes.byref(p), guides.data_ptr(), noisy.data_ptr(),
+                            out.data_ptr(), _stream(guides)), "flr_moments")
+    return out
+
+
+def solve(moment_planes: torch.Tensor, num_guides: int, num_channels: int, eps: float = 1e-3,
+          mode: str = "ridge", eps_mul: float = 0.0,
+          out: torch.Tensor | None = None) -> torch.Tensor:
+    """Per-pixel regularised solve: moment planes -> coefficient planes [(Q+1)*C,H,W]."""
+    _need(moment_planes, "moments")
+    _, H, W = moment_planes.shape
+    Q, C = num_guides, num_channels
+    if moment_planes.shape[0] != num_moment_planes(Q, C):
+        raise ValueError("moment plane count does not match num_guides/num_channels")
+    p = make_params(H, W, Q, C, 0, eps=eps, mode=mode, eps_mul=eps_mul)
+    if out is None:
+        out = torch.empty((num_coeff_planes(Q, C), H, W), dtype=torch.float32,
+                          device=moment_planes.device)
+    _need(out, "out")
+    check(lib().flr_solve(ctypes.byref(p), moment_planes.data_ptr(), out.data_ptr(),
+                          _stream(moment_planes)), "flr_solve")
+    return out
+
+
+def apply(guides: torch.Tensor, coeffs: torch.Tensor, radius: int, average: bool = True,
+          tile_rows: int = 0, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Optional window-average of the coefficients, then reconstruction -> [C,H,W]."""
+    _need(guides, "guides")
+    _need(coeffs, "coeffs")
+    Q, H, W = guides.shape
+    if coeffs.shape[0] % (Q + 1) != 0:
+        raise ValueError("coefficient plane count must be a multiple of Q+1")
+    C = coeffs.shape[0] // (Q + 1)
+    p = make_params(H, W, Q, C, radius, average=average, tile_rows=tile_rows)
+    if out is None:
+        out = torch.empty((C, H, W), dtype=torch.float32, device=guides.device)
+    _need(out, "out")
+    check(lib().flr_apply(ctypes.byref(p), guides.data_ptr(), coeffs.data_ptr(),
+                          out.data_ptr(), _stream(guides)), "flr_apply")
+    return out
+
+
+def denoise(noisy: torch.Tensor, guides: torch.Tensor, radius: int = 8, eps: float = 1e-3,
+            mode: str = "ridge", eps_mul: float = 0.0, average: bool = True,
+            fused: bool = True, tile_rows: int = 0, out: torch.Tensor | None = None,
+            workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """The whole FLR path -> [C,H,W]. ``workspace`` is a uint8 device tensor
+    of at least ``workspace_bytes`` bytes; it is allocated when omitted."""
+    _need(guides, "guides")
+    _need(noisy, "noisy")
+    Q, H, W = guides.shape
+    C = noisy.shape[0]
+    if noisy.shape[1:] != guides.shape[1:]:
+        raise ValueError("noisy and guides must have the same height and width")
+    p = make_params(H, W, Q, C, radius, eps=eps, mode=mode, eps_mul=eps_mul, average=average,
+                    fused=fused, tile_rows=tile_rows)
+    need = workspace_bytes(p)
+    if need == 0 and lib().flr_validate_params(ctypes.byref(p)) != 0:
+        check(lib().flr_validate_params(ctypes.byref(p)), "flr_denoise")
+    if workspace is None and need > 0:
+        workspace = torch.empty(need, dtype=torch.uint8, device=guides.device)
+    ws_ptr = workspace.data_ptr() if workspace is not None else None
+    ws_len = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    if out is None:
+        out = torch.empty((C, H, W), dtype=torch.float32, device=guides.device)
+    _need(out, "out")
+    check(lib().flr_denoise(ctypes.byref(p), guides.data_ptr(), noisy.data_ptr(), out.data_ptr(),
+                            ws_ptr, ws_len, _stream(guides)), "flr_denoise")
+    return out
+
+
+__all__ = ["FLRError", "make_params", "num_moment_planes", "num_coeff_planes", "workspace_bytes",
+           "moments", "solve", "apply", "denoise"]

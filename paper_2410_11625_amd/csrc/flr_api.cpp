@@ -1,0 +1,240 @@
+// Host side of the C ABI declared in include/flr.h: argument validation
+// (pure CPU, before any HIP call), launch planning and dispatch to the
+// per-guide-count kernel instantiations.
+#include <math.h>
+#include <initializer_list>
+#include <stdint.h>
+
+#include "flr.h"
+#include "flr_launch.hpp"
+
+namespace {
+
+using flr::LaunchArgs;
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(a), b0 = reinterpret_cast<uintptr_t>(b);
+  return a0 < b0 + nb && b0 < a0 + na;
+}
+
+size_t plane_bytes(const flr_params* p) {
+  return (size_t)p->height * (size_t)p->width * sizeof(float);
+}
+
+flr_status check_ptrs(std::initializer_list<const void*> ptrs) {
+  for (const void* q : ptrs)
+    if (!q) return FLR_ERR_NULL;
+  for (const void* q : ptrs)
+    if (!aligned16(q)) return FLR_ERR_ALIGN;
+  return FLR_OK;
+}
+
+LaunchArgs base_args(const flr_params* p) {
+  LaunchArgs a = {};
+  a.H = p->height;
+  a.W = p->width;
+  a.r = p->radius;
+  a.eps = p->eps;
+  a.eps_mul = p->eps_mul;
+  a.reg_mode = p->reg_mode;
+  a.raw = (p->flags & FLR_FLAG_RAW_MOMENTS) ? 1 : 0;
+  return a;
+}
+
+void plan(const flr_params* p, int kind, LaunchArgs* a) {
+  flr::plan_walk(kind, p->height, p->width, p->radius, p->tile_rows, &a->tiles_x, &a->n_seg,
+                 &a->seg_rows);
+  const int Q = p->num_guides, C = p->num_channels, r = p->radius;
+  const int fc = (Q + 1) * C;
+  const int ncoef = flr::kThreads - 2 * r;
+  (void)fc;
+  a->hchunk_m = flr::plan_chunk(flr::moment_group_rows(Q, C), ncoef, r);
+  a->hchunk_a = flr::plan_chunk(flr::coeff_group_rows(Q, C), flr::strip_out_cols(kind, r), r);
+}
+
+flr_status dispatch(int Q, int C, int kind, const LaunchArgs& a, void* stream) {
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e;
+  switch (Q) {
+    case 1: e = flr::launch_q1(C, kind, a, s); break;
+    case 2: e = flr::launch_q2(C, kind, a, s); break;
+    case 3: e = flr::launch_q3(C, kind, a, s); break;
+    case 4: e = flr::launch_q4(C, kind, a, s); break;
+    case 5: e = flr::launch_q5(C, kind, a, s); break;
+    case 6: e = flr::launch_q6(C, kind, a, s); break;
+    case 7: e = flr::launch_q7(C, kind, a, s); break;
+    case 8: e = flr::launch_q8(C, kind, a, s); break;
+    case 9: e = flr::launch_q9(C, kind, a, s); break;
+    case 10: e = flr::launch_q10(C, kind, a, s); break;
+    case 11: e = flr::launch_q11(C, kind, a, s); break;
+    case 12: e = flr::launch_q12(C, kind, a, s); break;
+    default: return FLR_ERR_CHANNELS;
+  }
+  return e == hipSuccess ? FLR_OK : FLR_ERR_HIP;
+}
+
+size_t ring_bytes(const flr_params* p) {
+  int tiles_x, n_seg, seg_rows;
+  flr::plan_walk(flr::K_FUSED1, p->height, p->width, p->radius, p->tile_rows, &tiles_x, &n_seg,
+                 &seg_rows);
+  return (size_t)tiles_x * n_seg *
+         flr::ring_bytes_per_block(p->num_guides, p->num_channels, p->radius);
+}
+
+// Unfused workspace: the moment image, then the coefficient image at the
+// next 256-byte boundary.
+size_t unfused_coeff_offset(const flr_params* p) {
+  const size_t mb = flr_num_moment_planes(p->num_guides, p->num_channels) * plane_bytes(p);
+  return (mb + 255) / 256 * 256;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t flr_num_moment_planes(int32_t Q, int32_t C) {
+  if (Q < 1 || Q > FLR_MAX_GUIDES || C < 1 || C > FLR_MAX_CHANNELS) return 0;
+  return (size_t)(1 + flr::num_sums(Q, C));
+}
+
+size_t flr_num_coeff_planes(int32_t Q, int32_t C) {
+  if (Q < 1 || Q > FLR_MAX_GUIDES || C < 1 || C > FLR_MAX_CHANNELS) return 0;
+  return (size_t)(Q + 1) * C;
+}
+
+flr_status flr_validate_params(const flr_params* p) {
+  if (!p) return FLR_ERR_NULL;
+  if (p->height < 1 || p->width < 1 || p->height > FLR_MAX_DIM || p->width > FLR_MAX_DIM)
+    return FLR_ERR_SHAPE;
+  if ((int64_t)p->height * p->width > ((int64_t)1 << 28)) return FLR_ERR_SHAPE;
+  if (p->num_guides < 1 || p->num_guides > FLR_MAX_GUIDES || p->num_channels < 1 ||
+      p->num_channels > FLR_MAX_CHANNELS)
+    return FLR_ERR_CHANNELS;
+  if (p->radius < 0 || p->radius > FLR_MAX_RADIUS) return FLR_ERR_RADIUS;
+  if (!isfinite(p->eps) || p->eps < 0.f || !isfinite(p->eps_mul) || p->eps_mul < 0.f)
+    return FLR_ERR_EPS;
+  if (p->reg_mode != FLR_REG_RIDGE && p->reg_mode != FLR_REG_PAPER) return FLR_ERR_MODE;
+  if ((p->average_coeffs != 0 && p->average_coeffs != 1) || (p->fused != 0 && p->fused != 1))
+    return FLR_ERR_MODE;
+  if (p->flags & ~(uint32_t)FLR_FLAG_RAW_MOMENTS) return FLR_ERR_MODE;
+  if (p->tile_rows < 0) return FLR_ERR_SHAPE;
+  return FLR_OK;
+}
+
+size_t flr_denoise_workspace_bytes(const flr_params* p) {
+  if (flr_validate_params(p) != FLR_OK) return 0;
+  const size_t pb = plane_bytes(p);
+  if (!p->fused)
+    return unfused_coeff_offset(p) + flr_num_coeff_planes(p->num_guides, p->num_channels) * pb;
+  return p->average_coeffs ? ring_bytes(p) : 0;
+}
+
+flr_status flr_moments(const flr_params* p, const float* guides, const float* noisy,
+                       float* moments, void* stream) {
+  flr_status st = flr_validate_params(p);
+  if (st != FLR_OK) return st;
+  if ((st = check_ptrs({guides, noisy, moments})) != FLR_OK) return st;
+  const size_t pb = plane_bytes(p);
+  const size_t mb = flr_num_moment_planes(p->num_guides, p->num_channels) * pb;
+  if (overlaps(moments, mb, guides, p->num_guides * pb) ||
+      overlaps(moments, mb, noisy, p->num_channels * pb))
+    return FLR_ERR_ALIAS;
+  LaunchArgs a = base_args(p);
+  a.guides = guides;
+  a.noisy = noisy;
+  a.out = moments;
+  plan(p, flr::K_MOMENTS, &a);
+  return dispatch(p->num_guides, p->num_channels, flr::K_MOMENTS, a, stream);
+}
+
+flr_status flr_solve(const flr_params* p, const float* moments, float* coeffs, void* stream) {
+  flr_status st = flr_validate_params(p);
+  if (st != FLR_OK) return st;
+  if ((st = check_ptrs({moments, coeffs})) != FLR_OK) return st;
+  const size_t pb = plane_bytes(p);
+  if (overlaps(coeffs, flr_num_coeff_planes(p->num_guides, p->num_channels) * pb, moments,
+               flr_num_moment_planes(p->num_guides, p->num_channels) * pb))
+    return FLR_ERR_ALIAS;
+  LaunchArgs a = base_args(p);
+  a.planes = moments;
+  a.out = coeffs;
+  return dispatch(p->num_guides, p->num_channels, flr::K_SOLVE, a, stream);
+}
+
+flr_status flr_apply(const flr_params* p, const float* guides, const float* coeffs, float* out,
+                     void* stream) {
+  flr_status st = flr_validate_params(p);
+  if (st != FLR_OK) return st;
+  if ((st = check_ptrs({guides, coeffs, out})) != FLR_OK) return st;
+  const size_t pb = plane_bytes(p);
+  const size_t ob = p->num_channels * pb;
+  if (overlaps(out, ob, guides, p->num_guides * pb) ||
+      overlaps(out, ob, coeffs, flr_num_coeff_planes(p->num_guides, p->num_channels) * pb))
+    return FLR_ERR_ALIAS;
+  LaunchArgs a = base_args(p);
+  a.guides = guides;
+  a.planes = coeffs;
+  a.out = out;
+  const int kind = p->average_coeffs ? flr::K_APPLY_AVG : flr::K_APPLY_POINT;
+  if (kind == flr::K_APPLY_AVG) plan(p, kind, &a);
+  return dispatch(p->num_guides, p->num_channels, kind, a, stream);
+}
+
+flr_status flr_denoise(const flr_params* p, const float* guides, const float* noisy, float* out,
+                       void* workspace, size_t workspace_bytes, void* stream) {
+  flr_status st = flr_validate_params(p);
+  if (st != FLR_OK) return st;
+  if ((st = check_ptrs({guides, noisy, out})) != FLR_OK) return st;
+  if (p->flags & FLR_FLAG_RAW_MOMENTS) return FLR_ERR_MODE;
+  const size_t pb = plane_bytes(p);
+  const size_t ob = p->num_channels * pb;
+  if (overlaps(out, ob, guides, p->num_guides * pb) ||
+      overlaps(out, ob, noisy, p->num_channels * pb))
+    return FLR_ERR_ALIAS;
+  const size_t need = flr_denoise_workspace_bytes(p);
+  if (need > 0) {
+    if (!workspace || workspace_bytes < need) return FLR_ERR_WORKSPACE;
+    if (!aligned16(workspace)) return FLR_ERR_ALIGN;
+    if (overlaps(workspace, need, guides, p->num_guides * pb) ||
+        overlaps(workspace, need, noisy, p->num_channels * pb) ||
+        overlaps(workspace, need, out, ob))
+      return FLR_ERR_ALIAS;
+  }
+  const int Q = p->num_guides, C = p->num_channels;
+  if (p->fused) {
+    LaunchArgs a = base_args(p);
+    a.guides = guides;
+    a.noisy = noisy;
+    a.out = out;
+    a.ring = static_cast<float*>(workspace);
+    const int kind = p->average_coeffs ? flr::K_FUSED1 : flr::K_FUSED0;
+    plan(p, kind, &a);
+    return dispatch(Q, C, kind, a, stream);
+  }
+  float* moments = static_cast<float*>(workspace);
+  float* coeffs = reinterpret_cast<float*>(static_cast<char*>(workspace) + unfused_coeff_offset(p));
+  if ((st = flr_moments(p, guides, noisy, moments, stream)) != FLR_OK) return st;
+  if ((st = flr_solve(p, moments, coeffs, stream)) != FLR_OK) return st;
+  return flr_apply(p, guides, coeffs, out, stream);
+}
+
+const char* flr_status_str(flr_status s) {
+  switch (s) {
+    case FLR_OK: return "ok";
+    case FLR_ERR_NULL: return "null pointer argument";
+    case FLR_ERR_SHAPE: return "height/width out of range";
+    case FLR_ERR_RADIUS: return "radius out of range";
+    case FLR_ERR_EPS: return "eps/eps_mul negative or not finite";
+    case FLR_ERR_CHANNELS: return "number of guides or channels out of range";
+    case FLR_ERR_ALIAS: return "output overlaps an input";
+    case FLR_ERR_ALIGN: return "pointer not 16-byte aligned";
+    case FLR_ERR_WORKSPACE: return "workspace missing or too small";
+    case FLR_ERR_MODE: return "invalid reg_mode, flags or boolean field";
+    case FLR_ERR_HIP: return "HIP launch failed";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

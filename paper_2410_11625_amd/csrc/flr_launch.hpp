@@ -1,0 +1,174 @@
+// Launch geometry and the interface between the host dispatcher and the
+// per-guide-count kernel instantiations. Host and device code share it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace flr {
+
+// One workgroup = one column strip of kThreads input columns walking down a
+// segment of rows. Four 64-wide wavefronts.
+constexpr int kThreads = 256;
+// MI355X compute units; the automatic segment choice aims for whole waves of
+// workgroups over this many CUs (the walker kernels run one workgroup per CU).
+constexpr int kCUs = 256;
+// Numeric types. Products of the FP32 inputs are summed in sum_t; central
+// moments, the solve, the coefficient ring, the coefficient average and the
+// reconstruction run in solve_t. (With packed FP32 unused, an FP64 FMA
+// issues at the same rate as an FP32 one on CDNA4; FP64 costs registers and
+// LDS bytes, not ALU slots.)
+#ifndef FLR_SUM_T
+#define FLR_SUM_T double
+#endif
+#ifndef FLR_SOLVE_T
+#define FLR_SOLVE_T double
+#endif
+// Element type of the fused kernel's coefficient ring (coefficients relative
+// to the workgroup anchor).
+#ifndef FLR_RING_T
+#define FLR_RING_T float
+#endif
+typedef FLR_SUM_T sum_t;
+typedef FLR_SOLVE_T solve_t;
+typedef FLR_RING_T ring_t;
+// LDS row stride in elements: kThreads + 1 keeps lanes that read
+// consecutive channel rows of one column on distinct banks.
+constexpr int kLdsStride = kThreads + 1;
+// LDS per workgroup (gfx950: 160 KiB).
+constexpr int kLdsBytes = 163840;
+// Channel rows of element size `elem` that fit twice (source and
+// destination of the horizontal pass) in LDS.
+__host__ __device__ constexpr int max_lds_rows(int elem) {
+  return kLdsBytes / (2 * kLdsStride * elem);
+}
+__host__ __device__ constexpr int group_count(int rows, int elem) {
+  return (rows + max_lds_rows(elem) - 1) / max_lds_rows(elem);
+}
+__host__ __device__ constexpr int group_size(int rows, int elem) {
+  return (rows + group_count(rows, elem) - 1) / group_count(rows, elem);
+}
+
+enum Kind : int {
+  K_MOMENTS = 0,      // window moments -> moment planes
+  K_SOLVE = 1,        // moment planes -> coefficient planes
+  K_APPLY_POINT = 2,  // coefficient planes + guides -> output (no averaging)
+  K_APPLY_AVG = 3,    // coefficient planes -> window average -> output
+  K_FUSED0 = 4,       // moments -> solve -> apply, no averaging, one kernel
+  K_FUSED1 = 5,       // moments -> solve -> average -> apply, one kernel
+};
+
+struct LaunchArgs {
+  const float* guides;   // [Q][H][W]
+  const float* noisy;    // [C][H][W]
+  const float* planes;   // K_SOLVE: moments; K_APPLY_*: coefficients
+  float* out;            // moments / coefficients / output image
+  void* ring;            // K_FUSED1 workspace (ring_t elements)
+  int H, W, r;
+  int seg_rows, tiles_x, n_seg;
+  int hchunk_m, hchunk_a;  // horizontal-pass chunk lengths (moments, averaging)
+  float eps, eps_mul;
+  int reg_mode;
+  int raw;
+};
+
+__host__ __device__ constexpr int num_sums(int Q, int C) {
+  return Q + C + Q * (Q + 1) / 2 + Q * C;
+}
+
+// Output columns per strip for a walker kernel.
+inline int strip_out_cols(int kind, int r) {
+  if (kind == K_FUSED1) return kThreads - 4 * r;
+  return kThreads - 2 * r;  // K_MOMENTS, K_FUSED0, K_APPLY_AVG
+}
+
+inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// Rows of coefficient halo a walker recomputes above and below its segment.
+inline int row_halo(int kind, int r) { return kind == K_FUSED1 ? r : 0; }
+
+// Pick tiles and segments. With tile_rows > 0 the caller fixes the segment
+// length; otherwise minimise (workgroup waves) x (rows walked per segment).
+inline void plan_walk(int kind, int H, int W, int r, int tile_rows, int* tiles_x, int* n_seg,
+                      int* seg_rows) {
+  const int tout = strip_out_cols(kind, r);
+  *tiles_x = ceil_div(W, tout);
+  if (tile_rows > 0) {
+    *seg_rows = tile_rows < H ? tile_rows : H;
+    *n_seg = ceil_div(H, *seg_rows);
+    return;
+  }
+  const int hc = row_halo(kind, r);
+  double best = 1e300;
+  int best_n = 1;
+  const int nmax = H < 4096 ? H : 4096;
+  for (int n = 1; n <= nmax; ++n) {
+    const int R = ceil_div(H, n);
+    if (n > 1 && ceil_div(H, n - 1) == R) continue;
+    const int wgs = *tiles_x * n;
+    const double waves = (double)ceil_div(wgs, kCUs);
+    // rows solved per segment plus a share for the moment warm-up rows
+    const double cost = waves * ((double)R + 2.0 * hc + 0.5 * r) + 1e-3 * n;
+    if (cost < best) {
+      best = cost;
+      best_n = n;
+    }
+  }
+  *seg_rows = ceil_div(H, best_n);
+  *n_seg = ceil_div(H, *seg_rows);
+}
+
+// Chunk length for the LDS horizontal pass over `rows` channel rows and
+// `nout` outputs: minimise (task passes) x (window taps + 2 per output).
+inline int plan_chunk(int rows, int nout, int r) {
+  int best = nout;
+  double bestc = 1e300;
+  for (int nch = 1; nch <= nout; ++nch) {
+    const int chunk = ceil_div(nout, nch);
+    if (nch > 1 && ceil_div(nout, nch - 1) == chunk) continue;
+    const int passes = ceil_div(rows * ceil_div(nout, chunk), kThreads);
+    const double cost = passes * (2.0 * r + 1 + 2.0 * (chunk - 1));
+    if (cost < bestc) {
+      bestc = cost;
+      best = chunk;
+    }
+  }
+  return best;
+}
+
+// Moment channels per LDS group, and coefficient planes per LDS group.
+inline int moment_group_rows(int Q, int C) { return group_size(num_sums(Q, C), sizeof(sum_t)); }
+inline int coeff_group_rows(int Q, int C) { return group_size((Q + 1) * C, sizeof(solve_t)); }
+
+inline size_t walk_lds_bytes(int kind, int Q, int C) {
+  size_t b = (size_t)coeff_group_rows(Q, C) * sizeof(solve_t);
+  if (kind != K_APPLY_AVG) {
+    const size_t m = (size_t)moment_group_rows(Q, C) * sizeof(sum_t);
+    if (m > b) b = m;
+  }
+  return 2 * b * kLdsStride;
+}
+
+inline size_t ring_bytes_per_block(int Q, int C, int r) {
+  return (size_t)(2 * r + 1) * (Q + 1) * C * kThreads * sizeof(ring_t);
+}
+
+// Per-guide-count dispatch entry points (one translation unit each).
+#define FLR_DECLARE_Q(q) \
+  hipError_t launch_q##q(int C, int kind, const LaunchArgs& a, hipStream_t s);
+FLR_DECLARE_Q(1)
+FLR_DECLARE_Q(2)
+FLR_DECLARE_Q(3)
+FLR_DECLARE_Q(4)
+FLR_DECLARE_Q(5)
+FLR_DECLARE_Q(6)
+FLR_DECLARE_Q(7)
+FLR_DECLARE_Q(8)
+FLR_DECLARE_Q(9)
+FLR_DECLARE_Q(10)
+FLR_DECLARE_Q(11)
+FLR_DECLARE_Q(12)
+#undef FLR_DECLARE_Q
+
+}  // namespace flr

@@ -1,0 +1,212 @@
+"""Build and drive the host-executed build of the FLR kernel sources.
+
+``build()`` compiles ``emu.cpp`` (the kernel templates) and the library's
+own ``flr_api.cpp`` with g++ into ``_build/libflr_emu.so``; ``Emu`` calls the
+real C ABI entry points on guard-paged host buffers. Run as a script it
+executes one named case and prints a JSON line, so that a crash in the
+emulated kernels cannot take down the test runner. Test infrastructure only.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+CSRC = os.path.join(ROOT, "paper_2410_11625_amd", "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+BUILD = os.path.join(HERE, "_build")
+# Optional numeric-policy override, e.g. "FLR_SUM_T=double,FLR_SOLVE_T=double"
+# (used to compare precision variants of the same sources).
+VARIANT = os.environ.get("FLR_EMU_VARIANT", "")
+SO = os.path.join(BUILD, "libflr_emu%s.so" % ("_" + VARIANT.replace("=", "-").replace(",", "_")
+                                              if VARIANT else ""))
+
+sys.path.insert(0, ROOT)
+from paper_2410_11625_amd._lib import FlrParams  # noqa: E402  (ctypes struct layout only)
+
+
+def build(force: bool = False) -> str:
+    srcs = [os.path.join(HERE, "emu.cpp"), os.path.join(CSRC, "flr_api.cpp")]
+    deps = srcs + [os.path.join(HERE, "hip", "hip_runtime.h"),
+                   os.path.join(CSRC, "flr_device.hpp"), os.path.join(CSRC, "flr_launch.hpp"),
+                   os.path.join(INCLUDE, "flr.h")]
+    if not force and os.path.exists(SO) and \
+            os.path.getmtime(SO) >= max(os.path.getmtime(d) for d in deps):
+        return SO
+    os.makedirs(BUILD, exist_ok=True)
+    defs = [f"-D{d}" for d in VARIANT.split(",") if d]
+    cmd = ["g++", "-std=c++20", "-O1", "-g", "-pthread", "-shared", "-fPIC", *defs,
+           f"-I{HERE}", f"-I{INCLUDE}", f"-I{CSRC}", *srcs, "-o", SO + ".tmp"]
+    subprocess.run(cmd, check=True)
+    os.replace(SO + ".tmp", SO)
+    return SO
+
+
+class Emu:
+    def __init__(self):
+        L = ctypes.CDLL(build())
+        vp = ctypes.c_void_p
+        P = ctypes.POINTER(FlrParams)
+        L.emu_alloc.argtypes = [ctypes.c_size_t]
+        L.emu_alloc.restype = vp
+        L.emu_free.argtypes = [vp, ctypes.c_size_t]
+        L.emu_message.restype = ctypes.c_char_p
+        L.flr_moments.argtypes = [P, vp, vp, vp, vp]
+        L.flr_solve.argtypes = [P, vp, vp, vp]
+        L.flr_apply.argtypes = [P, vp, vp, vp, vp]
+        L.flr_denoise.argtypes = [P, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.flr_denoise_workspace_bytes.argtypes = [P]
+        L.flr_denoise_workspace_bytes.restype = ctypes.c_size_t
+        L.flr_num_moment_planes.restype = ctypes.c_size_t
+        L.flr_num_coeff_planes.restype = ctypes.c_size_t
+        self.L = L
+        self._bufs = []
+
+    def buf(self, arr=None, shape=None):
+        """Guard-paged float32 buffer (copy of ``arr`` or uninitialised NaNs)."""
+        if arr is not None:
+            arr = np.ascontiguousarray(arr, dtype=np.float32)
+            shape = arr.shape
+        nbytes = int(np.prod(shape)) * 4
+        ptr = self.L.emu_alloc(max(nbytes, 4))
+        view = np.ctypeslib.as_array((ctypes.c_float * max(nbytes // 4, 1)).from_address(ptr))
+        view = view[: nbytes // 4].reshape(shape)
+        if arr is not None:
+            view[...] = arr
+        else:
+            view[...] = np.nan
+        self._bufs.append((ptr, nbytes))
+        return ptr, view
+
+    def close(self):
+        for ptr, n in self._bufs:
+            self.L.emu_free(ptr, max(n, 4))
+        self._bufs = []
+
+    def check(self, st, what):
+        if st != 0:
+            raise RuntimeError(f"{what} returned {st}: {self.L.emu_message().decode()}")
+
+    def denoise(self, noisy, guides, p: FlrParams):
+        gp, _ = self.buf(guides)
+        yp, _ = self.buf(noisy)
+        op, out = self.buf(shape=noisy.shape)
+        need = self.L.flr_denoise_workspace_bytes(ctypes.byref(p))
+        wp = self.buf(shape=(max(need // 4, 1),))[0] if need else None
+        self.check(self.L.flr_denoise(ctypes.byref(p), gp, yp, op, wp, need, None), "flr_denoise")
+        return out.copy()
+
+    def moments(self, noisy, guides, p: FlrParams):
+        Q, H, W = guides.shape
+        C = noisy.shape[0]
+        M = self.L.flr_num_moment_planes(Q, C)
+        gp, _ = self.buf(guides)
+        yp, _ = self.buf(noisy)
+        mp, mom = self.buf(shape=(M, H, W))
+        self.check(self.L.flr_moments(ctypes.byref(p), gp, yp, mp, None), "flr_moments")
+        return mom.copy()
+
+    def solve(self, planes, p: FlrParams):
+        Q, C = p.num_guides, p.num_channels
+        mp, _ = self.buf(planes)
+        cp, co = self.buf(shape=((Q + 1) * C,) + planes.shape[1:])
+        self.check(self.L.flr_solve(ctypes.byref(p), mp, cp, None), "flr_solve")
+        return co.copy()
+
+    def apply(self, guides, coeffs, p: FlrParams):
+        gp, _ = self.buf(guides)
+        cp, _ = self.buf(coeffs)
+        op, out = self.buf(shape=(p.num_channels,) + guides.shape[1:])
+        self.check(self.L.flr_apply(ctypes.byref(p), gp, cp, op, None), "flr_apply")
+        return out.copy()
+
+
+def params(H, W, Q, C, r, eps=1e-3, mode=0, eps_mul=0.0, average=1, fused=1, raw=False,
+           tile_rows=0):
+    return FlrParams(height=H, width=W, num_guides=Q, num_channels=C, radius=r, eps=eps,
+                     eps_mul=eps_mul, reg_mode=mode, average_coeffs=average, fused=fused,
+                     flags=1 if raw else 0, tile_rows=tile_rows)
+
+
+def run_case(spec: dict) -> dict:
+    """Execute one case described by ``spec`` and return error figures."""
+    from oracle import flr_ref as ref
+    from synth import make_config, random_frame, small_integer_frame
+
+    kind = spec["kind"]
+    H, W, Q, C, r = spec["H"], spec["W"], spec["Q"], spec["C"], spec["r"]
+    emu = Emu()
+    try:
+        if kind == "raw_moments":
+            fr = small_integer_frame(H, W, Q, C, seed=spec.get("seed", 0))
+            p = params(H, W, Q, C, r, raw=True, tile_rows=spec.get("tile_rows", 0))
+            got = emu.moments(fr["noisy"], fr["guides"], p)
+            n, XtX, XtY = ref.window_moments(fr["noisy"], fr["guides"], r)
+            want = [n] + [XtX[..., 0, 1 + q] for q in range(Q)] + \
+                [XtY[..., 0, c] for c in range(C)] + \
+                [XtX[..., 1 + a, 1 + b] for a in range(Q) for b in range(a, Q)] + \
+                [XtY[..., 1 + q, c] for q in range(Q) for c in range(C)]
+            want = np.stack(want)
+            return {"exact": bool(np.array_equal(got.astype(np.float64), want)),
+                    "maxabs": float(np.max(np.abs(got - want)))}
+        if spec.get("frame") == "config":
+            fr = make_config(spec["config"], h=H, w=W)
+        else:
+            fr = random_frame(H, W, Q, C, seed=spec.get("seed", 0), smooth=spec.get("smooth", 1.5),
+                              offset=spec.get("offset", 0.0))
+        noisy, guides = fr["noisy"], fr["guides"]
+        mode = {"ridge": 0, "paper": 1}[spec.get("mode", "ridge")]
+        eps, em = spec.get("eps", 1e-3), spec.get("eps_mul", 0.0)
+        avg = spec.get("average", 1)
+        tr = spec.get("tile_rows", 0)
+        mname = spec.get("mode", "ridge")
+        want = ref.flr_reference(noisy, guides, r, eps, mname, eps_mul=em, average=bool(avg))
+        scale = max(float(np.sqrt(np.mean(want ** 2))), 1e-30)
+        res = {}
+        if kind in ("fused", "both"):
+            got = emu.denoise(noisy, guides, params(H, W, Q, C, r, eps, mode, em, avg, 1,
+                                                    tile_rows=tr))
+            den = np.maximum(np.abs(want), 1e-3 * scale)
+            res["fused_rel"] = float(np.max(np.abs(got - want) / den))
+        if kind in ("unfused", "both"):
+            got = emu.denoise(noisy, guides, params(H, W, Q, C, r, eps, mode, em, avg, 0,
+                                                    tile_rows=tr))
+            den = np.maximum(np.abs(want), 1e-3 * scale)
+            res["unfused_rel"] = float(np.max(np.abs(got - want) / den))
+        if kind == "stages":
+            p = params(H, W, Q, C, r, eps, mode, em, avg, 0, tile_rows=tr)
+            mom = emu.moments(noisy, guides, p)
+            mref = ref.central_moment_planes(noisy, guides, r)
+            res["moments_err"] = float(np.max(np.abs(mom - mref)) / np.max(np.abs(mref)))
+            coef = emu.solve(mref.astype(np.float32), p)
+            n, Mn, Bn = ref.moments_from_central_planes(mref.astype(np.float32), Q, C)
+            cref = ref.coefficient_planes(ref.solve_normalised(Mn, Bn, eps, mname, em))
+            res["solve_err"] = float(np.max(np.abs(coef - cref)) / np.max(np.abs(cref)))
+            out = emu.apply(guides, cref.astype(np.float32), p)
+            A = ref.coefficients_from_planes(cref.astype(np.float32), Q, C)
+            A = ref.average_coefficients(A, r) if avg else A
+            oref = ref.apply_model(A, guides)
+            res["apply_err"] = float(np.max(np.abs(out - oref)) / np.max(np.abs(oref)))
+        return res
+    finally:
+        emu.close()
+
+
+def run_in_subprocess(spec: dict, timeout: float = 600.0) -> dict:
+    res = subprocess.run([sys.executable, os.path.abspath(__file__), json.dumps(spec)],
+                         stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True,
+                         timeout=timeout, cwd=ROOT)
+    if res.returncode != 0:
+        raise RuntimeError(f"emulated case {spec} failed (rc={res.returncode}):\n"
+                           f"{res.stdout[-2000:]}\n{res.stderr[-4000:]}")
+    return json.loads(res.stdout.strip().splitlines()[-1])
+
+
+if __name__ == "__main__":
+    print(json.dumps(run_case(json.loads(sys.argv[1]))))

@@ -1,0 +1,119 @@
+"""The C ABI library: it loads, exports every declared entry point, and
+rejects bad arguments on the host before any HIP call (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2410_11625_amd import _lib
+from paper_2410_11625_amd._lib import FlrParams
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _params(**kw):
+    base = dict(height=64, width=80, num_guides=4, num_channels=3, radius=8, eps=1e-3,
+                eps_mul=0.0, reg_mode=0, average_coeffs=1, fused=1, flags=0, tile_rows=0)
+    base.update(kw)
+    return FlrParams(**base)
+
+
+@pytest.fixture(scope="module")
+def L():
+    return _lib.lib()
+
+
+def test_header_declares_what_the_library_exports(L):
+    hdr = open(os.path.join(ROOT, "include", "flr.h")).read()
+    declared = set(re.findall(r"^\s*(?:const char\*|size_t|flr_status)\s+(flr_\w+)\s*\(", hdr,
+                              re.M))
+    assert declared == set(_lib.EXPORTED)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_params_struct_layout_matches_header():
+    # 12 four-byte fields, no padding
+    assert ctypes.sizeof(FlrParams) == 48
+    hdr = open(os.path.join(ROOT, "include", "flr.h")).read()
+    body = hdr[hdr.index("typedef struct {"):hdr.index("} flr_params;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = re.findall(r"(\w+)(?:,\s*(\w+))?;", body)
+    flat = [n for pair in names for n in pair if n]
+    assert flat == [f[0] for f in FlrParams._fields_]
+
+
+def test_plane_counts(L):
+    assert L.flr_num_moment_planes(4, 1) == 1 + 4 + 1 + 10 + 4   # 20 (5x5 system)
+    assert L.flr_num_moment_planes(8, 3) == 72
+    assert L.flr_num_moment_planes(12, 3) == 130
+    assert L.flr_num_coeff_planes(8, 3) == 27
+    assert L.flr_num_moment_planes(0, 1) == 0
+    assert L.flr_num_moment_planes(13, 1) == 0
+    assert L.flr_num_coeff_planes(4, 5) == 0
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("height", 0, 2), ("width", -1, 2), ("width", 40000, 2),
+    ("num_guides", 0, 5), ("num_guides", 13, 5), ("num_channels", 0, 5), ("num_channels", 5, 5),
+    ("radius", -1, 3), ("radius", 33, 3),
+    ("eps", -1e-3, 4), ("eps", float("nan"), 4), ("eps", float("inf"), 4), ("eps_mul", -1.0, 4),
+    ("reg_mode", 2, 9), ("average_coeffs", 2, 9), ("fused", -1, 9), ("flags", 8, 9),
+    ("tile_rows", -2, 2),
+])
+def test_validation_codes(L, field, value, status):
+    p = _params(**{field: value})
+    assert L.flr_validate_params(ctypes.byref(p)) == status
+    # every entry point returns the same code, before touching the pointers
+    fake = ctypes.c_void_p(0x1000)
+    assert L.flr_denoise(ctypes.byref(p), fake, fake, ctypes.c_void_p(0x100000), fake,
+                         1 << 30, None) == status
+
+
+def test_valid_params(L):
+    assert L.flr_validate_params(ctypes.byref(_params())) == 0
+    assert L.flr_validate_params(None) == 1
+
+
+def test_null_alignment_alias_and_workspace_errors(L):
+    p = _params(fused=0)
+    plane = 64 * 80 * 4
+    g, y, o = 0x10000000, 0x20000000, 0x30000000
+    need = L.flr_denoise_workspace_bytes(ctypes.byref(p))
+    ws = 0x40000000
+    assert need > 0
+    assert L.flr_denoise(ctypes.byref(p), None, y, o, ws, need, None) == 1
+    assert L.flr_denoise(ctypes.byref(p), g + 4, y, o, ws, need, None) == 7
+    # output overlapping the guides
+    assert L.flr_denoise(ctypes.byref(p), g, y, g + plane, ws, need, None) == 6
+    # workspace missing / too small / overlapping the output
+    assert L.flr_denoise(ctypes.byref(p), g, y, o, None, need, None) == 8
+    assert L.flr_denoise(ctypes.byref(p), g, y, o, ws, need - 16, None) == 8
+    assert L.flr_denoise(ctypes.byref(p), g, y, o, o, need, None) == 6
+    # raw-moments flag belongs to flr_moments only
+    pr = _params(flags=1)
+    assert L.flr_denoise(ctypes.byref(pr), g, y, o, ws, need, None) == 9
+    # stage entry points
+    assert L.flr_moments(ctypes.byref(p), g, y, g, None) == 6
+    assert L.flr_solve(ctypes.byref(p), g, g + 64, None) == 6
+    assert L.flr_apply(ctypes.byref(p), g, y, None, None) == 1
+
+
+def test_workspace_sizes(L):
+    pf0 = _params(average_coeffs=0)
+    assert L.flr_denoise_workspace_bytes(ctypes.byref(pf0)) == 0
+    pu = _params(fused=0)
+    H, W, Q, C = 64, 80, 4, 3
+    M, FC = L.flr_num_moment_planes(Q, C), L.flr_num_coeff_planes(Q, C)
+    mb = M * H * W * 4
+    assert L.flr_denoise_workspace_bytes(ctypes.byref(pu)) == (mb + 255) // 256 * 256 + FC * H * W * 4
+    pf1 = _params()
+    assert L.flr_denoise_workspace_bytes(ctypes.byref(pf1)) > 0
+    assert L.flr_denoise_workspace_bytes(ctypes.byref(_params(radius=-1))) == 0
+
+
+def test_status_strings(L):
+    for s in range(11):
+        assert len(L.flr_status_str(s)) > 0
+    assert L.flr_status_str(99) == b"unknown status"

@@ -1,0 +1,197 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerance (from the workload definition): max relative error 1e-4 for the
+FP32-in/FP32-out regression path, with the relative error of a pixel taken
+as |gpu - ref| / max(|ref|, 1e-3 * rms(ref)) so that pixels whose reference
+value is near zero are judged on the image's scale. Integer work (raw window
+sums of small integers) must match bit for bit.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2410_11625_amd as flr  # noqa: E402
+from oracle import flr_ref as ref  # noqa: E402
+from synth import make_config, random_frame, small_integer_frame  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(_dev())
+
+
+def rel_err(got, want):
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    rms = max(float(np.sqrt(np.mean(want ** 2))), 1e-30)
+    return float(np.max(np.abs(got - want) / np.maximum(np.abs(want), 1e-3 * rms)))
+
+
+def gpu_denoise(fr, r, eps, **kw):
+    out = flr.denoise(_t(fr["noisy"]), _t(fr["guides"]), radius=r, eps=eps, **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+# --------------------------------------------------------------------------
+# Integer work: raw window sums are exact for small integers.
+
+@pytest.mark.parametrize("H,W,Q,C,r,tr", [(37, 300, 3, 2, 3, 10), (5, 7, 1, 1, 8, 0),
+                                         (64, 700, 8, 3, 8, 0), (3, 1000, 4, 1, 32, 0),
+                                         (300, 40, 2, 4, 5, 17)])
+def test_raw_moments_bit_exact(H, W, Q, C, r, tr):
+    fr = small_integer_frame(H, W, Q, C, seed=H + W)
+    got = flr.moments(_t(fr["guides"]), _t(fr["noisy"]), r, raw=True, tile_rows=tr)
+    got = got.cpu().numpy().astype(np.float64)
+    n, XtX, XtY = ref.window_moments(fr["noisy"], fr["guides"], r)
+    want = np.stack([n] + [XtX[..., 0, 1 + q] for q in range(Q)] +
+                    [XtY[..., 0, c] for c in range(C)] +
+                    [XtX[..., 1 + a, 1 + b] for a in range(Q) for b in range(a, Q)] +
+                    [XtY[..., 1 + q, c] for q in range(Q) for c in range(C)])
+    assert np.array_equal(got, want)
+
+
+# --------------------------------------------------------------------------
+# Whole path vs oracle at sizes the oracle finishes in seconds.
+
+@pytest.fixture(scope="module")
+def cfg0():
+    fr = make_config(0)
+    fr["ref"] = ref.flr_reference(fr["noisy"], fr["guides"], 8, 1e-3)
+    return fr
+
+
+@pytest.fixture(scope="module")
+def cfg1_crop():
+    # 120 x 520 crop-sized frame of the 1080p workload: three strips with a
+    # ragged last one, several row segments
+    fr = make_config(1, h=120, w=520)
+    fr["ref"] = ref.flr_reference(fr["noisy"], fr["guides"], 8, 1e-3)
+    return fr
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_config0_full_frame(cfg0, fused):
+    got = gpu_denoise(cfg0, 8, 1e-3, fused=fused)
+    assert rel_err(got, cfg0["ref"]) <= TOL
+
+
+@pytest.mark.parametrize("fused", [True, False])
+@pytest.mark.parametrize("tile_rows", [0, 7, 33])
+def test_config1_crop(cfg1_crop, fused, tile_rows):
+    got = gpu_denoise(cfg1_crop, 8, 1e-3, fused=fused, tile_rows=tile_rows)
+    assert rel_err(got, cfg1_crop["ref"]) <= TOL
+
+
+def test_config1_stages(cfg1_crop):
+    fr = cfg1_crop
+    g, y = _t(fr["guides"]), _t(fr["noisy"])
+    mom = flr.moments(g, y, 8).cpu().numpy()
+    mref = ref.central_moment_planes(fr["noisy"], fr["guides"], 8)
+    # moments are returned in float32: compare each plane on its own scale
+    for k in range(mref.shape[0]):
+        scale = np.max(np.abs(mref[k])) + 1e-30
+        assert np.max(np.abs(mom[k] - mref[k])) / scale < 1e-5, k
+    # solve: from the oracle's moments rounded to float32
+    m32 = mref.astype(np.float32)
+    co = flr.solve(_t(m32), 8, 3, eps=1e-3).cpu().numpy()
+    _, Mn, Bn = ref.moments_from_central_planes(m32, 8, 3)
+    cref = ref.coefficient_planes(ref.solve_normalised(Mn, Bn, 1e-3))
+    assert np.max(np.abs(co - cref)) / np.max(np.abs(cref)) < 1e-5
+    # apply: from the oracle's coefficients rounded to float32
+    c32 = cref.astype(np.float32)
+    out = flr.apply(g, _t(c32), 8, average=True).cpu().numpy()
+    A = ref.coefficients_from_planes(c32, 8, 3)
+    oref = ref.apply_model(ref.average_coefficients(A, 8), fr["guides"])
+    assert rel_err(out, oref) <= TOL
+
+
+@pytest.mark.parametrize("H,W,Q,C,r", [
+    (1, 1, 1, 1, 8), (1, 300, 3, 1, 2), (70, 1, 1, 2, 3), (17, 3, 2, 2, 8), (9, 11, 2, 1, 20),
+    (257, 263, 5, 1, 4), (40, 600, 12, 3, 8), (33, 250, 6, 4, 32), (50, 130, 7, 2, 0),
+])
+@pytest.mark.parametrize("average", [True, False])
+def test_shapes_guides_channels(H, W, Q, C, r, average):
+    fr = random_frame(H, W, Q, C, seed=H * 7 + W + Q, smooth=1.5)
+    want = ref.flr_reference(fr["noisy"], fr["guides"], r, 1e-3, average=average)
+    for fused in (True, False):
+        got = gpu_denoise(fr, r, 1e-3, average=average, fused=fused)
+        assert rel_err(got, want) <= TOL, (fused,)
+
+
+@pytest.mark.parametrize("eps,eps_mul", [(1e-3, 0.0), (1e-2, 0.2)])
+def test_paper_regulariser(eps, eps_mul):
+    fr = random_frame(45, 300, 4, 3, seed=5, smooth=2.0, offset=1.5)
+    want = ref.flr_reference(fr["noisy"], fr["guides"], 4, eps, "paper", eps_mul=eps_mul)
+    for fused in (True, False):
+        got = gpu_denoise(fr, 4, eps, mode="paper", eps_mul=eps_mul, fused=fused)
+        assert rel_err(got, want) <= TOL
+
+
+# --------------------------------------------------------------------------
+# Full 1080p workload in the benchmark's launch configuration: sampled
+# output blocks (corners, edges, interior) against the oracle evaluated on
+# each block with its 2r halo.
+
+@pytest.fixture(scope="module")
+def cfg1_full():
+    return make_config(1)
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_config1_full_frame_sampled_blocks(cfg1_full, fused):
+    fr = cfg1_full
+    got = gpu_denoise(fr, 8, 1e-3, fused=fused)
+    H, W = 1080, 1920
+    blocks = [(0, 24, 0, 40), (0, 24, W - 40, W), (H - 24, H, 0, 40), (H - 24, H, W - 40, W),
+              (530, 560, 950, 990), (0, 20, 900, 960), (700, 730, 0, 30), (300, 330, 1880, W),
+              (H - 16, H, 1200, 1260), (96, 130, 215, 240), (451, 480, 1343, 1380)]
+    for (y0, y1, x0, x1) in blocks:
+        want = ref.flr_reference_block(fr["noisy"], fr["guides"], 8, 1e-3, y0, y1, x0, x1)
+        assert rel_err(got[:, y0:y1, x0:x1], want) <= TOL, (y0, x0)
+    assert np.all(np.isfinite(got))
+
+
+# --------------------------------------------------------------------------
+# Properties of the implementation.
+
+def test_repeat_runs_are_bitwise_identical(cfg1_crop):
+    a = gpu_denoise(cfg1_crop, 8, 1e-3)
+    b = gpu_denoise(cfg1_crop, 8, 1e-3)
+    assert np.array_equal(a, b)
+
+
+def test_nan_input_propagates(cfg1_crop):
+    fr = dict(noisy=cfg1_crop["noisy"].copy(), guides=cfg1_crop["guides"])
+    fr["noisy"][1, 60, 300] = np.nan
+    got = gpu_denoise(fr, 8, 1e-3)
+    assert np.isnan(got[1, 60, 300])
+    assert np.isnan(got[1, 60 - 16, 300 + 16])
+    # pixels whose windows cannot reach the NaN stay finite
+    assert np.all(np.isfinite(got[:, :60 - 16, :]))
+
+
+def test_two_calls_in_a_row_with_smaller_second(cfg1_crop):
+    big = gpu_denoise(cfg1_crop, 8, 1e-3)
+    small = dict(noisy=cfg1_crop["noisy"][:, :50, :200].copy(),
+                 guides=cfg1_crop["guides"][:, :50, :200].copy())
+    s = gpu_denoise(small, 8, 1e-3)
+    want = ref.flr_reference(small["noisy"], small["guides"], 8, 1e-3)
+    assert rel_err(s, want) <= TOL
+    assert np.array_equal(gpu_denoise(cfg1_crop, 8, 1e-3), big)
+
+
+def test_api_rejects_cpu_tensors():
+    fr = random_frame(8, 8, 2, 1, seed=0)
+    with pytest.raises(ValueError):
+        flr.denoise(torch.from_numpy(fr["noisy"]), torch.from_numpy(fr["guides"]))
