@@ -47,11 +47,10 @@ void plan(const flr_params* p, int kind, LaunchArgs* a) {
   flr::plan_walk(kind, p->height, p->width, p->radius, p->tile_rows, &a->tiles_x, &a->n_seg,
                  &a->seg_rows);
   const int Q = p->num_guides, C = p->num_channels, r = p->radius;
-  const int fc = (Q + 1) * C;
   const int ncoef = flr::kThreads - 2 * r;
-  (void)fc;
-  a->hchunk_m = flr::plan_chunk(flr::moment_group_rows(Q, C), ncoef, r);
-  a->hchunk_a = flr::plan_chunk(flr::coeff_group_rows(Q, C), flr::strip_out_cols(kind, r), r);
+  const flr::WalkLayout L = flr::walk_layout(Q, C, kind);
+  a->hchunk_m = L.mg > 0 ? flr::plan_chunk(L.mg, ncoef, r) : 1;
+  a->hchunk_a = flr::plan_chunk(L.ag, flr::strip_out_cols(kind, r), r);
 }
 
 flr_status dispatch(int Q, int C, int kind, const LaunchArgs& a, void* stream) {

@@ -33,7 +33,6 @@ struct Dims {
   static constexpr int NQC = Q * C;           // guide x channel products
   static constexpr int NS = Q + C + NP + NQC; // summed channels (n is analytic)
   static constexpr int FC = F * C;            // coefficients per pixel
-  static constexpr int MG = group_size(NS, sizeof(sum_t));   // moment rows per LDS group
   static constexpr int AG = group_size(FC, sizeof(solve_t)); // coefficient rows per LDS group
 };
 
@@ -52,7 +51,22 @@ __device__ __forceinline__ int win_count(int i, int n, int r) {
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return fma(a, b, c); }
 __device__ __forceinline__ float rsqrt_t(float x) { return rsqrtf(x); }
-__device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
+// FP64 1/sqrt(x): the FP32 hardware estimate (about 2^-23 relative) refined
+// by one Newton step (error squared, about 2^-46, far below what the FP32
+// inputs carry); outside the FP32 range, plain 1/sqrt.
+__device__ __forceinline__ double rsqrt_t(double x) {
+  if (!(x > 1e-36 && x < 1e36)) return 1.0 / sqrt(x);
+  double y = (double)rsqrtf((float)x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+// 1/n for a window count n >= 1, refined the same way.
+__device__ __forceinline__ float recip_count(int n, float) { return 1.f / (float)n; }
+__device__ __forceinline__ double recip_count(int n, double) {
+  const double d = (double)n;
+  const double y = (double)(1.f / (float)n);
+  return fma(y, fma(-d, y, 1.0), y);
+}
 
 // max(x, 0) that lets NaN through.
 template <typename T>
@@ -141,19 +155,58 @@ __device__ __forceinline__ void hbox(const E* __restrict__ src, E* __restrict__ 
                                      int nout, int r, int chunk) {
   const int nch = (nout + chunk - 1) / chunk;
   const int ntask = rows * nch;
-  for (int t = threadIdx.x; t < ntask; t += kThreads) {
-    const int m = t % rows;
-    const int ch = t / rows;
-    const E* s = src + m * kLdsStride;
-    E* d = dst + m * kLdsStride;
-    const int j0 = ch * chunk;
-    const int j1 = min(j0 + chunk, nout);
-    E acc = E(0);
-    for (int k = 0; k <= 2 * r; ++k) acc += s[j0 + k];
-    d[j0] = acc;
-    for (int jj = j0 + 1; jj < j1; ++jj) {
-      acc += s[jj + 2 * r] - s[jj - 1];
-      d[jj] = acc;
+  const int w = 2 * r + 1;
+  // Each thread runs two tasks side by side, so that two independent
+  // dependency chains hide each other's LDS latency.
+  for (int t0 = threadIdx.x; t0 < ntask; t0 += 2 * kThreads) {
+    const int t1 = t0 + kThreads;
+    const int m0 = t0 % rows, j00 = (t0 / rows) * chunk;
+    const int n0 = min(chunk, nout - j00);
+    const int m1 = t1 < ntask ? t1 % rows : m0;
+    const int j01 = t1 < ntask ? (t1 / rows) * chunk : j00;
+    const int n1 = t1 < ntask ? min(chunk, nout - j01) : 0;
+    const E* s0 = src + m0 * kLdsStride + j00;
+    const E* s1 = src + m1 * kLdsStride + j01;
+    E* d0 = dst + m0 * kLdsStride + j00;
+    E* d1 = dst + m1 * kLdsStride + j01;
+    E a0 = E(0), b0 = E(0), a1 = E(0), b1 = E(0);
+    int k = 0;
+    for (; k + 2 <= w; k += 2) {
+      a0 += s0[k];
+      b0 += s0[k + 1];
+      a1 += s1[k];
+      b1 += s1[k + 1];
+    }
+    if (k < w) {
+      a0 += s0[k];
+      a1 += s1[k];
+    }
+    E acc0 = a0 + b0, acc1 = a1 + b1;
+    d0[0] = acc0;
+    if (n1 > 0) d1[0] = acc1;
+    const E* e0 = s0 + 2 * r;
+    const E* e1 = s1 + 2 * r;
+    const int n = min(n0, n1);
+    int j = 1;
+    for (; j + 2 <= n; j += 2) {
+      const E p0 = e0[j], p1 = e0[j + 1], q0 = s0[j - 1], q1 = s0[j];
+      const E u0 = e1[j], u1 = e1[j + 1], v0 = s1[j - 1], v1 = s1[j];
+      acc0 += p0 - q0;
+      acc1 += u0 - v0;
+      d0[j] = acc0;
+      d1[j] = acc1;
+      acc0 += p1 - q1;
+      acc1 += u1 - v1;
+      d0[j + 1] = acc0;
+      d1[j + 1] = acc1;
+    }
+    for (int jj = j; jj < n0; ++jj) {
+      acc0 += e0[jj] - s0[jj - 1];
+      d0[jj] = acc0;
+    }
+    for (int jj = (n1 > 0 ? j : n1); jj < n1; ++jj) {
+      acc1 += e1[jj] - s1[jj - 1];
+      d1[jj] = acc1;
     }
   }
 }
@@ -174,6 +227,31 @@ __device__ __forceinline__ void load_px(const LaunchArgs& a, int64_t pl, int64_t
 #pragma unroll
     for (int c = 0; c < C; ++c) y[c] = sum_t(0);
   }
+}
+
+// Raw FP32 guides and noisy values of one pixel (zeros outside the image),
+// and their conversion to the shifted sum type. Split so that the loads for
+// the next row can be issued a whole iteration before they are consumed.
+template <int Q, int C>
+__device__ __forceinline__ void load_raw(const LaunchArgs& a, int64_t pl, int64_t off, bool ok,
+                                         float (&v)[Q + C]) {
+  if (ok) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = a.guides[q * pl + off];
+#pragma unroll
+    for (int c = 0; c < C; ++c) v[Q + c] = a.noisy[c * pl + off];
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q + C; ++i) v[i] = 0.f;
+  }
+}
+template <int Q, int C>
+__device__ __forceinline__ void shift_raw(const float (&v)[Q + C], bool ok, const float (&cg)[Q],
+                                          sum_t (&g)[Q], sum_t (&y)[C]) {
+#pragma unroll
+  for (int q = 0; q < Q; ++q) g[q] = ok ? (sum_t)v[q] - (sum_t)cg[q] : sum_t(0);
+#pragma unroll
+  for (int c = 0; c < C; ++c) y[c] = (sum_t)v[Q + c];
 }
 
 // Channel order: sum g[Q] | sum y[C] | sum g_p g_q (p<=q) | sum g_q y_c.
@@ -205,44 +283,45 @@ __device__ __forceinline__ void vupdate(sum_t (&V)[num_sums(Q, C)], const sum_t 
   }
 }
 
-// Position of channel m of the upper-triangle block: row p, column q.
-template <int Q>
-__host__ __device__ constexpr int tri_row(int k) {
-  int p = 0;
-  while (k >= Q - p) {
-    k -= Q - p;
-    ++p;
-  }
-  return p;
-}
-template <int Q>
-__host__ __device__ constexpr int tri_col(int k) {
-  int p = 0;
-  while (k >= Q - p) {
-    k -= Q - p;
-    ++p;
-  }
-  return p + k;
-}
-
-// Fold window sum v of channel m (order: sum g | sum y | sum g_p g_q |
-// sum g_q y_c, shifted guides) into the central moments: mu~, nu, the
-// guide covariance Hm and the guide/channel covariance R. Channels arrive in
-// increasing m, so the means are complete before any covariance needs them.
+// Fold the window sums of channels [g0, g0 + gn) (one LDS group; column
+// base pointer `col`, row stride kLdsStride) into the central moments: mu~,
+// nu, the guide covariance Hm and the guide/channel covariance R. Channel
+// order: sum g | sum y | sum g_p g_q (p <= q) | sum g_q y_c (shifted guides).
+// Groups arrive in increasing order and the first holds all Q + C first
+// moments, so the means are complete before any covariance needs them. All
+// loops unroll and every group test folds at compile time.
 template <int Q, int C, typename T>
-__device__ __forceinline__ void centre_channel(int m, T v, T inv_n, T (&mu)[Q], T (&nu)[C],
-                                               T (&Hm)[Q * (Q + 1) / 2], T (&R)[Q * C]) {
+__device__ __forceinline__ void centre_group(int g0, int gn, const sum_t* col, T inv_n, T (&mu)[Q],
+                                             T (&nu)[C], T (&Hm)[Q * (Q + 1) / 2],
+                                             T (&R)[Q * C]) {
   constexpr int NP = Q * (Q + 1) / 2;
-  if (m < Q) {
-    mu[m] = v * inv_n;
-  } else if (m < Q + C) {
-    nu[m - Q] = v * inv_n;
-  } else if (m < Q + C + NP) {
-    const int k = m - Q - C;
-    Hm[k] = fma_t(v, inv_n, -mu[tri_row<Q>(k)] * mu[tri_col<Q>(k)]);
-  } else {
-    const int k = m - Q - C - NP;
-    R[k] = fma_t(v, inv_n, -mu[k / C] * nu[k % C]);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int m = q;
+    if (m >= g0 && m < g0 + gn) mu[q] = (T)col[(m - g0) * kLdsStride] * inv_n;
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int m = Q + c;
+    if (m >= g0 && m < g0 + gn) nu[c] = (T)col[(m - g0) * kLdsStride] * inv_n;
+  }
+#pragma unroll
+  for (int p = 0; p < Q; ++p) {
+#pragma unroll
+    for (int q = p; q < Q; ++q) {
+      const int m = Q + C + tri<Q>(p, q);
+      if (m >= g0 && m < g0 + gn)
+        Hm[tri<Q>(p, q)] = fma_t((T)col[(m - g0) * kLdsStride], inv_n, -mu[p] * mu[q]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int m = Q + C + NP + q * C + c;
+      if (m >= g0 && m < g0 + gn)
+        R[q * C + c] = fma_t((T)col[(m - g0) * kLdsStride], inv_n, -mu[q] * nu[c]);
+    }
   }
 }
 
@@ -290,6 +369,21 @@ __device__ __forceinline__ void average_and_reconstruct(solve_t* t0, solve_t* t1
   }
 }
 
+// Reconstruction from the window sums of all F*C coefficient rows (column
+// base `col`): out_c = (sum b~_c + sum_q g~_q sum a_qc) / n.
+template <int Q, int C>
+__device__ __forceinline__ void reconstruct(const solve_t* col, bool active, const solve_t (&gq)[Q],
+                                            solve_t inv_n, float* out_c0, int64_t pl) {
+  if (!active) return;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    solve_t acc = col[c * kLdsStride];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc = fma_t(gq[q], col[((1 + q) * C + c) * kLdsStride], acc);
+    out_c0[c * pl] = (float)(acc * inv_n);
+  }
+}
+
 enum WalkMode : int { W_MOMENTS = 0, W_FUSED0 = 1, W_FUSED1 = 2 };
 
 // ---------------------------------------------------------------------------
@@ -310,15 +404,17 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
   constexpr int NS = D::NS;
   constexpr int FC = D::FC;
   constexpr int NP = D::NP;
-  constexpr int MG = D::MG;
-  constexpr size_t BYTES_M = (size_t)MG * sizeof(sum_t);
-  constexpr size_t BYTES_A = (size_t)D::AG * sizeof(T);
-  constexpr size_t HALF = (BYTES_M > BYTES_A ? BYTES_M : BYTES_A) * kLdsStride;
+  constexpr WalkLayout LAY =
+      walk_layout(Q, C, MODE == W_FUSED1 ? K_FUSED1 : (MODE == W_FUSED0 ? K_FUSED0 : K_MOMENTS));
+  constexpr int MG = LAY.mg;
+  constexpr bool VA_LDS = MODE == W_FUSED1 && LAY.va_lds;
   extern __shared__ float lds[];
-  sum_t* S0 = reinterpret_cast<sum_t*>(lds);
-  sum_t* S1 = reinterpret_cast<sum_t*>(reinterpret_cast<char*>(lds) + HALF);
-  T* T0 = reinterpret_cast<T*>(lds);
-  T* T1 = reinterpret_cast<T*>(reinterpret_cast<char*>(lds) + HALF);
+  char* lb = reinterpret_cast<char*>(lds);
+  sum_t* S0 = reinterpret_cast<sum_t*>(lb);
+  sum_t* S1 = reinterpret_cast<sum_t*>(lb + LAY.a);
+  T* T0 = reinterpret_cast<T*>(lb);
+  T* T1 = reinterpret_cast<T*>(lb + LAY.a);
+  T* VAL = reinterpret_cast<T*>(lb + LAY.a + LAY.b);  // VA_LDS: [FC][kLdsStride]
 
   const int tid = threadIdx.x;
   const int r = a.r;
@@ -366,34 +462,68 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
     }
   }
 
-  constexpr int NVA = MODE == W_FUSED1 ? FC : 1;
-  T Va[NVA];
+  constexpr int NVA = (MODE == W_FUSED1 && !VA_LDS) ? FC : 1;
+  avg_t Va[NVA];
 #pragma unroll
-  for (int f = 0; f < NVA; ++f) Va[f] = T(0);
+  for (int f = 0; f < NVA; ++f) Va[f] = avg_t(0);
+  if (VA_LDS) {
+#pragma unroll
+    for (int f = 0; f < FC; ++f) VAL[f * kLdsStride + tid] = T(0);
+  }
   ring_t* ring =
       reinterpret_cast<ring_t*>(a.ring) + (size_t)blockIdx.x * (size_t)(2 * r + 1) * FC * kThreads + tid;
 
+  // inputs of the rows entering (ym + r) and leaving (ym - r - 1) the window
+  float fa[Q + C], fs[Q + C];
+  bool okA = false, okS = false;
+  auto fetch = [&](int y) {
+    const int ya = y + r;
+    const int ys = y - r - 1;
+    okA = xin && ya >= 0 && ya < H;
+    okS = xin && y > ym0 && ys >= 0 && ys < H;
+    load_raw<Q, C>(a, pl, (int64_t)ya * W + xi, okA, fa);
+    load_raw<Q, C>(a, pl, (int64_t)ys * W + xi, okS, fs);
+  };
+  fetch(ym0);
+
+  // Coefficient ring (K_FUSED1, r > 0): oldv holds the values of the row
+  // leaving the vertical average at the current step. The reads for the next
+  // step are issued after this step's use but before this step's ring
+  // stores, so that waiting for them never waits on recent stores (vector
+  // memory operations retire in issue order).
+  constexpr int NRING = MODE == W_FUSED1 ? FC : 1;
+  ring_t oldv[NRING];
+  auto ring_fetch = [&](int y) {
+    const int yold = y - 2 * r - 1;
+    const bool ok = MODE == W_FUSED1 && r > 0 && tid < ncoef && y < ym1 && yold >= ym0 &&
+                    yold >= 0 && yold < H;
+    const ring_t* rs = ring + (size_t)((y - ym0) % (2 * r + 1)) * FC * kThreads;
+#pragma unroll
+    for (int f = 0; f < NRING; ++f) oldv[f] = ok ? rs[f * kThreads] : ring_t(0);
+  };
+  ring_fetch(ym0);
+
   for (int ym = ym0; ym < ym1; ++ym) {
     {
-      const int ya = ym + r;
-      const int ys = ym - r - 1;
-      const bool oka = ya >= 0 && ya < H;
-      const bool oks = ym > ym0 && ys >= 0 && ys < H;
       sum_t ga[Q], yA[C], gs[Q], yS[C];
-      load_px<Q, C>(a, pl, (int64_t)ya * W + xi, xin && oka, cg, ga, yA);
-      load_px<Q, C>(a, pl, (int64_t)ys * W + xi, xin && oks, cg, gs, yS);
+      shift_raw<Q, C>(fa, okA, cg, ga, yA);
+      shift_raw<Q, C>(fs, okS, cg, gs, yS);
       vupdate<Q, C>(V, ga, yA, gs, yS);
     }
+    if (ym + 1 < ym1) fetch(ym + 1);
+
+    const int slot = MODE == W_FUSED1 ? (ym - ym0) % (2 * r + 1) : 0;
     const bool row_in = ym >= 0 && ym < H;
 
-    T cv[NVA];
+    constexpr int NCV = MODE == W_FUSED1 ? FC : 1;
+    T cv[NCV];
 #pragma unroll
-    for (int f = 0; f < NVA; ++f) cv[f] = T(0);
+    for (int f = 0; f < NCV; ++f) cv[f] = T(0);
 
     if (row_in) {
       const int64_t off = (int64_t)ym * W + xc;
       const int ni = cvalid ? win_count(ym, H, r) * win_count(xc, W, r) : 1;
-      const T inv_n = T(1) / (T)ni;
+      const T inv_n = recip_count(ni, T(0));
       T mu[Q], nu[C], Hm[NP], R[Q * C];
 #pragma unroll
       for (int g0 = 0; g0 < NS; g0 += MG) {
@@ -405,13 +535,12 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
         hbox(S0, S1, gn, ncoef, r, a.hchunk_m);
         __syncthreads();
         if (cvalid) {
+          if (MODE == W_MOMENTS && a.raw) {
 #pragma unroll
-          for (int m = 0; m < gn; ++m) {
-            const sum_t v = S1[m * kLdsStride + tid];
-            if (MODE == W_MOMENTS && a.raw)
-              a.out[(1 + g0 + m) * pl + off] = (float)v;
-            else
-              centre_channel<Q, C, T>(g0 + m, (T)v, inv_n, mu, nu, Hm, R);
+            for (int m = 0; m < gn; ++m)
+              a.out[(1 + g0 + m) * pl + off] = (float)S1[m * kLdsStride + tid];
+          } else {
+            centre_group<Q, C, T>(g0, gn, S1 + tid, inv_n, mu, nu, Hm, R);
           }
         }
       }
@@ -464,21 +593,27 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
     if (MODE == W_FUSED1) {
       // vertical window sums of the coefficients through the ring
       if (tid < ncoef) {
-        const int slot = (ym - ym0) % (2 * r + 1);
-        ring_t* rs = ring + (size_t)slot * FC * kThreads;
-        const int yold = ym - 2 * r - 1;
-        const bool okold = yold >= ym0 && yold >= 0 && yold < H;
 #pragma unroll
         for (int f = 0; f < FC; ++f) {
           // the ring holds the stored (rounded) values, so add those too
           const ring_t nw = (ring_t)cv[f];
-          const T old = okold ? (T)rs[f * kThreads] : T(0);
-          Va[f] += (T)nw - old;
+          if (r == 0) {  // window of one row: no history needed
+            if (VA_LDS)
+              VAL[f * kLdsStride + tid] = (T)nw;
+            else
+              Va[f] = (avg_t)nw;
+          } else if (VA_LDS) {
+            VAL[f * kLdsStride + tid] += (T)nw - (T)oldv[f];
+          } else {
+            Va[f] += (avg_t)nw - (avg_t)oldv[f];
+          }
         }
-        if (row_in) {
+      }
+      ring_fetch(ym + 1);
+      if (tid < ncoef && row_in && r > 0) {
+        ring_t* rs = ring + (size_t)slot * FC * kThreads;
 #pragma unroll
-          for (int f = 0; f < FC; ++f) rs[f * kThreads] = (ring_t)cv[f];
-        }
+        for (int f = 0; f < FC; ++f) rs[f * kThreads] = (ring_t)cv[f];
       }
       const int yo = ym - r;
       if (yo >= Y0 && yo < Y1) {
@@ -490,19 +625,26 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
         if (active) {
 #pragma unroll
           for (int q = 0; q < Q; ++q) gq[q] = ((T)a.guides[q * pl + off] - (T)cg[q]);
-          inv = T(1) / (T)(win_count(yo, H, r) * win_count(xo, W, r));
+          inv = recip_count(win_count(yo, H, r) * win_count(xo, W, r), T(0));
         } else {
 #pragma unroll
           for (int q = 0; q < Q; ++q) gq[q] = T(0);
         }
-        average_and_reconstruct<Q, C>(
-            T0, T1, tout, r, a.hchunk_a, active, gq, inv, a.out + off, pl,
-            [&](int f0, int gn, T* dst) {
-              if (tid < ncoef) {
+        if (VA_LDS) {
+          __syncthreads();
+          hbox(VAL, T1, FC, tout, r, a.hchunk_a);
+          __syncthreads();
+          reconstruct<Q, C>(T1 + tid, active, gq, inv, a.out + off, pl);
+        } else {
+          average_and_reconstruct<Q, C>(
+              T0, T1, tout, r, a.hchunk_a, active, gq, inv, a.out + off, pl,
+              [&](int f0, int gn, T* dst) {
+                if (tid < ncoef) {
 #pragma unroll
-                for (int k = 0; k < gn; ++k) dst[k * kLdsStride + tid] = Va[f0 + k];
-              }
-            });
+                  for (int k = 0; k < gn; ++k) dst[k * kLdsStride + tid] = (T)Va[f0 + k];
+                }
+              });
+        }
       }
     }
   }
@@ -567,10 +709,10 @@ template <int Q, int C>
 __global__ void __launch_bounds__(kThreads, 1) apply_avg_kernel(LaunchArgs a) {
   using T = solve_t;
   constexpr int FC = Dims<Q, C>::FC;
-  constexpr size_t HALF = (size_t)Dims<Q, C>::AG * sizeof(T) * kLdsStride;
+  constexpr WalkLayout LAY = walk_layout(Q, C, K_APPLY_AVG);
   extern __shared__ float lds[];
   T* T0 = reinterpret_cast<T*>(lds);
-  T* T1 = reinterpret_cast<T*>(reinterpret_cast<char*>(lds) + HALF);
+  T* T1 = reinterpret_cast<T*>(reinterpret_cast<char*>(lds) + LAY.a);
   const int tid = threadIdx.x;
   const int r = a.r;
   const int H = a.H;
@@ -615,7 +757,7 @@ __global__ void __launch_bounds__(kThreads, 1) apply_avg_kernel(LaunchArgs a) {
     if (active) {
 #pragma unroll
       for (int q = 0; q < Q; ++q) gq[q] = (T)a.guides[q * pl + off];
-      inv = T(1) / (T)(win_count(yo, H, r) * win_count(xo, W, r));
+      inv = recip_count(win_count(yo, H, r) * win_count(xo, W, r), T(0));
     } else {
 #pragma unroll
       for (int q = 0; q < Q; ++q) gq[q] = T(0);

@@ -33,6 +33,11 @@ constexpr int kCUs = 256;
 typedef FLR_SUM_T sum_t;
 typedef FLR_SOLVE_T solve_t;
 typedef FLR_RING_T ring_t;
+// Running vertical sums of the ring values in the fused kernel.
+#ifndef FLR_AVG_T
+#define FLR_AVG_T double
+#endif
+typedef FLR_AVG_T avg_t;
 // LDS row stride in elements: kThreads + 1 keeps lanes that read
 // consecutive channel rows of one column on distinct banks.
 constexpr int kLdsStride = kThreads + 1;
@@ -137,17 +142,59 @@ inline int plan_chunk(int rows, int nout, int r) {
   return best;
 }
 
-// Moment channels per LDS group, and coefficient planes per LDS group.
-inline int moment_group_rows(int Q, int C) { return group_size(num_sums(Q, C), sizeof(sum_t)); }
-inline int coeff_group_rows(int Q, int C) { return group_size((Q + 1) * C, sizeof(solve_t)); }
+// LDS layout of the walker kernels (bytes, rows of kLdsStride elements):
+//   [0, a)            source rows of the horizontal pass (one moment group);
+//   [a, a + b)        destination rows (moment group, or coefficient sums);
+//   [a + b, + va)     K_FUSED1 only, when it fits: the persistent vertical
+//                     window sums of the coefficients, F*C rows of solve_t,
+//                     read directly by the horizontal averaging pass.
+// Moment channels are processed in groups of `mg` rows; the first group
+// always holds all Q + C first moments.
+struct WalkLayout {
+  int mg;          // moment rows per group
+  int ag;          // coefficient rows per averaging group (va_lds: all F*C)
+  bool va_lds;     // coefficient sums live in LDS
+  size_t a, b, va; // region sizes in bytes
+};
+
+__host__ __device__ constexpr WalkLayout walk_layout(int Q, int C, int kind) {
+  const int ns = num_sums(Q, C);
+  const int fc = (Q + 1) * C;
+  const int row_s = kLdsStride * (int)sizeof(sum_t);
+  const int row_t = kLdsStride * (int)sizeof(solve_t);
+  WalkLayout L{0, 0, false, 0, 0, 0};
+  if (kind == K_APPLY_AVG) {
+    L.ag = group_size(fc, sizeof(solve_t));
+    L.a = L.b = (size_t)L.ag * row_t;
+    return L;
+  }
+  if (kind == K_FUSED1) {
+    const int va = fc * row_t;
+    const int left = kLdsBytes - 2 * va;  // Va region + destination sized for F*C rows
+    const int mg_max = left > 0 ? left / row_s : 0;
+    if (mg_max >= Q + C) {
+      const int ng = (ns + mg_max - 1) / mg_max;
+      L.mg = (ns + ng - 1) / ng;
+      L.ag = fc;
+      L.va_lds = true;
+      L.a = (size_t)L.mg * row_s;
+      const size_t bm = (size_t)L.mg * row_s;
+      L.b = bm > (size_t)va ? bm : (size_t)va;
+      L.va = (size_t)va;
+      return L;
+    }
+  }
+  L.mg = group_size(ns, sizeof(sum_t));
+  L.ag = group_size(fc, sizeof(solve_t));
+  const size_t m = (size_t)L.mg * row_s;
+  const size_t c = (size_t)L.ag * row_t;
+  L.a = L.b = m > c ? m : c;
+  return L;
+}
 
 inline size_t walk_lds_bytes(int kind, int Q, int C) {
-  size_t b = (size_t)coeff_group_rows(Q, C) * sizeof(solve_t);
-  if (kind != K_APPLY_AVG) {
-    const size_t m = (size_t)moment_group_rows(Q, C) * sizeof(sum_t);
-    if (m > b) b = m;
-  }
-  return 2 * b * kLdsStride;
+  const WalkLayout L = walk_layout(Q, C, kind);
+  return L.a + L.b + L.va;
 }
 
 inline size_t ring_bytes_per_block(int Q, int C, int r) {
