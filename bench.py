@@ -117,7 +117,8 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--unfused", action="store_true", help="time the three-stage path instead")
+    ap.add_argument("--path", default="fused", choices=["fused", "two_pass", "stages"],
+                    help="flr_denoise execution path to time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args(argv)
@@ -156,7 +157,7 @@ def main(argv=None):
             continue
         sets.append((torch.from_numpy(fr["noisy"]).to(dev), torch.from_numpy(fr["guides"]).to(dev),
                      torch.empty((C, H, W), dtype=torch.float32, device=dev)))
-    fused = not args.unfused
+    fused = args.path
     p = flr.make_params(H, W, Q, C, R, eps=EPS, average=True, fused=fused)
     ws_bytes = flr.workspace_bytes(p)
     ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
@@ -208,7 +209,7 @@ def main(argv=None):
 
     cpu = None if args.no_cpu_baseline else cpu_baseline()
     line = {
-        "metric": "Mpixel/s at 1080p (FLR, fused), ms/frame, % roofline, err vs FP64",
+        "metric": "Mpixel/s at 1080p (FLR), ms/frame, % roofline, err vs FP64",
         "value": round(mpix_s, 2),
         "unit": "Mpixel/s",
         "n_gpus": 1,
@@ -222,7 +223,9 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": "FLR 1920x1080 RGB frame, 8 guides + constant, radius 8, "
                                "eps 1e-3, ridge, window-averaged coefficients",
-                   "path": "fused" if fused else "unfused (moments -> solve -> apply)",
+                   "path": {"fused": "fused (one kernel)",
+                            "two_pass": "two kernels (moments+solve, average+reconstruct)",
+                            "stages": "three stages (moments, solve, apply)"}[fused],
                    "io_dtype": "f32", "accumulate_dtype": "f64", "buffer_sets": nsets,
                    "ms_per_frame_p10_p50_p90": [round(float(np.percentile(per, q)), 5)
                                                 for q in (10, 50, 90)],

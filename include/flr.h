@@ -15,7 +15,9 @@
  *                with Eq. tikhonov, or the Appendix normalisation);
  *   flr_apply    optional window-average of the coefficients, then the
  *                reconstruction I_k = x_k A_k (Sec. 3.1);
- *   flr_denoise  all of the above, fused into one kernel or as three stages.
+ *   flr_denoise  all of the above: in one fused kernel, in two kernels
+ *                (moments + solve, then average + reconstruction), or as the
+ *                three stage entry points (see flr_path).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -82,11 +84,23 @@ typedef enum {
   FLR_ERR_ALIAS = 6,      /* an output overlaps an input */
   FLR_ERR_ALIGN = 7,      /* a pointer is not 16-byte aligned */
   FLR_ERR_WORKSPACE = 8,  /* workspace missing or smaller than required */
-  FLR_ERR_MODE = 9,       /* reg_mode / flags / boolean field invalid */
+  FLR_ERR_MODE = 9,       /* reg_mode / fused / flags / boolean field invalid */
   FLR_ERR_HIP = 10        /* a HIP launch failed */
 } flr_status;
 
 typedef enum { FLR_REG_RIDGE = 0, FLR_REG_PAPER = 1 } flr_reg_mode;
+
+/* flr_denoise execution paths (flr_params.fused) */
+typedef enum {
+  FLR_PATH_STAGES = 0,   /* flr_moments -> flr_solve -> flr_apply, images in the workspace */
+  FLR_PATH_FUSED = 1,    /* one kernel: moments, solve, average, reconstruction; with
+                            averaging, coefficients pass through a per-workgroup ring
+                            in the workspace and r coefficient rows are recomputed at
+                            each workgroup's top and bottom */
+  FLR_PATH_TWO_PASS = 2  /* with averaging: one kernel for moments and solve writing the
+                            coefficient image to the workspace, then the averaging and
+                            reconstruction of flr_apply; without averaging: as FUSED */
+} flr_path;
 
 /* flags */
 #define FLR_FLAG_RAW_MOMENTS 1u /* flr_moments only: write raw window sums
@@ -104,8 +118,7 @@ typedef struct {
   int32_t reg_mode;        /* flr_reg_mode */
   int32_t average_coeffs;  /* 1: average (b, a) over the window before
                               reconstruction; 0: use the pixel's own model */
-  int32_t fused;           /* flr_denoise: 1 = one fused kernel,
-                              0 = flr_moments -> flr_solve -> flr_apply */
+  int32_t fused;           /* flr_denoise: an flr_path */
   uint32_t flags;          /* FLR_FLAG_* */
   int32_t tile_rows;       /* rows per workgroup segment; 0 = automatic */
 } flr_params;
@@ -116,9 +129,11 @@ size_t flr_num_moment_planes(int32_t num_guides, int32_t num_channels);
 size_t flr_num_coeff_planes(int32_t num_guides, int32_t num_channels);
 
 /* Workspace bytes flr_denoise needs for these parameters (0 if invalid):
- * unfused: the moment and coefficient images, (M + F*C)*H*W floats;
- * fused with averaging: a per-workgroup ring of 2r+1 coefficient rows;
- * fused without averaging: 0. Depends on the launch geometry only. */
+ * FLR_PATH_STAGES: the moment and coefficient images, (M + F*C)*H*W floats
+ * (the coefficient image starts at the next 256-byte boundary);
+ * FLR_PATH_FUSED with averaging: a per-workgroup ring of 2r+1 coefficient rows;
+ * FLR_PATH_TWO_PASS with averaging: the coefficient image, F*C*H*W floats;
+ * without averaging: 0 (STAGES aside). Depends on the launch geometry only. */
 size_t flr_denoise_workspace_bytes(const flr_params* p);
 
 /* Window moments (Sec. 3.2). Reads guides, noisy; writes moments [M][H][W]. */

@@ -15,6 +15,18 @@ from ._lib import (FLR_FLAG_RAW_MOMENTS, FLR_REG_PAPER, FLR_REG_RIDGE, FLRError,
                    check, lib)
 
 _MODES = {"ridge": FLR_REG_RIDGE, "paper": FLR_REG_PAPER}
+# flr_denoise execution paths (flr_path in the C header)
+PATHS = {"stages": 0, "fused": 1, "two_pass": 2}
+
+
+def _path(fused) -> int:
+    """True/False keep their meaning (fused kernel / three stages); a path name
+    or its integer value selects any path."""
+    if isinstance(fused, str):
+        return PATHS[fused]
+    if isinstance(fused, bool):
+        return 1 if fused else 0
+    return int(fused)
 
 
 def _need(t: torch.Tensor, name: str, ndim: int = 3) -> None:
@@ -36,12 +48,12 @@ def _stream(t: torch.Tensor) -> ctypes.c_void_p:
 
 def make_params(H: int, W: int, Q: int, C: int, radius: int, eps: float = 1e-3,
                 mode: str = "ridge", eps_mul: float = 0.0, average: bool = True,
-                fused: bool = True, raw: bool = False, tile_rows: int = 0) -> FlrParams:
+                fused=True, raw: bool = False, tile_rows: int = 0) -> FlrParams:
     if mode not in _MODES:
         raise ValueError(f"mode must be one of {sorted(_MODES)}")
     return FlrParams(height=H, width=W, num_guides=Q, num_channels=C, radius=radius,
                      eps=eps, eps_mul=eps_mul, reg_mode=_MODES[mode],
-                     average_coeffs=int(bool(average)), fused=int(bool(fused)),
+                     average_coeffs=int(bool(average)), fused=_path(fused),
                      flags=FLR_FLAG_RAW_MOMENTS if raw else 0, tile_rows=tile_rows)
 
 
@@ -113,10 +125,12 @@ def apply(guides: torch.Tensor, coeffs: torch.Tensor, radius: int, average: bool
 
 def denoise(noisy: torch.Tensor, guides: torch.Tensor, radius: int = 8, eps: float = 1e-3,
             mode: str = "ridge", eps_mul: float = 0.0, average: bool = True,
-            fused: bool = True, tile_rows: int = 0, out: torch.Tensor | None = None,
+            fused=True, tile_rows: int = 0, out: torch.Tensor | None = None,
             workspace: torch.Tensor | None = None) -> torch.Tensor:
-    """The whole FLR path -> [C,H,W]. ``workspace`` is a uint8 device tensor
-    of at least ``workspace_bytes`` bytes; it is allocated when omitted."""
+    """The whole FLR path -> [C,H,W]. ``fused``: True (one kernel), False
+    (three stages) or a path name from ``PATHS``. ``workspace`` is a uint8
+    device tensor of at least ``workspace_bytes`` bytes; it is allocated when
+    omitted."""
     _need(guides, "guides")
     _need(noisy, "noisy")
     Q, H, W = guides.shape

@@ -115,7 +115,7 @@ flr_status flr_validate_params(const flr_params* p) {
   if (!isfinite(p->eps) || p->eps < 0.f || !isfinite(p->eps_mul) || p->eps_mul < 0.f)
     return FLR_ERR_EPS;
   if (p->reg_mode != FLR_REG_RIDGE && p->reg_mode != FLR_REG_PAPER) return FLR_ERR_MODE;
-  if ((p->average_coeffs != 0 && p->average_coeffs != 1) || (p->fused != 0 && p->fused != 1))
+  if ((p->average_coeffs != 0 && p->average_coeffs != 1) || p->fused < 0 || p->fused > 2)
     return FLR_ERR_MODE;
   if (p->flags & ~(uint32_t)FLR_FLAG_RAW_MOMENTS) return FLR_ERR_MODE;
   if (p->tile_rows < 0) return FLR_ERR_SHAPE;
@@ -125,9 +125,12 @@ flr_status flr_validate_params(const flr_params* p) {
 size_t flr_denoise_workspace_bytes(const flr_params* p) {
   if (flr_validate_params(p) != FLR_OK) return 0;
   const size_t pb = plane_bytes(p);
-  if (!p->fused)
+  if (p->fused == FLR_PATH_STAGES)
     return unfused_coeff_offset(p) + flr_num_coeff_planes(p->num_guides, p->num_channels) * pb;
-  return p->average_coeffs ? ring_bytes(p) : 0;
+  if (!p->average_coeffs) return 0;
+  if (p->fused == FLR_PATH_TWO_PASS)
+    return flr_num_coeff_planes(p->num_guides, p->num_channels) * pb;
+  return ring_bytes(p);
 }
 
 flr_status flr_moments(const flr_params* p, const float* guides, const float* noisy,
@@ -202,6 +205,15 @@ flr_status flr_denoise(const flr_params* p, const float* guides, const float* no
       return FLR_ERR_ALIAS;
   }
   const int Q = p->num_guides, C = p->num_channels;
+  if (p->fused == FLR_PATH_TWO_PASS && p->average_coeffs) {
+    LaunchArgs a = base_args(p);
+    a.guides = guides;
+    a.noisy = noisy;
+    a.out = static_cast<float*>(workspace);
+    plan(p, flr::K_COEFFS, &a);
+    if ((st = dispatch(Q, C, flr::K_COEFFS, a, stream)) != FLR_OK) return st;
+    return flr_apply(p, guides, static_cast<const float*>(workspace), out, stream);
+  }
   if (p->fused) {
     LaunchArgs a = base_args(p);
     a.guides = guides;

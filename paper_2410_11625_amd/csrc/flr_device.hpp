@@ -33,7 +33,6 @@ struct Dims {
   static constexpr int NQC = Q * C;           // guide x channel products
   static constexpr int NS = Q + C + NP + NQC; // summed channels (n is analytic)
   static constexpr int FC = F * C;            // coefficients per pixel
-  static constexpr int AG = group_size(FC, sizeof(solve_t)); // coefficient rows per LDS group
 };
 
 // Index of (p, q), p <= q, in a row-major packed upper triangle.
@@ -156,8 +155,8 @@ __device__ __forceinline__ void hbox(const E* __restrict__ src, E* __restrict__ 
   const int nch = (nout + chunk - 1) / chunk;
   const int ntask = rows * nch;
   const int w = 2 * r + 1;
-  // Each thread runs two tasks side by side, so that two independent
-  // dependency chains hide each other's LDS latency.
+  // Each thread runs two tasks side by side, and issues the loads of four
+  // outputs of both at once, so that independent LDS reads overlap.
   for (int t0 = threadIdx.x; t0 < ntask; t0 += 2 * kThreads) {
     const int t1 = t0 + kThreads;
     const int m0 = t0 % rows, j00 = (t0 / rows) * chunk;
@@ -169,28 +168,35 @@ __device__ __forceinline__ void hbox(const E* __restrict__ src, E* __restrict__ 
     const E* s1 = src + m1 * kLdsStride + j01;
     E* d0 = dst + m0 * kLdsStride + j00;
     E* d1 = dst + m1 * kLdsStride + j01;
-    E a0 = E(0), b0 = E(0), a1 = E(0), b1 = E(0);
+    E a0 = E(0), b0 = E(0), c0 = E(0), e0 = E(0);
+    E a1 = E(0), b1 = E(0), c1 = E(0), e1 = E(0);
     int k = 0;
-    for (; k + 2 <= w; k += 2) {
+    for (; k + 4 <= w; k += 4) {
       a0 += s0[k];
       b0 += s0[k + 1];
+      c0 += s0[k + 2];
+      e0 += s0[k + 3];
       a1 += s1[k];
       b1 += s1[k + 1];
+      c1 += s1[k + 2];
+      e1 += s1[k + 3];
     }
-    if (k < w) {
+    for (; k < w; ++k) {
       a0 += s0[k];
       a1 += s1[k];
     }
-    E acc0 = a0 + b0, acc1 = a1 + b1;
+    E acc0 = (a0 + b0) + (c0 + e0), acc1 = (a1 + b1) + (c1 + e1);
     d0[0] = acc0;
     if (n1 > 0) d1[0] = acc1;
-    const E* e0 = s0 + 2 * r;
-    const E* e1 = s1 + 2 * r;
+    const E* x0 = s0 + 2 * r;
+    const E* x1 = s1 + 2 * r;
     const int n = min(n0, n1);
     int j = 1;
-    for (; j + 2 <= n; j += 2) {
-      const E p0 = e0[j], p1 = e0[j + 1], q0 = s0[j - 1], q1 = s0[j];
-      const E u0 = e1[j], u1 = e1[j + 1], v0 = s1[j - 1], v1 = s1[j];
+    for (; j + 4 <= n; j += 4) {
+      const E p0 = x0[j], p1 = x0[j + 1], p2 = x0[j + 2], p3 = x0[j + 3];
+      const E q0 = s0[j - 1], q1 = s0[j], q2 = s0[j + 1], q3 = s0[j + 2];
+      const E u0 = x1[j], u1 = x1[j + 1], u2 = x1[j + 2], u3 = x1[j + 3];
+      const E v0 = s1[j - 1], v1 = s1[j], v2 = s1[j + 1], v3 = s1[j + 2];
       acc0 += p0 - q0;
       acc1 += u0 - v0;
       d0[j] = acc0;
@@ -199,33 +205,23 @@ __device__ __forceinline__ void hbox(const E* __restrict__ src, E* __restrict__ 
       acc1 += u1 - v1;
       d0[j + 1] = acc0;
       d1[j + 1] = acc1;
+      acc0 += p2 - q2;
+      acc1 += u2 - v2;
+      d0[j + 2] = acc0;
+      d1[j + 2] = acc1;
+      acc0 += p3 - q3;
+      acc1 += u3 - v3;
+      d0[j + 3] = acc0;
+      d1[j + 3] = acc1;
     }
     for (int jj = j; jj < n0; ++jj) {
-      acc0 += e0[jj] - s0[jj - 1];
+      acc0 += x0[jj] - s0[jj - 1];
       d0[jj] = acc0;
     }
     for (int jj = (n1 > 0 ? j : n1); jj < n1; ++jj) {
-      acc1 += e1[jj] - s1[jj - 1];
+      acc1 += x1[jj] - s1[jj - 1];
       d1[jj] = acc1;
     }
-  }
-}
-
-// Guides (shifted by the anchor) and noisy values of one pixel; zeros when
-// the pixel is outside the image so that it contributes nothing.
-template <int Q, int C>
-__device__ __forceinline__ void load_px(const LaunchArgs& a, int64_t pl, int64_t off, bool ok,
-                                        const float (&cg)[Q], sum_t (&g)[Q], sum_t (&y)[C]) {
-  if (ok) {
-#pragma unroll
-    for (int q = 0; q < Q; ++q) g[q] = (sum_t)a.guides[q * pl + off] - (sum_t)cg[q];
-#pragma unroll
-    for (int c = 0; c < C; ++c) y[c] = (sum_t)a.noisy[c * pl + off];
-  } else {
-#pragma unroll
-    for (int q = 0; q < Q; ++q) g[q] = sum_t(0);
-#pragma unroll
-    for (int c = 0; c < C; ++c) y[c] = sum_t(0);
   }
 }
 
@@ -290,10 +286,10 @@ __device__ __forceinline__ void vupdate(sum_t (&V)[num_sums(Q, C)], const sum_t 
 // Groups arrive in increasing order and the first holds all Q + C first
 // moments, so the means are complete before any covariance needs them. All
 // loops unroll and every group test folds at compile time.
-template <int Q, int C, typename T>
+template <int Q, int C, typename T, typename U>
 __device__ __forceinline__ void centre_group(int g0, int gn, const sum_t* col, T inv_n, T (&mu)[Q],
-                                             T (&nu)[C], T (&Hm)[Q * (Q + 1) / 2],
-                                             T (&R)[Q * C]) {
+                                             T (&nu)[C], U (&Hm)[Q * (Q + 1) / 2],
+                                             U (&R)[Q * C]) {
   constexpr int NP = Q * (Q + 1) / 2;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -311,7 +307,7 @@ __device__ __forceinline__ void centre_group(int g0, int gn, const sum_t* col, T
     for (int q = p; q < Q; ++q) {
       const int m = Q + C + tri<Q>(p, q);
       if (m >= g0 && m < g0 + gn)
-        Hm[tri<Q>(p, q)] = fma_t((T)col[(m - g0) * kLdsStride], inv_n, -mu[p] * mu[q]);
+        Hm[tri<Q>(p, q)] = (U)fma_t((T)col[(m - g0) * kLdsStride], inv_n, -mu[p] * mu[q]);
     }
   }
 #pragma unroll
@@ -320,7 +316,7 @@ __device__ __forceinline__ void centre_group(int g0, int gn, const sum_t* col, T
     for (int c = 0; c < C; ++c) {
       const int m = Q + C + NP + q * C + c;
       if (m >= g0 && m < g0 + gn)
-        R[q * C + c] = fma_t((T)col[(m - g0) * kLdsStride], inv_n, -mu[q] * nu[c]);
+        R[q * C + c] = (U)fma_t((T)col[(m - g0) * kLdsStride], inv_n, -mu[q] * nu[c]);
     }
   }
 }
@@ -329,14 +325,12 @@ __device__ __forceinline__ void centre_group(int g0, int gn, const sum_t* col, T
 // the caller in groups via `fill`), and the reconstruction
 //   out_c = (sum b~_c + sum_q g~_q sum a_qc) / n   for output lane `o`.
 // `fill(f0, gn, t0)` writes coefficient rows f0..f0+gn-1 into t0.
-template <int Q, int C, typename Fill>
+template <int Q, int C, int AG, typename Fill>
 __device__ __forceinline__ void average_and_reconstruct(solve_t* t0, solve_t* t1, int nout, int r,
                                                         int chunk, bool active,
                                                         const solve_t (&gq)[Q], solve_t inv_n,
                                                         float* out_c0, int64_t pl, Fill fill) {
-  using D = Dims<Q, C>;
-  constexpr int FC = D::FC;
-  constexpr int AG = D::AG;
+  constexpr int FC = Dims<Q, C>::FC;
   solve_t acc[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) acc[c] = solve_t(0);
@@ -384,13 +378,14 @@ __device__ __forceinline__ void reconstruct(const solve_t* col, bool active, con
   }
 }
 
-enum WalkMode : int { W_MOMENTS = 0, W_FUSED0 = 1, W_FUSED1 = 2 };
+enum WalkMode : int { W_MOMENTS = 0, W_FUSED0 = 1, W_FUSED1 = 2, W_COEFFS = 3 };
 
 // ---------------------------------------------------------------------------
 // The walker. MODE selects what happens with the window moments of each
 // coefficient position:
 //   W_MOMENTS  write the moment planes (central, or raw sums with a.raw);
 //   W_FUSED0   solve and reconstruct at the same pixel;
+//   W_COEFFS   solve and write the coefficient planes (original units);
 //   W_FUSED1   solve, push the coefficients through a per-workgroup ring of
 //              2r+1 rows (global workspace) to form vertical window sums,
 //              stage those through LDS for the horizontal sums, and
@@ -404,8 +399,10 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
   constexpr int NS = D::NS;
   constexpr int FC = D::FC;
   constexpr int NP = D::NP;
-  constexpr WalkLayout LAY =
-      walk_layout(Q, C, MODE == W_FUSED1 ? K_FUSED1 : (MODE == W_FUSED0 ? K_FUSED0 : K_MOMENTS));
+  constexpr WalkLayout LAY = walk_layout(
+      Q, C,
+      MODE == W_FUSED1 ? K_FUSED1
+                       : (MODE == W_FUSED0 ? K_FUSED0 : (MODE == W_COEFFS ? K_COEFFS : K_MOMENTS)));
   constexpr int MG = LAY.mg;
   constexpr bool VA_LDS = MODE == W_FUSED1 && LAY.va_lds;
   extern __shared__ float lds[];
@@ -449,15 +446,27 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
   const int ym0 = Y0 - hc;
   const int ym1 = Y1 + hc;
   {
+    // warm-up: rows [ym0 - r, ym0 + r) of the first window, each row's loads
+    // issued one step ahead
     sum_t zg[Q], zy[C];
 #pragma unroll
     for (int q = 0; q < Q; ++q) zg[q] = sum_t(0);
 #pragma unroll
     for (int c = 0; c < C; ++c) zy[c] = sum_t(0);
+    float wb[Q + C];
+    bool wok = xin && ym0 - r >= 0 && ym0 - r < H;
+    load_raw<Q, C>(a, pl, (int64_t)(ym0 - r) * W + xi, wok, wb);
     for (int yy = ym0 - r; yy < ym0 + r; ++yy) {
-      if (yy < 0 || yy >= H) continue;
+      float cur[Q + C];
+#pragma unroll
+      for (int i = 0; i < Q + C; ++i) cur[i] = wb[i];
+      const bool cok = wok;
+      if (yy + 1 < ym0 + r) {
+        wok = xin && yy + 1 >= 0 && yy + 1 < H;
+        load_raw<Q, C>(a, pl, (int64_t)(yy + 1) * W + xi, wok, wb);
+      }
       sum_t g[Q], y[C];
-      load_px<Q, C>(a, pl, (int64_t)yy * W + xi, xin, cg, g, y);
+      shift_raw<Q, C>(cur, cok, cg, g, y);
       vupdate<Q, C>(V, g, y, zg, zy);
     }
   }
@@ -524,13 +533,18 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
       const int64_t off = (int64_t)ym * W + xc;
       const int ni = cvalid ? win_count(ym, H, r) * win_count(xc, W, r) : 1;
       const T inv_n = recip_count(ni, T(0));
-      T mu[Q], nu[C], Hm[NP], R[Q * C];
+      // means in solve_t; the centred system (formed in solve_t) in chol_t
+      T mu[Q], nu[C];
+      chol_t Hm[NP], R[Q * C];
+      // Group g's vertical sums go to LDS in the same barrier interval in
+      // which group g-1's window sums are consumed. (The first write needs no
+      // barrier: the source rows were last read by a horizontal pass that
+      // ended before a barrier of the previous step.)
+#pragma unroll
+      for (int m = 0; m < (MG < NS ? MG : NS); ++m) S0[m * kLdsStride + tid] = V[m];
 #pragma unroll
       for (int g0 = 0; g0 < NS; g0 += MG) {
         const int gn = NS - g0 < MG ? NS - g0 : MG;
-        __syncthreads();
-#pragma unroll
-        for (int m = 0; m < gn; ++m) S0[m * kLdsStride + tid] = V[g0 + m];
         __syncthreads();
         hbox(S0, S1, gn, ncoef, r, a.hchunk_m);
         __syncthreads();
@@ -540,8 +554,14 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
             for (int m = 0; m < gn; ++m)
               a.out[(1 + g0 + m) * pl + off] = (float)S1[m * kLdsStride + tid];
           } else {
-            centre_group<Q, C, T>(g0, gn, S1 + tid, inv_n, mu, nu, Hm, R);
+            centre_group<Q, C, T, chol_t>(g0, gn, S1 + tid, inv_n, mu, nu, Hm, R);
           }
+        }
+        if (g0 + MG < NS) {
+          const int g1 = g0 + MG;
+          const int gn1 = NS - g1 < MG ? NS - g1 : MG;
+#pragma unroll
+          for (int m = 0; m < gn1; ++m) S0[m * kLdsStride + tid] = V[g1 + m];
         }
       }
       if (cvalid) {
@@ -559,11 +579,26 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
           }
         } else {
           T mu_o[Q];
+          chol_t mu_c[Q];
 #pragma unroll
-          for (int q = 0; q < Q; ++q) mu_o[q] = mu[q] + (T)cg[q];
-          regularise<Q, T>(Hm, mu_o, (T)a.eps, (T)a.eps_mul, a.reg_mode);
-          chol_solve<Q, C, T>(Hm, R);
-          if (MODE == W_FUSED0) {
+          for (int q = 0; q < Q; ++q) {
+            mu_o[q] = mu[q] + (T)cg[q];
+            mu_c[q] = (chol_t)mu_o[q];
+          }
+          regularise<Q, chol_t>(Hm, mu_c, (chol_t)a.eps, (chol_t)a.eps_mul, a.reg_mode);
+          chol_solve<Q, C, chol_t>(Hm, R);
+          if (MODE == W_COEFFS) {
+            // b = nu - a^T mu in original units
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+              T b = nu[c];
+#pragma unroll
+              for (int q = 0; q < Q; ++q) b = fma_t(-(T)R[q * C + c], mu_o[q], b);
+              a.out[c * pl + off] = (float)b;
+            }
+#pragma unroll
+            for (int k = 0; k < Q * C; ++k) a.out[(C + k) * pl + off] = (float)R[k];
+          } else if (MODE == W_FUSED0) {
             T gp[Q];
 #pragma unroll
             for (int q = 0; q < Q; ++q) gp[q] = ((T)a.guides[q * pl + off] - (T)cg[q]) - mu[q];
@@ -571,7 +606,7 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
             for (int c = 0; c < C; ++c) {
               T acc = nu[c];
 #pragma unroll
-              for (int q = 0; q < Q; ++q) acc = fma_t(gp[q], R[q * C + c], acc);
+              for (int q = 0; q < Q; ++q) acc = fma_t(gp[q], (T)R[q * C + c], acc);
               a.out[c * pl + off] = (float)acc;
             }
           } else {
@@ -580,11 +615,11 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
             for (int c = 0; c < C; ++c) {
               T b = nu[c];
 #pragma unroll
-              for (int q = 0; q < Q; ++q) b = fma_t(-R[q * C + c], mu[q], b);
+              for (int q = 0; q < Q; ++q) b = fma_t(-(T)R[q * C + c], mu[q], b);
               cv[c] = b;
             }
 #pragma unroll
-            for (int k = 0; k < Q * C; ++k) cv[C + k] = R[k];
+            for (int k = 0; k < Q * C; ++k) cv[C + k] = (T)R[k];
           }
         }
       }
@@ -636,7 +671,7 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
           __syncthreads();
           reconstruct<Q, C>(T1 + tid, active, gq, inv, a.out + off, pl);
         } else {
-          average_and_reconstruct<Q, C>(
+          average_and_reconstruct<Q, C, LAY.ag>(
               T0, T1, tout, r, a.hchunk_a, active, gq, inv, a.out + off, pl,
               [&](int f0, int gn, T* dst) {
                 if (tid < ncoef) {
@@ -706,7 +741,7 @@ __global__ void __launch_bounds__(256) apply_point_kernel(LaunchArgs a) {
 // coefficient columns [X0 - r, X0 - r + kThreads) and keep vertical window
 // sums of all F*C coefficient planes; horizontal sums go through LDS.
 template <int Q, int C>
-__global__ void __launch_bounds__(kThreads, 1) apply_avg_kernel(LaunchArgs a) {
+__global__ void __launch_bounds__(kThreads, 2) apply_avg_kernel(LaunchArgs a) {
   using T = solve_t;
   constexpr int FC = Dims<Q, C>::FC;
   constexpr WalkLayout LAY = walk_layout(Q, C, K_APPLY_AVG);
@@ -730,13 +765,29 @@ __global__ void __launch_bounds__(kThreads, 1) apply_avg_kernel(LaunchArgs a) {
   T Va[FC];
 #pragma unroll
   for (int f = 0; f < FC; ++f) Va[f] = T(0);
-  for (int yy = Y0 - r; yy < Y0 + r; ++yy) {
-    if (yy < 0 || yy >= H || !xin) continue;
-    const int64_t off = (int64_t)yy * W + xcol;
+  {
+    // warm-up rows [Y0 - r, Y0 + r), loads issued one row ahead
+    float wb[FC];
+    auto wfetch = [&](int yy) {
+      const bool ok = xin && yy >= 0 && yy < H;
+      const int64_t off = (int64_t)yy * W + xcol;
 #pragma unroll
-    for (int f = 0; f < FC; ++f) Va[f] += (T)a.planes[f * pl + off];
+      for (int f = 0; f < FC; ++f) wb[f] = ok ? a.planes[f * pl + off] : 0.f;
+    };
+    wfetch(Y0 - r);
+    for (int yy = Y0 - r; yy < Y0 + r; ++yy) {
+      float cur[FC];
+#pragma unroll
+      for (int f = 0; f < FC; ++f) cur[f] = wb[f];
+      if (yy + 1 < Y0 + r) wfetch(yy + 1);
+#pragma unroll
+      for (int f = 0; f < FC; ++f) Va[f] += (T)cur[f];
+    }
   }
-  for (int yo = Y0; yo < Y1; ++yo) {
+  // coefficient rows entering (yo + r) and leaving (yo - r - 1) the vertical
+  // window, loaded one step ahead
+  float ca[FC], cs[FC];
+  auto fetch = [&](int yo) {
     const int ya = yo + r;
     const int ys = yo - r - 1;
     const bool oka = xin && ya < H;
@@ -745,10 +796,15 @@ __global__ void __launch_bounds__(kThreads, 1) apply_avg_kernel(LaunchArgs a) {
     const int64_t offs = (int64_t)ys * W + xcol;
 #pragma unroll
     for (int f = 0; f < FC; ++f) {
-      const T add = oka ? (T)a.planes[f * pl + offa] : T(0);
-      const T sub = oks ? (T)a.planes[f * pl + offs] : T(0);
-      Va[f] += add - sub;
+      ca[f] = oka ? a.planes[f * pl + offa] : 0.f;
+      cs[f] = oks ? a.planes[f * pl + offs] : 0.f;
     }
+  };
+  fetch(Y0);
+  for (int yo = Y0; yo < Y1; ++yo) {
+#pragma unroll
+    for (int f = 0; f < FC; ++f) Va[f] += (T)ca[f] - (T)cs[f];
+    if (yo + 1 < Y1) fetch(yo + 1);
     const int xo = X0 + tid;
     const bool active = tid < tout && xo < W;
     const int64_t off = (int64_t)yo * W + (active ? xo : 0);
@@ -762,7 +818,7 @@ __global__ void __launch_bounds__(kThreads, 1) apply_avg_kernel(LaunchArgs a) {
 #pragma unroll
       for (int q = 0; q < Q; ++q) gq[q] = T(0);
     }
-    average_and_reconstruct<Q, C>(T0, T1, tout, r, a.hchunk_a, active, gq, inv, a.out + off, pl,
+    average_and_reconstruct<Q, C, LAY.ag>(T0, T1, tout, r, a.hchunk_a, active, gq, inv, a.out + off, pl,
                                   [&](int f0, int gn, T* dst) {
 #pragma unroll
                                     for (int k = 0; k < gn; ++k)
@@ -795,6 +851,8 @@ hipError_t launch_qc(int kind, const LaunchArgs& a, hipStream_t s) {
       return launch_with_lds(walk_kernel<Q, C, W_FUSED0>, wblocks, walk_lds_bytes(kind, Q, C), a, s);
     case K_FUSED1:
       return launch_with_lds(walk_kernel<Q, C, W_FUSED1>, wblocks, walk_lds_bytes(kind, Q, C), a, s);
+    case K_COEFFS:
+      return launch_with_lds(walk_kernel<Q, C, W_COEFFS>, wblocks, walk_lds_bytes(kind, Q, C), a, s);
     case K_APPLY_AVG:
       return launch_with_lds(apply_avg_kernel<Q, C>, wblocks, walk_lds_bytes(kind, Q, C), a, s);
     case K_SOLVE:

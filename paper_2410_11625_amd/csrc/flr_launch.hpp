@@ -15,8 +15,9 @@ constexpr int kThreads = 256;
 // workgroups over this many CUs (the walker kernels run one workgroup per CU).
 constexpr int kCUs = 256;
 // Numeric types. Products of the FP32 inputs are summed in sum_t; central
-// moments, the solve, the coefficient ring, the coefficient average and the
-// reconstruction run in solve_t. (With packed FP32 unused, an FP64 FMA
+// moments, intercepts, the coefficient average and the reconstruction run in
+// solve_t; the centred, regularised system is factorised and solved in
+// chol_t (it is well conditioned once centred in solve_t). (With packed FP32 unused, an FP64 FMA
 // issues at the same rate as an FP32 one on CDNA4; FP64 costs registers and
 // LDS bytes, not ALU slots.)
 #ifndef FLR_SUM_T
@@ -30,6 +31,11 @@ constexpr int kCUs = 256;
 #ifndef FLR_RING_T
 #define FLR_RING_T float
 #endif
+// Factorisation and triangular solves of the per-pixel system.
+#ifndef FLR_CHOL_T
+#define FLR_CHOL_T float
+#endif
+typedef FLR_CHOL_T chol_t;
 typedef FLR_SUM_T sum_t;
 typedef FLR_SOLVE_T solve_t;
 typedef FLR_RING_T ring_t;
@@ -62,6 +68,7 @@ enum Kind : int {
   K_APPLY_AVG = 3,    // coefficient planes -> window average -> output
   K_FUSED0 = 4,       // moments -> solve -> apply, no averaging, one kernel
   K_FUSED1 = 5,       // moments -> solve -> average -> apply, one kernel
+  K_COEFFS = 6,       // moments -> solve -> coefficient planes, one kernel
 };
 
 struct LaunchArgs {
@@ -90,11 +97,16 @@ inline int strip_out_cols(int kind, int r) {
 
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
+// Workgroups of a walker kernel resident per CU (LDS and registers allow two
+// for the coefficient-averaging walker, one for the others).
+inline int workgroups_per_cu(int kind) { return kind == K_APPLY_AVG ? 2 : 1; }
+
 // Rows of coefficient halo a walker recomputes above and below its segment.
 inline int row_halo(int kind, int r) { return kind == K_FUSED1 ? r : 0; }
 
 // Pick tiles and segments. With tile_rows > 0 the caller fixes the segment
 // length; otherwise minimise (workgroup waves) x (rows walked per segment).
+// K_MOMENTS, K_FUSED0, K_COEFFS and K_APPLY_AVG have no coefficient-row halo.
 inline void plan_walk(int kind, int H, int W, int r, int tile_rows, int* tiles_x, int* n_seg,
                       int* seg_rows) {
   const int tout = strip_out_cols(kind, r);
@@ -105,6 +117,7 @@ inline void plan_walk(int kind, int H, int W, int r, int tile_rows, int* tiles_x
     return;
   }
   const int hc = row_halo(kind, r);
+  const int per_cu = workgroups_per_cu(kind);
   double best = 1e300;
   int best_n = 1;
   const int nmax = H < 4096 ? H : 4096;
@@ -112,7 +125,7 @@ inline void plan_walk(int kind, int H, int W, int r, int tile_rows, int* tiles_x
     const int R = ceil_div(H, n);
     if (n > 1 && ceil_div(H, n - 1) == R) continue;
     const int wgs = *tiles_x * n;
-    const double waves = (double)ceil_div(wgs, kCUs);
+    const double waves = (double)ceil_div(wgs, kCUs * per_cu);
     // rows solved per segment plus a share for the moment warm-up rows
     const double cost = waves * ((double)R + 2.0 * hc + 0.5 * r) + 1e-3 * n;
     if (cost < best) {
@@ -125,14 +138,15 @@ inline void plan_walk(int kind, int H, int W, int r, int tile_rows, int* tiles_x
 }
 
 // Chunk length for the LDS horizontal pass over `rows` channel rows and
-// `nout` outputs: minimise (task passes) x (window taps + 2 per output).
+// `nout` outputs: minimise (task passes) x (window taps + 2 per output). A
+// pass runs two tasks per thread side by side, so its latency is that of one.
 inline int plan_chunk(int rows, int nout, int r) {
   int best = nout;
   double bestc = 1e300;
   for (int nch = 1; nch <= nout; ++nch) {
     const int chunk = ceil_div(nout, nch);
     if (nch > 1 && ceil_div(nout, nch - 1) == chunk) continue;
-    const int passes = ceil_div(rows * ceil_div(nout, chunk), kThreads);
+    const int passes = ceil_div(rows * ceil_div(nout, chunk), 2 * kThreads);
     const double cost = passes * (2.0 * r + 1 + 2.0 * (chunk - 1));
     if (cost < bestc) {
       bestc = cost;
@@ -164,7 +178,10 @@ __host__ __device__ constexpr WalkLayout walk_layout(int Q, int C, int kind) {
   const int row_t = kLdsStride * (int)sizeof(solve_t);
   WalkLayout L{0, 0, false, 0, 0, 0};
   if (kind == K_APPLY_AVG) {
-    L.ag = group_size(fc, sizeof(solve_t));
+    // two workgroups per CU: at most half the LDS each
+    const int ag_max = (kLdsBytes / 2) / (2 * row_t);
+    const int ng = (fc + ag_max - 1) / ag_max;
+    L.ag = (fc + ng - 1) / ng;
     L.a = L.b = (size_t)L.ag * row_t;
     return L;
   }

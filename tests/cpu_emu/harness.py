@@ -174,6 +174,11 @@ def run_case(spec: dict) -> dict:
                                                     tile_rows=tr))
             den = np.maximum(np.abs(want), 1e-3 * scale)
             res["fused_rel"] = float(np.max(np.abs(got - want) / den))
+        if kind in ("two_pass", "both"):
+            got = emu.denoise(noisy, guides, params(H, W, Q, C, r, eps, mode, em, avg, 2,
+                                                    tile_rows=tr))
+            den = np.maximum(np.abs(want), 1e-3 * scale)
+            res["two_pass_rel"] = float(np.max(np.abs(got - want) / den))
         if kind in ("unfused", "both"):
             got = emu.denoise(noisy, guides, params(H, W, Q, C, r, eps, mode, em, avg, 0,
                                                     tile_rows=tr))

@@ -59,7 +59,7 @@ def test_plane_counts(L):
     ("num_guides", 0, 5), ("num_guides", 13, 5), ("num_channels", 0, 5), ("num_channels", 5, 5),
     ("radius", -1, 3), ("radius", 33, 3),
     ("eps", -1e-3, 4), ("eps", float("nan"), 4), ("eps", float("inf"), 4), ("eps_mul", -1.0, 4),
-    ("reg_mode", 2, 9), ("average_coeffs", 2, 9), ("fused", -1, 9), ("flags", 8, 9),
+    ("reg_mode", 2, 9), ("average_coeffs", 2, 9), ("fused", -1, 9), ("fused", 3, 9), ("flags", 8, 9),
     ("tile_rows", -2, 2),
 ])
 def test_validation_codes(L, field, value, status):
@@ -110,6 +110,9 @@ def test_workspace_sizes(L):
     assert L.flr_denoise_workspace_bytes(ctypes.byref(pu)) == (mb + 255) // 256 * 256 + FC * H * W * 4
     pf1 = _params()
     assert L.flr_denoise_workspace_bytes(ctypes.byref(pf1)) > 0
+    p2 = _params(fused=2)
+    assert L.flr_denoise_workspace_bytes(ctypes.byref(p2)) == FC * H * W * 4
+    assert L.flr_denoise_workspace_bytes(ctypes.byref(_params(fused=2, average_coeffs=0))) == 0
     assert L.flr_denoise_workspace_bytes(ctypes.byref(_params(radius=-1))) == 0
 
 

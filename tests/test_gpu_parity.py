@@ -80,13 +80,16 @@ def cfg1_crop():
     return fr
 
 
-@pytest.mark.parametrize("fused", [True, False])
+PATHS = ["fused", "two_pass", "stages"]
+
+
+@pytest.mark.parametrize("fused", PATHS)
 def test_config0_full_frame(cfg0, fused):
     got = gpu_denoise(cfg0, 8, 1e-3, fused=fused)
     assert rel_err(got, cfg0["ref"]) <= TOL
 
 
-@pytest.mark.parametrize("fused", [True, False])
+@pytest.mark.parametrize("fused", PATHS)
 @pytest.mark.parametrize("tile_rows", [0, 7, 33])
 def test_config1_crop(cfg1_crop, fused, tile_rows):
     got = gpu_denoise(cfg1_crop, 8, 1e-3, fused=fused, tile_rows=tile_rows)
@@ -124,7 +127,7 @@ def test_config1_stages(cfg1_crop):
 def test_shapes_guides_channels(H, W, Q, C, r, average):
     fr = random_frame(H, W, Q, C, seed=H * 7 + W + Q, smooth=1.5)
     want = ref.flr_reference(fr["noisy"], fr["guides"], r, 1e-3, average=average)
-    for fused in (True, False):
+    for fused in PATHS:
         got = gpu_denoise(fr, r, 1e-3, average=average, fused=fused)
         assert rel_err(got, want) <= TOL, (fused,)
 
@@ -133,7 +136,7 @@ def test_shapes_guides_channels(H, W, Q, C, r, average):
 def test_paper_regulariser(eps, eps_mul):
     fr = random_frame(45, 300, 4, 3, seed=5, smooth=2.0, offset=1.5)
     want = ref.flr_reference(fr["noisy"], fr["guides"], 4, eps, "paper", eps_mul=eps_mul)
-    for fused in (True, False):
+    for fused in PATHS:
         got = gpu_denoise(fr, 4, eps, mode="paper", eps_mul=eps_mul, fused=fused)
         assert rel_err(got, want) <= TOL
 
@@ -148,7 +151,7 @@ def cfg1_full():
     return make_config(1)
 
 
-@pytest.mark.parametrize("fused", [True, False])
+@pytest.mark.parametrize("fused", PATHS)
 def test_config1_full_frame_sampled_blocks(cfg1_full, fused):
     fr = cfg1_full
     got = gpu_denoise(fr, 8, 1e-3, fused=fused)
