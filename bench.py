@@ -2,16 +2,20 @@
 """Benchmark of the FLR hot path on one MI355X.
 
 Workload: one 1920x1080 RGB frame per step (8 guides + the implied constant,
-window radius 8, regulariser 1e-3, coefficients window-averaged), the whole
-path fused into one kernel launch through the C ABI. Inputs are seeded
-synthetic frames resident in HBM before timing starts; several distinct
-input/output buffer sets (more than the 256 MB Infinity Cache in total) are
-used in rotation so that repeated steps cannot be served from that cache.
+window radius 8, regulariser 1e-3, coefficients window-averaged) through the
+C ABI. Inputs are seeded synthetic frames resident in HBM before timing
+starts; several distinct input/output buffer sets (more than the 256 MB
+Infinity Cache in total) are used in rotation so that repeated steps cannot
+be served from that cache.
+
+Paths: ``two_pass`` (default; flr_coefficients then flr_apply, the fastest),
+``fused`` (one kernel) and ``stages`` (flr_moments, flr_solve, flr_apply).
 
 Prints one JSON line. Besides throughput it reports the dominant kernel's
-roofline figures (algorithmic FP64 flops per launch over the launch's
-average duration from HIP events recorded on the launch stream) and the
-FP64 CPU oracle timed on a bounded sample of the same workload.
+roofline figures (its algorithmic FP64 flops over its average duration from
+HIP events recorded on the launch stream) and the FP64 CPU oracle timed on a
+bounded sample of the same workload. ``--copy-calibration`` also runs a
+plain device copy of known size, the reference for the HBM byte counters.
 """
 from __future__ import annotations
 
@@ -30,27 +34,34 @@ sys.path.insert(0, ROOT)
 H, W, Q, C, R, EPS = 1080, 1920, 8, 3, 8, 1e-3
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (= 256 CU x 64 lanes x 2 x 2.4 GHz)
 PEAK_HBM_GBPS = 8000.0       # MI355X HBM3E
-ALGO_BYTES_PER_PX = 4 * (Q + C) + 4 * C   # read guides + noisy, write output: 56 B
+COPY_BYTES = 1 << 30         # calibration copy: 1 GiB read + 1 GiB written
 
 
-def algo_flops_per_px(Q: int, C: int) -> int:
-    """Algorithmic flops per output pixel (FMA = 2), excluding halo recompute.
-
-    Counted term by term for one pixel of the fused path; the derivation is
-    written out next to the roofline in the design notes.
-    """
+def flops_terms(Q: int, C: int) -> dict:
+    """Algorithmic flops per output pixel (FMA = 2) of each step, excluding
+    halo recomputation. Mirrors the derivation in the design notes."""
     NP = Q * (Q + 1) // 2
     NS = Q + C + NP + Q * C
     FC = (Q + 1) * C
-    moments = 4 * (NP + Q * C) + 2 * (Q + C) + 2 * NS       # vertical slide of products, horizontal slide
-    centre = (Q + C) + 3 * (NP + Q * C)                      # means, covariances
-    regul = Q
-    chol = 2 * sum(j * (Q - j) for j in range(Q)) + Q * (Q - 1) // 2 + Q   # FMAs, scalings, rsqrt
-    subst = 2 * (2 * (Q * (Q - 1) // 2) * C) + 2 * Q * C     # two triangular solves, C RHS
-    bias = 2 * Q * C
-    average = 4 * FC + C                                     # vertical + horizontal slide, scale
-    recon = 2 * Q * C + C
-    return moments + centre + regul + chol + subst + bias + average + recon
+    return {
+        "moments": 4 * (NP + Q * C) + 2 * (Q + C) + 2 * NS,   # vertical and horizontal slides
+        "centre": (Q + C) + 3 * (NP + Q * C),
+        "regularise": Q,
+        "cholesky": 2 * sum(j * (Q - j) for j in range(Q)) + Q * (Q - 1) // 2 + Q,
+        "substitution": 2 * (2 * (Q * (Q - 1) // 2) * C) + 2 * Q * C,
+        "intercept": 2 * Q * C,
+        "average": 4 * FC + C,
+        "reconstruct": 2 * Q * C + C,
+    }
+
+
+def algo_flops_per_px(Q: int, C: int, part: str = "all") -> int:
+    t = flops_terms(Q, C)
+    if part == "coefficients":
+        return sum(v for k, v in t.items() if k not in ("average", "reconstruct"))
+    if part == "apply":
+        return t["average"] + t["reconstruct"]
+    return sum(t.values())
 
 
 def kernel_source_digest() -> str:
@@ -61,14 +72,14 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "flr_fused_1080p_rgb_q8_counters.json")
-    if not os.path.exists(path):
+def load_traffic(path_name: str):
+    """HBM bytes per launch of the dominant kernel, from the committed
+    rocprofv3 counter summary, if it was taken on the current sources."""
+    f = os.path.join(ROOT, "profiles", f"flr_{path_name}_1080p_rgb_q8_counters.json")
+    if not os.path.exists(f):
         return None
     try:
-        d = json.load(open(path))
+        d = json.load(open(f))
     except Exception:
         return None
     if d.get("kernel_source_digest") != kernel_source_digest():
@@ -117,9 +128,11 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--path", default="fused", choices=["fused", "two_pass", "stages"],
+    ap.add_argument("--path", default="two_pass", choices=["two_pass", "fused", "stages"],
                     help="flr_denoise execution path to time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (HBM counter reference)")
     ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args(argv)
 
@@ -149,52 +162,83 @@ def main(argv=None):
     nsets = max(4, -(-300_000_000 // per_set))
     sets = []
     for s in range(nsets):
-        fr = make_config(1, seed=1 + 1000 * s) if s < 2 else None
-        if fr is None:   # remaining sets: permuted copies (distinct memory, same statistics)
+        if s < 2:
+            fr = make_config(1, seed=1 + 1000 * s)
+            sets.append((torch.from_numpy(fr["noisy"]).to(dev),
+                         torch.from_numpy(fr["guides"]).to(dev),
+                         torch.empty((C, H, W), dtype=torch.float32, device=dev)))
+        else:  # further sets: shifted copies (distinct memory, same statistics)
             base = sets[s % 2]
             sets.append((base[0].roll(s, dims=2).contiguous(), base[1].roll(s, dims=2).contiguous(),
                          torch.empty((C, H, W), dtype=torch.float32, device=dev)))
-            continue
-        sets.append((torch.from_numpy(fr["noisy"]).to(dev), torch.from_numpy(fr["guides"]).to(dev),
-                     torch.empty((C, H, W), dtype=torch.float32, device=dev)))
-    fused = args.path
-    p = flr.make_params(H, W, Q, C, R, eps=EPS, average=True, fused=fused)
-    ws_bytes = flr.workspace_bytes(p)
-    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    path = args.path
+    p = flr.make_params(H, W, Q, C, R, eps=EPS, average=True, fused=path)
+    ws = torch.empty(max(flr.workspace_bytes(p), 1), dtype=torch.uint8, device=dev)
+    coeffs = torch.empty((flr.num_coeff_planes(Q, C), H, W), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
 
-    def step(k):
+    # One step = one frame through the whole path. For two_pass the two
+    # kernels are timed separately (event between the launches).
+    def step(k, evs=None):
         noisy, guides, out = sets[k % nsets]
-        flr.denoise(noisy, guides, radius=R, eps=EPS, average=True, fused=fused, out=out,
-                    workspace=ws)
+        if evs is not None:
+            evs[0].record(stream)
+        if path == "two_pass":
+            flr.coefficients(guides, noisy, R, eps=EPS, out=coeffs)
+            if evs is not None:
+                evs[1].record(stream)
+            flr.apply(guides, coeffs, R, average=True, out=out)
+        else:
+            flr.denoise(noisy, guides, radius=R, eps=EPS, average=True, fused=path, out=out,
+                        workspace=ws)
+            if evs is not None:
+                evs[1].record(stream)
+        if evs is not None:
+            evs[2].record(stream)
 
     for k in range(args.warmup):
         step(k)
     torch.cuda.synchronize()
 
-    stream = torch.cuda.current_stream(dev)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
+    ev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(args.steps)]
     t_all0 = torch.cuda.Event(enable_timing=True)
     t_all1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_all0.record(stream)
     for k in range(args.steps):
-        ev[k][0].record(stream)
-        step(k)
-        ev[k][1].record(stream)
+        step(k, ev[k])
     t_all1.record(stream)
     torch.cuda.synchronize()
     total_ms = t_all0.elapsed_time(t_all1)
-    per = np.array([a.elapsed_time(b) for a, b in ev])
+    per = np.array([a.elapsed_time(c) for a, b, c in ev])
+    first = np.array([a.elapsed_time(b) for a, b, c in ev])
     ms_per_step = total_ms / args.steps
-
     pix = H * W
-    mpix_s = pix / (ms_per_step / 1e3) / 1e6
-    kern_ms = float(np.mean(per))
-    flops = algo_flops_per_px(Q, C) * pix
-    achieved_tflops = flops / (kern_ms / 1e3) / 1e12
-    hbm_gbps = ALGO_BYTES_PER_PX * pix / (kern_ms / 1e3) / 1e9
-    traffic = load_traffic()
+
+    # dominant kernel: the coefficient kernel for two_pass, the whole launch
+    # sequence (one kernel) for fused, the whole path for stages
+    if path == "two_pass":
+        dom_ms = float(np.mean(first))
+        dom_flops = algo_flops_per_px(Q, C, "coefficients") * pix
+        dom_bytes = (4 * (Q + C) + 4 * (Q + 1) * C) * pix
+        dom_name = "flr_coefficients (walk_kernel<8,3,W_COEFFS>)"
+        second_ms = float(np.mean(per - first))
+    else:
+        dom_ms = float(np.mean(per))
+        dom_flops = algo_flops_per_px(Q, C) * pix
+        dom_bytes = (4 * (Q + C) + 4 * C) * pix
+        dom_name = "fused walk_kernel<8,3,W_FUSED1>" if path == "fused" else "three-stage path"
+        second_ms = None
+    achieved = dom_flops / (dom_ms / 1e3) / 1e12
+    hbm_gbps = dom_bytes / (dom_ms / 1e3) / 1e9
+
+    if args.copy_calibration:
+        src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
 
     # parity of the timed launches' output against the oracle on sampled blocks
     from oracle import flr_ref
@@ -210,7 +254,7 @@ def main(argv=None):
     cpu = None if args.no_cpu_baseline else cpu_baseline()
     line = {
         "metric": "Mpixel/s at 1080p (FLR), ms/frame, % roofline, err vs FP64",
-        "value": round(mpix_s, 2),
+        "value": round(pix / (ms_per_step / 1e3) / 1e6, 2),
         "unit": "Mpixel/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -225,16 +269,20 @@ def main(argv=None):
                                "eps 1e-3, ridge, window-averaged coefficients",
                    "path": {"fused": "fused (one kernel)",
                             "two_pass": "two kernels (moments+solve, average+reconstruct)",
-                            "stages": "three stages (moments, solve, apply)"}[fused],
-                   "io_dtype": "f32", "accumulate_dtype": "f64", "buffer_sets": nsets,
+                            "stages": "three stages (moments, solve, apply)"}[path],
+                   "io_dtype": "f32", "accumulate_dtype": "f64 sums/centring, f32 factorisation",
+                   "buffer_sets": nsets,
                    "ms_per_frame_p10_p50_p90": [round(float(np.percentile(per, q)), 5)
                                                 for q in (10, 50, 90)],
+                   "second_kernel_ms": None if second_ms is None else round(second_ms, 5),
                    "max_rel_err_vs_fp64_sampled": max(errs)},
-        "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3),
-                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved_tflops / PEAK_FP64_TFLOPS, 4),
-                     "traffic": traffic,
-                     "algo_flops_per_px": algo_flops_per_px(Q, C),
+        "roofline": {"bound": "alu", "kernel": dom_name,
+                     "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                     "traffic": load_traffic(path),
+                     "kernel_ms": round(dom_ms, 5),
+                     "algo_flops_per_launch": dom_flops,
+                     "algo_hbm_bytes_per_launch": dom_bytes,
                      "hbm_algo_GBps": round(hbm_gbps, 1),
                      "hbm_frac": round(hbm_gbps / PEAK_HBM_GBPS, 4)},
         "cpu_baseline": cpu,

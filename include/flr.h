@@ -13,6 +13,7 @@
  *                X_k^T Y_k exactly), returned as central moments;
  *   flr_solve    the regularised small SPD solve per pixel (Eq. closed_form
  *                with Eq. tikhonov, or the Appendix normalisation);
+ *   flr_coefficients  the two above in one pass, without the moment image;
  *   flr_apply    optional window-average of the coefficients, then the
  *                reconstruction I_k = x_k A_k (Sec. 3.1);
  *   flr_denoise  all of the above: in one fused kernel, in two kernels
@@ -144,6 +145,13 @@ flr_status flr_moments(const flr_params* p, const float* guides, const float* no
  * Reads central moments [M][H][W] as written by flr_moments; writes coeffs
  * [F*C][H][W] in original units. Uses reg_mode, eps, eps_mul. */
 flr_status flr_solve(const flr_params* p, const float* moments, float* coeffs, void* stream);
+
+/* Moments and solve in one pass (no moment image): writes the coefficient
+ * planes [F*C][H][W] in original units, the result of flr_moments followed
+ * by flr_solve, with the window sums and the solve kept in FP64/FP32 on chip.
+ * Uses radius, reg_mode, eps, eps_mul, tile_rows. */
+flr_status flr_coefficients(const flr_params* p, const float* guides, const float* noisy,
+                            float* coeffs, void* stream);
 
 /* Window-average of the coefficients if p->average_coeffs (same clipped
  * window as the moments), then reconstruction out_c = b_c + sum_q g_q a_qc

@@ -5,8 +5,8 @@ Regression for Low-Cost, Path Traced Lambertian Global Illumination"
 (Sec. 3.1-3.2 and the Appendix), as hand-written HIP kernels behind the C ABI
 in ``include/flr.h``. This package is the thin Python binding.
 """
-from .api import (FLRError, apply, denoise, make_params, moments, num_coeff_planes,
-                  num_moment_planes, solve, workspace_bytes)
+from .api import (PATHS, FLRError, apply, coefficients, denoise, make_params, moments,
+                  num_coeff_planes, num_moment_planes, solve, workspace_bytes)
 
-__all__ = ["FLRError", "apply", "denoise", "make_params", "moments", "num_coeff_planes",
-           "num_moment_planes", "solve", "workspace_bytes"]
+__all__ = ["PATHS", "FLRError", "apply", "coefficients", "denoise", "make_params", "moments",
+           "num_coeff_planes", "num_moment_planes", "solve", "workspace_bytes"]

@@ -28,8 +28,8 @@ STATUS_NAMES = {
 
 # Every symbol include/flr.h declares.
 EXPORTED = ("flr_num_moment_planes", "flr_num_coeff_planes", "flr_denoise_workspace_bytes",
-            "flr_moments", "flr_solve", "flr_apply", "flr_denoise", "flr_status_str",
-            "flr_validate_params")
+            "flr_moments", "flr_solve", "flr_coefficients", "flr_apply", "flr_denoise",
+            "flr_status_str", "flr_validate_params")
 
 
 class FlrParams(ctypes.Structure):
@@ -83,6 +83,8 @@ def lib() -> ctypes.CDLL:
     L.flr_moments.restype = ctypes.c_int
     L.flr_solve.argtypes = [P, vp, vp, vp]
     L.flr_solve.restype = ctypes.c_int
+    L.flr_coefficients.argtypes = [P, vp, vp, vp, vp]
+    L.flr_coefficients.restype = ctypes.c_int
     L.flr_apply.argtypes = [P, vp, vp, vp, vp]
     L.flr_apply.restype = ctypes.c_int
     L.flr_denoise.argtypes = [P, vp, vp, vp, vp, ctypes.c_size_t, vp]

@@ -105,6 +105,24 @@ def solve(moment_planes: torch.Tensor, num_guides: int, num_channels: int, eps: 
     return out
 
 
+def coefficients(guides: torch.Tensor, noisy: torch.Tensor, radius: int, eps: float = 1e-3,
+                 mode: str = "ridge", eps_mul: float = 0.0, tile_rows: int = 0,
+                 out: torch.Tensor | None = None) -> torch.Tensor:
+    """Moments and solve in one pass -> coefficient planes [(Q+1)*C,H,W]."""
+    _need(guides, "guides")
+    _need(noisy, "noisy")
+    Q, H, W = guides.shape
+    C = noisy.shape[0]
+    p = make_params(H, W, Q, C, radius, eps=eps, mode=mode, eps_mul=eps_mul, tile_rows=tile_rows)
+    if out is None:
+        out = torch.empty((num_coeff_planes(Q, C), H, W), dtype=torch.float32,
+                          device=guides.device)
+    _need(out, "out")
+    check(lib().flr_coefficients(ctypes.byref(p), guides.data_ptr(), noisy.data_ptr(),
+                                 out.data_ptr(), _stream(guides)), "flr_coefficients")
+    return out
+
+
 def apply(guides: torch.Tensor, coeffs: torch.Tensor, radius: int, average: bool = True,
           tile_rows: int = 0, out: torch.Tensor | None = None) -> torch.Tensor:
     """Optional window-average of the coefficients, then reconstruction -> [C,H,W]."""
@@ -154,5 +172,5 @@ def denoise(noisy: torch.Tensor, guides: torch.Tensor, radius: int = 8, eps: flo
     return out
 
 
-__all__ = ["FLRError", "make_params", "num_moment_planes", "num_coeff_planes", "workspace_bytes",
-           "moments", "solve", "apply", "denoise"]
+__all__ = ["FLRError", "PATHS", "make_params", "num_moment_planes", "num_coeff_planes",
+           "workspace_bytes", "moments", "solve", "coefficients", "apply", "denoise"]

@@ -165,6 +165,25 @@ flr_status flr_solve(const flr_params* p, const float* moments, float* coeffs, v
   return dispatch(p->num_guides, p->num_channels, flr::K_SOLVE, a, stream);
 }
 
+flr_status flr_coefficients(const flr_params* p, const float* guides, const float* noisy,
+                            float* coeffs, void* stream) {
+  flr_status st = flr_validate_params(p);
+  if (st != FLR_OK) return st;
+  if ((st = check_ptrs({guides, noisy, coeffs})) != FLR_OK) return st;
+  if (p->flags & FLR_FLAG_RAW_MOMENTS) return FLR_ERR_MODE;
+  const size_t pb = plane_bytes(p);
+  const size_t cb = flr_num_coeff_planes(p->num_guides, p->num_channels) * pb;
+  if (overlaps(coeffs, cb, guides, p->num_guides * pb) ||
+      overlaps(coeffs, cb, noisy, p->num_channels * pb))
+    return FLR_ERR_ALIAS;
+  LaunchArgs a = base_args(p);
+  a.guides = guides;
+  a.noisy = noisy;
+  a.out = coeffs;
+  plan(p, flr::K_COEFFS, &a);
+  return dispatch(p->num_guides, p->num_channels, flr::K_COEFFS, a, stream);
+}
+
 flr_status flr_apply(const flr_params* p, const float* guides, const float* coeffs, float* out,
                      void* stream) {
   flr_status st = flr_validate_params(p);
@@ -206,13 +225,9 @@ flr_status flr_denoise(const flr_params* p, const float* guides, const float* no
   }
   const int Q = p->num_guides, C = p->num_channels;
   if (p->fused == FLR_PATH_TWO_PASS && p->average_coeffs) {
-    LaunchArgs a = base_args(p);
-    a.guides = guides;
-    a.noisy = noisy;
-    a.out = static_cast<float*>(workspace);
-    plan(p, flr::K_COEFFS, &a);
-    if ((st = dispatch(Q, C, flr::K_COEFFS, a, stream)) != FLR_OK) return st;
-    return flr_apply(p, guides, static_cast<const float*>(workspace), out, stream);
+    float* coeffs = static_cast<float*>(workspace);
+    if ((st = flr_coefficients(p, guides, noisy, coeffs, stream)) != FLR_OK) return st;
+    return flr_apply(p, guides, coeffs, out, stream);
   }
   if (p->fused) {
     LaunchArgs a = base_args(p);

@@ -198,3 +198,22 @@ def test_api_rejects_cpu_tensors():
     fr = random_frame(8, 8, 2, 1, seed=0)
     with pytest.raises(ValueError):
         flr.denoise(torch.from_numpy(fr["noisy"]), torch.from_numpy(fr["guides"]))
+
+
+def test_coefficients_entry_point(cfg1_crop):
+    """flr_coefficients = moments + solve in one pass; with flr_apply it is the two-pass path."""
+    fr = cfg1_crop
+    g, y = _t(fr["guides"]), _t(fr["noisy"])
+    co = flr.coefficients(g, y, 8, eps=1e-3)
+    out = flr.apply(g, co, 8, average=True)
+    torch.cuda.synchronize()
+    two = gpu_denoise(fr, 8, 1e-3, fused="two_pass")
+    assert np.array_equal(out.cpu().numpy(), two)
+    _, A = ref.flr_reference(fr["noisy"], fr["guides"], 8, 1e-3, return_coeffs=True)
+    cref = ref.coefficient_planes(A)
+    got = co.cpu().numpy()
+    # coefficients in original units: b carries the cancelling intercepts, so
+    # each plane is judged on its own scale
+    for k in range(cref.shape[0]):
+        scale = np.max(np.abs(cref[k])) + 1e-30
+        assert np.max(np.abs(got[k] - cref[k])) / scale < 1e-4, k
