@@ -225,6 +225,74 @@ __device__ __forceinline__ void hbox(const E* __restrict__ src, E* __restrict__ 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Horizontal window sums by segmented prefix sums. Lane l holds the value x_l
+// of its column. An inclusive prefix over aligned segments of L lanes (L = 16,
+// one DPP row, when 2r <= 16; else L = 64, the wavefront) is formed in
+// registers with DPP lane moves, log2(L) add steps, and staged through LDS
+// once. A window [j, j + 2r] with 2r <= L touches at most two segments, so its
+// sum is P[j + 2r] - P[j - 1] + (P[end of j's segment] if it crosses), with
+// P[j - 1] dropped when j starts a segment: three independent LDS reads in
+// place of a serial slide. Segments never cross a wavefront.
+
+// DPP control codes (GFX9 encoding): row_shr:k, row_bcast:15, row_bcast:31.
+constexpr int kDppRowShr = 0x110;
+constexpr int kDppRowBcast15 = 0x142;
+constexpr int kDppRowBcast31 = 0x143;
+
+// x of the DPP source lane (0 where the source is outside the row, or the
+// lane's row is masked off), 64-bit values as two 32-bit moves.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, ROW_MASK, 0xf, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_move(float x) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, true));
+}
+
+// Inclusive prefix of x over its 16-lane row, or over the wavefront (WIDE).
+// Every lane of the wavefront must take part.
+template <bool WIDE, typename E>
+__device__ __forceinline__ E seg_prefix(E x) {
+  x += dpp_move<kDppRowShr + 1, 0xf>(x);
+  x += dpp_move<kDppRowShr + 2, 0xf>(x);
+  x += dpp_move<kDppRowShr + 4, 0xf>(x);
+  x += dpp_move<kDppRowShr + 8, 0xf>(x);
+  if (WIDE) {
+    x += dpp_move<kDppRowBcast15, 0xa>(x);  // row totals 0 -> 1, 2 -> 3
+    x += dpp_move<kDppRowBcast31, 0xc>(x);  // rows 0..1 total -> 2, 3
+  }
+  return x;
+}
+
+// Prefix segments of 16 lanes serve windows up to 2r + 1 = 17 columns wide.
+__host__ __device__ constexpr bool wide_segments(int r) { return r > 8; }
+
+// LDS columns whose prefixes give the sum of window [j, j + 2r]:
+// P[ib] - P[ia] + P[it]. Terms that do not apply point at the row's pad
+// column kThreads, which holds zero.
+struct HWin {
+  int ib, ia, it;
+};
+template <bool WIDE>
+__device__ __forceinline__ HWin hwin(int j, int r) {
+  constexpr int lm = WIDE ? 63 : 15;
+  HWin h;
+  h.ib = min(j + 2 * r, kThreads - 1);
+  h.ia = (j & lm) != 0 ? j - 1 : kThreads;
+  h.it = (h.ib & ~lm) != (j & ~lm) ? (j | lm) : kThreads;
+  return h;
+}
+template <typename E>
+__device__ __forceinline__ E hwin_sum(const E* row, const HWin& h) {
+  return (row[h.ib] - row[h.ia]) + row[h.it];
+}
+
 // Raw FP32 guides and noisy values of one pixel (zeros outside the image),
 // and their conversion to the shifted sum type. Split so that the loads for
 // the next row can be issued a whole iteration before they are consumed.
@@ -279,35 +347,35 @@ __device__ __forceinline__ void vupdate(sum_t (&V)[num_sums(Q, C)], const sum_t 
   }
 }
 
-// Fold the window sums of channels [g0, g0 + gn) (one LDS group; column
-// base pointer `col`, row stride kLdsStride) into the central moments: mu~,
-// nu, the guide covariance Hm and the guide/channel covariance R. Channel
-// order: sum g | sum y | sum g_p g_q (p <= q) | sum g_q y_c (shifted guides).
-// Groups arrive in increasing order and the first holds all Q + C first
-// moments, so the means are complete before any covariance needs them. All
-// loops unroll and every group test folds at compile time.
+// Fold the window sums of channels [g0, g0 + gn) (one LDS group of segment
+// prefixes, row stride kLdsStride, read through `h`) into the central
+// moments: mu~, nu, the guide covariance Hm and the guide/channel covariance
+// R. Channel order: sum g | sum y | sum g_p g_q (p <= q) | sum g_q y_c
+// (shifted guides). Groups arrive in increasing order and the first holds all
+// Q + C first moments, so the means are complete before any covariance needs
+// them. All loops unroll and every group test folds at compile time.
 template <int Q, int C, typename T, typename U>
-__device__ __forceinline__ void centre_group(int g0, int gn, const sum_t* col, T inv_n, T (&mu)[Q],
-                                             T (&nu)[C], U (&Hm)[Q * (Q + 1) / 2],
-                                             U (&R)[Q * C]) {
+__device__ __forceinline__ void centre_group(int g0, int gn, const sum_t* P, const HWin& h,
+                                             T inv_n, T (&mu)[Q], T (&nu)[C],
+                                             U (&Hm)[Q * (Q + 1) / 2], U (&R)[Q * C]) {
   constexpr int NP = Q * (Q + 1) / 2;
+  auto win = [&](int m) { return (T)hwin_sum(P + (m - g0) * kLdsStride, h); };
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int m = q;
-    if (m >= g0 && m < g0 + gn) mu[q] = (T)col[(m - g0) * kLdsStride] * inv_n;
+    if (m >= g0 && m < g0 + gn) mu[q] = win(m) * inv_n;
   }
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const int m = Q + c;
-    if (m >= g0 && m < g0 + gn) nu[c] = (T)col[(m - g0) * kLdsStride] * inv_n;
+    if (m >= g0 && m < g0 + gn) nu[c] = win(m) * inv_n;
   }
 #pragma unroll
   for (int p = 0; p < Q; ++p) {
 #pragma unroll
     for (int q = p; q < Q; ++q) {
       const int m = Q + C + tri<Q>(p, q);
-      if (m >= g0 && m < g0 + gn)
-        Hm[tri<Q>(p, q)] = (U)fma_t((T)col[(m - g0) * kLdsStride], inv_n, -mu[p] * mu[q]);
+      if (m >= g0 && m < g0 + gn) Hm[tri<Q>(p, q)] = (U)fma_t(win(m), inv_n, -mu[p] * mu[q]);
     }
   }
 #pragma unroll
@@ -315,8 +383,7 @@ __device__ __forceinline__ void centre_group(int g0, int gn, const sum_t* col, T
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int m = Q + C + NP + q * C + c;
-      if (m >= g0 && m < g0 + gn)
-        R[q * C + c] = (U)fma_t((T)col[(m - g0) * kLdsStride], inv_n, -mu[q] * nu[c]);
+      if (m >= g0 && m < g0 + gn) R[q * C + c] = (U)fma_t(win(m), inv_n, -mu[q] * nu[c]);
     }
   }
 }
@@ -392,7 +459,7 @@ enum WalkMode : int { W_MOMENTS = 0, W_FUSED0 = 1, W_FUSED1 = 2, W_COEFFS = 3 };
 //              reconstruct with the averaged coefficients. The segment is
 //              extended by r coefficient rows above and below and the strip
 //              by r columns each side, so no data crosses workgroups.
-template <int Q, int C, int MODE>
+template <int Q, int C, int MODE, bool WIDE>
 __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
   using D = Dims<Q, C>;
   using T = solve_t;
@@ -430,6 +497,11 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
   const bool xin = xi >= 0 && xi < W;
   const int xc = X0 - hc + tid;      // coefficient column of this lane (tid < ncoef)
   const bool cvalid = tid < ncoef && xc >= 0 && xc < W;
+  constexpr int NG = (NS + MG - 1) / MG;  // LDS groups of moment channels
+  const HWin hw = hwin<WIDE>(tid, r);
+  // zero pad column of every prefix row of both buffers (no other pass
+  // writes column kThreads; the first group's barrier orders these stores)
+  for (int m = tid; m < 2 * MG; m += kThreads) (m < MG ? S0 : S1)[(m % MG) * kLdsStride + kThreads] = sum_t(0);
 
   float cg[Q];
   {
@@ -536,32 +608,28 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
       // means in solve_t; the centred system (formed in solve_t) in chol_t
       T mu[Q], nu[C];
       chol_t Hm[NP], R[Q * C];
-      // Group g's vertical sums go to LDS in the same barrier interval in
-      // which group g-1's window sums are consumed. (The first write needs no
-      // barrier: the source rows were last read by a horizontal pass that
-      // ended before a barrier of the previous step.)
+      // Groups of channels alternate between the two LDS buffers, so one
+      // barrier per group separates its prefix writes from its window reads
+      // and the reads of the group before last from this group's writes.
+      // With an odd group count the first buffer of a row is the one the
+      // previous row's last group read, hence the extra barrier.
+      if (NG % 2 == 1) __syncthreads();
 #pragma unroll
-      for (int m = 0; m < (MG < NS ? MG : NS); ++m) S0[m * kLdsStride + tid] = V[m];
-#pragma unroll
-      for (int g0 = 0; g0 < NS; g0 += MG) {
+      for (int gi = 0; gi < NG; ++gi) {
+        const int g0 = gi * MG;
         const int gn = NS - g0 < MG ? NS - g0 : MG;
-        __syncthreads();
-        hbox(S0, S1, gn, ncoef, r, a.hchunk_m);
+        sum_t* P = (gi & 1) ? S1 : S0;
+#pragma unroll
+        for (int m = 0; m < gn; ++m) P[m * kLdsStride + tid] = seg_prefix<WIDE>(V[g0 + m]);
         __syncthreads();
         if (cvalid) {
           if (MODE == W_MOMENTS && a.raw) {
 #pragma unroll
             for (int m = 0; m < gn; ++m)
-              a.out[(1 + g0 + m) * pl + off] = (float)S1[m * kLdsStride + tid];
+              a.out[(1 + g0 + m) * pl + off] = (float)hwin_sum(P + m * kLdsStride, hw);
           } else {
-            centre_group<Q, C, T, chol_t>(g0, gn, S1 + tid, inv_n, mu, nu, Hm, R);
+            centre_group<Q, C, T, chol_t>(g0, gn, P, hw, inv_n, mu, nu, Hm, R);
           }
-        }
-        if (g0 + MG < NS) {
-          const int g1 = g0 + MG;
-          const int gn1 = NS - g1 < MG ? NS - g1 : MG;
-#pragma unroll
-          for (int m = 0; m < gn1; ++m) S0[m * kLdsStride + tid] = V[g1 + m];
         }
       }
       if (cvalid) {
@@ -844,17 +912,23 @@ hipError_t launch_qc(int kind, const LaunchArgs& a, hipStream_t s) {
   const int64_t pl = (int64_t)a.H * a.W;
   const int pblocks = (int)((pl + 255) / 256);
   const int wblocks = a.tiles_x * a.n_seg;
+  const bool wide = wide_segments(a.r);
+  const size_t lds = walk_lds_bytes(kind, Q, C);
   switch (kind) {
     case K_MOMENTS:
-      return launch_with_lds(walk_kernel<Q, C, W_MOMENTS>, wblocks, walk_lds_bytes(kind, Q, C), a, s);
+      return wide ? launch_with_lds(walk_kernel<Q, C, W_MOMENTS, true>, wblocks, lds, a, s)
+                  : launch_with_lds(walk_kernel<Q, C, W_MOMENTS, false>, wblocks, lds, a, s);
     case K_FUSED0:
-      return launch_with_lds(walk_kernel<Q, C, W_FUSED0>, wblocks, walk_lds_bytes(kind, Q, C), a, s);
+      return wide ? launch_with_lds(walk_kernel<Q, C, W_FUSED0, true>, wblocks, lds, a, s)
+                  : launch_with_lds(walk_kernel<Q, C, W_FUSED0, false>, wblocks, lds, a, s);
     case K_FUSED1:
-      return launch_with_lds(walk_kernel<Q, C, W_FUSED1>, wblocks, walk_lds_bytes(kind, Q, C), a, s);
+      return wide ? launch_with_lds(walk_kernel<Q, C, W_FUSED1, true>, wblocks, lds, a, s)
+                  : launch_with_lds(walk_kernel<Q, C, W_FUSED1, false>, wblocks, lds, a, s);
     case K_COEFFS:
-      return launch_with_lds(walk_kernel<Q, C, W_COEFFS>, wblocks, walk_lds_bytes(kind, Q, C), a, s);
+      return wide ? launch_with_lds(walk_kernel<Q, C, W_COEFFS, true>, wblocks, lds, a, s)
+                  : launch_with_lds(walk_kernel<Q, C, W_COEFFS, false>, wblocks, lds, a, s);
     case K_APPLY_AVG:
-      return launch_with_lds(apply_avg_kernel<Q, C>, wblocks, walk_lds_bytes(kind, Q, C), a, s);
+      return launch_with_lds(apply_avg_kernel<Q, C>, wblocks, lds, a, s);
     case K_SOLVE:
       hipLaunchKernelGGL((solve_kernel<Q, C>), dim3(pblocks), dim3(256), 0, s, a);
       return hipGetLastError();

@@ -3,19 +3,31 @@
 // the library's own host dispatcher (flr_api.cpp), against the CPU stand-in
 // for the HIP runtime in ./hip/hip_runtime.h. Test infrastructure only.
 //
-// * A workgroup runs as blockDim.x std::threads meeting at a std::barrier.
-// * LDS is one static array; before each workgroup the requested bytes are
-//   filled with NaN (so reads of never-written LDS poison the result) and
-//   the rest with a canary that is checked afterwards.
+// * A workgroup runs on one host thread as blockDim.x user-space fibers
+//   (ucontext), one per lane. __syncthreads() parks a lane until every lane
+//   of the workgroup is parked there; a DPP move parks it until every lane
+//   of its 64-lane wavefront has published its source value. Parking at
+//   different barriers, or finishing while others wait, is reported as a
+//   launch failure instead of hanging.
+// * Workgroups run in parallel on several host threads, each with its own
+//   LDS (a thread_local array). Before each workgroup the requested bytes
+//   are filled with NaN (so reads of never-written LDS poison the result)
+//   and the rest with a canary that is checked afterwards.
+// * Each lane stack sits above a PROT_NONE guard page.
 // * emu_alloc() places each buffer against a PROT_NONE guard page, so an
 //   out-of-bounds global access past the end faults immediately.
 #include <sys/mman.h>
+#include <ucontext.h>
 #include <unistd.h>
 
-#include <barrier>
+#include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -26,11 +38,17 @@ thread_local dim3 blockIdx;
 dim3 blockDim;
 dim3 gridDim;
 
-static std::barrier<>* g_bar = nullptr;
 static hipError_t g_last = hipSuccess;
 static char g_msg[256] = "";
+static std::mutex g_err_mu;
 
-void __syncthreads() { g_bar->arrive_and_wait(); }
+static void set_error(hipError_t e, const char* msg) {
+  std::lock_guard<std::mutex> lk(g_err_mu);
+  if (g_last == hipSuccess) {
+    g_last = e;
+    std::snprintf(g_msg, sizeof g_msg, "%s", msg);
+  }
+}
 
 hipError_t hipGetLastError() {
   const hipError_t e = g_last;
@@ -38,9 +56,140 @@ hipError_t hipGetLastError() {
   return e;
 }
 
+namespace {
+
+constexpr unsigned kWave = 64;
+constexpr size_t kStackBytes = 512 * 1024;
+
+enum LaneState : int { READY, AT_BLOCK_BARRIER, AT_WAVE_BARRIER, DONE };
+
+struct Lane {
+  ucontext_t ctx;
+  LaneState state;
+  unsigned dpp_calls;
+  char* stack;  // kStackBytes above one guard page
+};
+
+// One host thread's workgroup scheduler.
+struct Workgroup {
+  ucontext_t sched;
+  std::vector<Lane> lanes;
+  unsigned cur = 0;
+  int dpp[2][1024];
+  std::function<void()> body;
+
+  Workgroup() : lanes(1024) {
+    const size_t pg = (size_t)sysconf(_SC_PAGESIZE);
+    for (auto& l : lanes) {
+      char* base = static_cast<char*>(mmap(nullptr, kStackBytes + pg, PROT_READ | PROT_WRITE,
+                                           MAP_PRIVATE | MAP_ANONYMOUS, -1, 0));
+      if (base == MAP_FAILED) std::abort();
+      mprotect(base, pg, PROT_NONE);
+      l.stack = base + pg;
+    }
+  }
+  ~Workgroup() {
+    const size_t pg = (size_t)sysconf(_SC_PAGESIZE);
+    for (auto& l : lanes) munmap(l.stack - pg, kStackBytes + pg);
+  }
+
+  void park(LaneState s) {
+    Lane& l = lanes[cur];
+    l.state = s;
+    swapcontext(&l.ctx, &sched);
+  }
+
+  static void entry();
+
+  // Runs `n` lanes of block `b` to completion; false on a barrier mismatch.
+  bool run(unsigned n, unsigned b, char* err, size_t errn) {
+    for (unsigned t = 0; t < n; ++t) {
+      Lane& l = lanes[t];
+      getcontext(&l.ctx);
+      l.ctx.uc_stack.ss_sp = l.stack;
+      l.ctx.uc_stack.ss_size = kStackBytes;
+      l.ctx.uc_link = &sched;
+      makecontext(&l.ctx, entry, 0);
+      l.state = READY;
+      l.dpp_calls = 0;
+    }
+    blockIdx = dim3(b);
+    for (;;) {
+      for (unsigned t = 0; t < n; ++t) {
+        if (lanes[t].state != READY) continue;
+        cur = t;
+        threadIdx = dim3(t);
+        swapcontext(&sched, &lanes[t].ctx);
+      }
+      unsigned done = 0, at_block = 0;
+      bool released = false;
+      for (unsigned w0 = 0; w0 < n; w0 += kWave) {
+        const unsigned w1 = std::min(n, w0 + kWave);
+        unsigned at_wave = 0;
+        for (unsigned t = w0; t < w1; ++t) at_wave += lanes[t].state == AT_WAVE_BARRIER;
+        if (at_wave == w1 - w0) {
+          for (unsigned t = w0; t < w1; ++t) lanes[t].state = READY;
+          released = true;
+        }
+      }
+      if (released) continue;
+      for (unsigned t = 0; t < n; ++t) {
+        done += lanes[t].state == DONE;
+        at_block += lanes[t].state == AT_BLOCK_BARRIER;
+      }
+      if (done == n) return true;
+      if (at_block == n) {
+        for (unsigned t = 0; t < n; ++t) lanes[t].state = READY;
+        continue;
+      }
+      std::snprintf(err, errn,
+                    "block %u: lanes diverged at barriers (%u done, %u at the workgroup barrier)",
+                    b, done, at_block);
+      return false;
+    }
+  }
+};
+
+thread_local Workgroup* t_wg = nullptr;
+
+void Workgroup::entry() {
+  Workgroup* w = t_wg;
+  w->body();
+  w->lanes[w->cur].state = DONE;
+}
+
+}  // namespace
+
+void __syncthreads() { t_wg->park(AT_BLOCK_BARRIER); }
+
+int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask,
+                                bool bound_ctrl) {
+  Workgroup* wg = t_wg;
+  const unsigned t = wg->cur, w = t / kWave, l = t % kWave;
+  const unsigned slot = wg->lanes[t].dpp_calls++ & 1u;
+  wg->dpp[slot][t] = src;
+  wg->park(AT_WAVE_BARRIER);
+  const int row = (int)(l / 16), rl = (int)(l % 16);
+  if (!((row_mask >> row) & 1) || !((bank_mask >> (rl / 4)) & 1)) return old;
+  int s = -1;
+  if (ctrl > 0x110 && ctrl <= 0x11f) {
+    const int k = ctrl - 0x110;
+    s = rl >= k ? (int)l - k : -1;
+  } else if (ctrl == 0x142) {
+    s = row >= 1 ? (row - 1) * 16 + 15 : -1;
+  } else if (ctrl == 0x143) {
+    s = row >= 2 ? 31 : -1;
+  } else {
+    std::fprintf(stderr, "emulator: unsupported DPP control 0x%x\n", ctrl);
+    std::abort();
+  }
+  if (s < 0) return bound_ctrl ? 0 : old;
+  return wg->dpp[slot][w * kWave + (unsigned)s];
+}
+
 namespace flr {
 constexpr size_t kEmuLdsFloats = 163840 / 4 + 4096;
-alignas(64) float lds[kEmuLdsFloats];
+alignas(64) thread_local float lds[kEmuLdsFloats];
 }  // namespace flr
 
 static const uint32_t kCanary = 0x7fc0dead;
@@ -48,37 +197,45 @@ static const uint32_t kCanary = 0x7fc0dead;
 template <typename A>
 void emu_launch_kernel(void (*k)(A), dim3 grid, dim3 block, size_t lds_bytes, hipStream_t, A a) {
   if (lds_bytes > 163840 || block.x == 0 || block.x > 1024) {
-    g_last = hipErrorInvalidValue;
+    set_error(hipErrorInvalidValue, "bad launch shape");
     return;
   }
   blockDim = block;
   gridDim = grid;
   const size_t used = (lds_bytes + 3) / 4;
-  for (unsigned b = 0; b < grid.x; ++b) {
-    uint32_t* w = reinterpret_cast<uint32_t*>(flr::lds);
-    for (size_t i = 0; i < used; ++i) w[i] = 0x7fc00000u;  // quiet NaN
-    for (size_t i = used; i < flr::kEmuLdsFloats; ++i) w[i] = kCanary;
-    std::barrier<> bar((std::ptrdiff_t)block.x);
-    g_bar = &bar;
-    std::vector<std::thread> ts;
-    ts.reserve(block.x);
-    for (unsigned t = 0; t < block.x; ++t) {
-      ts.emplace_back([=]() {
-        threadIdx = dim3(t);
-        blockIdx = dim3(b);
-        k(a);
-      });
-    }
-    for (auto& th : ts) th.join();
-    for (size_t i = used; i < flr::kEmuLdsFloats; ++i) {
-      if (w[i] != kCanary) {
-        std::snprintf(g_msg, sizeof g_msg, "LDS write past %zu bytes at float %zu (block %u)",
-                      lds_bytes, i, b);
-        g_last = hipErrorLaunchFailure;
-        return;
+  std::atomic<unsigned> next{0};
+  std::atomic<bool> failed{false};
+  auto worker = [&]() {
+    Workgroup wg;
+    t_wg = &wg;
+    wg.body = [&]() { k(a); };
+    char err[200];
+    for (unsigned b; !failed && (b = next++) < grid.x;) {
+      uint32_t* w = reinterpret_cast<uint32_t*>(flr::lds);
+      for (size_t i = 0; i < used; ++i) w[i] = 0x7fc00000u;  // quiet NaN
+      for (size_t i = used; i < flr::kEmuLdsFloats; ++i) w[i] = kCanary;
+      if (!wg.run(block.x, b, err, sizeof err)) {
+        set_error(hipErrorLaunchFailure, err);
+        failed = true;
+        break;
+      }
+      for (size_t i = used; i < flr::kEmuLdsFloats; ++i) {
+        if (w[i] != kCanary) {
+          std::snprintf(err, sizeof err, "LDS write past %zu bytes at float %zu (block %u)",
+                        lds_bytes, i, b);
+          set_error(hipErrorLaunchFailure, err);
+          failed = true;
+          break;
+        }
       }
     }
-  }
+    t_wg = nullptr;
+  };
+  const unsigned hw = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+  const unsigned nt = std::min(hw, grid.x);
+  std::vector<std::thread> ts;
+  for (unsigned i = 0; i < nt; ++i) ts.emplace_back(worker);
+  for (auto& th : ts) th.join();
 }
 
 #include "flr_device.hpp"

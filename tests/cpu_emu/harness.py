@@ -41,7 +41,7 @@ def build(force: bool = False) -> str:
         return SO
     os.makedirs(BUILD, exist_ok=True)
     defs = [f"-D{d}" for d in VARIANT.split(",") if d]
-    cmd = ["g++", "-std=c++20", "-O1", "-g", "-pthread", "-shared", "-fPIC", *defs,
+    cmd = ["g++", "-std=c++20", "-O1", "-g", "-pthread", "-fno-extern-tls-init", "-shared", "-fPIC", *defs,
            f"-I{HERE}", f"-I{INCLUDE}", f"-I{CSRC}", *srcs, "-o", SO + ".tmp"]
     subprocess.run(cmd, check=True)
     os.replace(SO + ".tmp", SO)

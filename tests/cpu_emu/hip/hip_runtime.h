@@ -1,6 +1,6 @@
 // CPU stand-in for the few HIP runtime names the FLR kernel sources use, so
 // that the same sources can be compiled with g++ and executed on the host:
-// a workgroup runs as blockDim.x host threads that meet at a real barrier.
+// a workgroup runs as blockDim.x fibers on one host thread.
 // Test infrastructure only.
 #pragma once
 
@@ -8,18 +8,19 @@
 #include <cmath>
 #include <cstddef>
 #include <cstdint>
+#include <cstring>
 
 #define __global__
 #define __device__
 #define __host__
 #define __forceinline__ inline
 #define __launch_bounds__(...)
-#define __shared__
+#define __shared__ thread_local
 #define HIP_SYMBOL(x) (&(x))
 
 struct dim3 {
   unsigned x, y, z;
-  dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
+  constexpr dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
 };
 
 extern thread_local dim3 threadIdx;
@@ -29,6 +30,32 @@ extern dim3 gridDim;
 void __syncthreads();
 
 inline float rsqrtf(float x) { return 1.0f / std::sqrt(x); }
+
+inline long long __double_as_longlong(double x) {
+  long long v;
+  std::memcpy(&v, &x, sizeof v);
+  return v;
+}
+inline double __longlong_as_double(long long v) {
+  double x;
+  std::memcpy(&x, &v, sizeof x);
+  return x;
+}
+inline int __float_as_int(float x) {
+  int v;
+  std::memcpy(&v, &x, sizeof v);
+  return v;
+}
+inline float __int_as_float(int v) {
+  float x;
+  std::memcpy(&x, &v, sizeof x);
+  return x;
+}
+
+// DPP lane move of a 64-lane wavefront (row_shr:1..15, row_bcast:15,
+// row_bcast:31); every lane of the wavefront must call it at the same point.
+int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask,
+                                bool bound_ctrl);
 using std::max;
 using std::min;
 
