@@ -22,6 +22,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
+#include "flr.h"
 #include "flr_launch.hpp"
 
 namespace flr {
@@ -239,6 +242,7 @@ __device__ __forceinline__ void hbox(const E* __restrict__ src, E* __restrict__ 
 constexpr int kDppRowShr = 0x110;
 constexpr int kDppRowBcast15 = 0x142;
 constexpr int kDppRowBcast31 = 0x143;
+constexpr int kDppWaveShr1 = 0x138;
 
 // x of the DPP source lane (0 where the source is outside the row, or the
 // lane's row is masked off), 64-bit values as two 32-bit moves.
@@ -270,6 +274,37 @@ __device__ __forceinline__ E seg_prefix(E x) {
   return x;
 }
 
+// Value of the lane to the left within the prefix segment (0 at its start).
+template <bool WIDE, typename E>
+__device__ __forceinline__ E seg_left(E x) {
+  return WIDE ? dpp_move<kDppWaveShr1, 0xf>(x) : dpp_move<kDppRowShr + 1, 0xf>(x);
+}
+
+// seg_prefix of N values at once, step by step across the values, so that
+// independent moves and adds overlap each other's latency.
+template <int CTRL, int ROW_MASK, int N, typename E>
+__device__ __forceinline__ void seg_step(E (&x)[N]) {
+  E t[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) t[i] = dpp_move<CTRL, ROW_MASK>(x[i]);
+  // keep the N moves ahead of their adds (independent work between a
+  // move and the add that reads it)
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] += t[i];
+}
+template <bool WIDE, int N, typename E>
+__device__ __forceinline__ void seg_prefix_n(E (&x)[N]) {
+  seg_step<kDppRowShr + 1, 0xf>(x);
+  seg_step<kDppRowShr + 2, 0xf>(x);
+  seg_step<kDppRowShr + 4, 0xf>(x);
+  seg_step<kDppRowShr + 8, 0xf>(x);
+  if (WIDE) {
+    seg_step<kDppRowBcast15, 0xa>(x);  // row totals 0 -> 1, 2 -> 3
+    seg_step<kDppRowBcast31, 0xc>(x);  // rows 0..1 total -> 2, 3
+  }
+}
+
 // Prefix segments of 16 lanes serve windows up to 2r + 1 = 17 columns wide.
 __host__ __device__ constexpr bool wide_segments(int r) { return r > 8; }
 
@@ -291,6 +326,31 @@ __device__ __forceinline__ HWin hwin(int j, int r) {
 template <typename E>
 __device__ __forceinline__ E hwin_sum(const E* row, const HWin& h) {
   return (row[h.ib] - row[h.ia]) + row[h.it];
+}
+
+// Buffer descriptor of one FP32 plane of `bytes` bytes (raw: stride 0,
+// GFX9 dword-3 format word), and a dword load at vector offset `vo` plus
+// scalar offset `so`.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, bytes, 0x00020000);
+}
+__device__ __forceinline__ float plane_load(__amdgpu_buffer_rsrc_t rs, int vo, int so) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, 0));
+}
+
+// Rows y0 .. y0 + NV - 1 of one column of an FP32 plane (byte offset xb of
+// the column; zero outside the image or where !xin).
+template <int NV>
+__device__ __forceinline__ void column_block(const float* plane, int bytes, int xb, int y0, int H,
+                                             int W, bool xin, float (&v)[NV]) {
+  const __amdgpu_buffer_rsrc_t rs = plane_rsrc(plane, bytes);
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int y = y0 + i;
+    const float t = plane_load(rs, xb, min(max(y, 0), H - 1) * W * 4);
+    const unsigned keep = (xin && y >= 0 && y < H) ? 0xffffffffu : 0u;
+    v[i] = __uint_as_float(__float_as_uint(t) & keep);
+  }
 }
 
 // Raw FP32 guides and noisy values of one pixel (zeros outside the image),
@@ -347,6 +407,39 @@ __device__ __forceinline__ void vupdate(sum_t (&V)[num_sums(Q, C)], const sum_t 
   }
 }
 
+// Change of channels [g0, g0 + gn) of the running vertical sums when the
+// entering pixel (ga, ya) is added and the leaving one (gs, ys) removed
+// (channel order as in vupdate); every index folds at compile time.
+template <int Q, int C, int MG>
+__device__ __forceinline__ void group_deltas(int g0, int gn, const sum_t (&ga)[Q],
+                                             const sum_t (&ya)[C], const sum_t (&gs)[Q],
+                                             const sum_t (&ys)[C], sum_t (&dl)[MG]) {
+  auto in = [&](int m) { return m >= g0 && m < g0 + gn; };
+#pragma unroll
+  for (int q = 0; q < Q; ++q)
+    if (in(q)) dl[q - g0] = ga[q] - gs[q];
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+    if (in(Q + c)) dl[Q + c - g0] = ya[c] - ys[c];
+  int k = Q + C;
+#pragma unroll
+  for (int p = 0; p < Q; ++p) {
+#pragma unroll
+    for (int q = p; q < Q; ++q) {
+      if (in(k)) dl[k - g0] = fma_t(-gs[p], gs[q], ga[p] * ga[q]);
+      ++k;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if (in(k)) dl[k - g0] = fma_t(-gs[q], ys[c], ga[q] * ya[c]);
+      ++k;
+    }
+  }
+}
+
 // Fold the window sums of channels [g0, g0 + gn) (one LDS group of segment
 // prefixes, row stride kLdsStride, read through `h`) into the central
 // moments: mu~, nu, the guide covariance Hm and the guide/channel covariance
@@ -354,12 +447,33 @@ __device__ __forceinline__ void vupdate(sum_t (&V)[num_sums(Q, C)], const sum_t 
 // (shifted guides). Groups arrive in increasing order and the first holds all
 // Q + C first moments, so the means are complete before any covariance needs
 // them. All loops unroll and every group test folds at compile time.
-template <int Q, int C, typename T, typename U>
+template <int Q, int C, int MG, typename T, typename U>
 __device__ __forceinline__ void centre_group(int g0, int gn, const sum_t* P, const HWin& h,
                                              T inv_n, T (&mu)[Q], T (&nu)[C],
                                              U (&Hm)[Q * (Q + 1) / 2], U (&R)[Q * C]) {
   constexpr int NP = Q * (Q + 1) / 2;
-  auto win = [&](int m) { return (T)hwin_sum(P + (m - g0) * kLdsStride, h); };
+  // window sums of the group: the three prefix reads of four channels are
+  // issued together, ahead of their arithmetic
+  constexpr int B = 4;
+  T ws[MG];
+#pragma unroll
+  for (int k0 = 0; k0 < MG; k0 += B) {
+    sum_t rb[B], ra[B], rt[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      if (k0 + i < gn) {
+        const sum_t* row = P + (k0 + i) * kLdsStride;
+        rb[i] = row[h.ib];
+        ra[i] = row[h.ia];
+        rt[i] = row[h.it];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < B; ++i)
+      if (k0 + i < gn) ws[k0 + i] = (T)((rb[i] - ra[i]) + rt[i]);
+  }
+  auto win = [&](int m) { return ws[m - g0]; };
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int m = q;
@@ -498,6 +612,12 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
   const int xc = X0 - hc + tid;      // coefficient column of this lane (tid < ncoef)
   const bool cvalid = tid < ncoef && xc >= 0 && xc < W;
   constexpr int NG = (NS + MG - 1) / MG;  // LDS groups of moment channels
+  // With at most two groups, every channel's segment prefix stays resident
+  // in LDS from one row to the next, and the running vertical sums are
+  // recovered from it (V[j] = P[j] - P[j-1] within a segment) instead of
+  // being held in registers across the row.
+  constexpr bool VL = MODE != W_FUSED1 && NG <= 2;
+  constexpr int IL = 4;  // channels whose lane moves interleave
   const HWin hw = hwin<WIDE>(tid, r);
   // zero pad column of every prefix row of both buffers (no other pass
   // writes column kThreads; the first group's barrier orders these stores)
@@ -543,6 +663,25 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
     }
   }
 
+  if (VL) {
+#pragma unroll
+    for (int gi = 0; gi < NG; ++gi) {
+      const int g0 = gi * MG;
+      const int gn = NS - g0 < MG ? NS - g0 : MG;
+      sum_t* P = (gi & 1) ? S1 : S0;
+#pragma unroll
+      for (int m0 = 0; m0 < gn; m0 += IL) {
+        sum_t x[IL];
+#pragma unroll
+        for (int i = 0; i < IL; ++i) x[i] = m0 + i < gn ? V[g0 + m0 + i] : sum_t(0);
+        seg_prefix_n<WIDE>(x);
+#pragma unroll
+        for (int i = 0; i < IL; ++i)
+          if (m0 + i < gn) P[(m0 + i) * kLdsStride + tid] = x[i];
+      }
+    }
+  }
+
   constexpr int NVA = (MODE == W_FUSED1 && !VA_LDS) ? FC : 1;
   avg_t Va[NVA];
 #pragma unroll
@@ -585,12 +724,10 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
   ring_fetch(ym0);
 
   for (int ym = ym0; ym < ym1; ++ym) {
-    {
-      sum_t ga[Q], yA[C], gs[Q], yS[C];
-      shift_raw<Q, C>(fa, okA, cg, ga, yA);
-      shift_raw<Q, C>(fs, okS, cg, gs, yS);
-      vupdate<Q, C>(V, ga, yA, gs, yS);
-    }
+    sum_t ga[Q], yA[C], gs[Q], yS[C];
+    shift_raw<Q, C>(fa, okA, cg, ga, yA);
+    shift_raw<Q, C>(fs, okS, cg, gs, yS);
+    if (!VL) vupdate<Q, C>(V, ga, yA, gs, yS);
     if (ym + 1 < ym1) fetch(ym + 1);
 
     const int slot = MODE == W_FUSED1 ? (ym - ym0) % (2 * r + 1) : 0;
@@ -619,8 +756,41 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
         const int g0 = gi * MG;
         const int gn = NS - g0 < MG ? NS - g0 : MG;
         sum_t* P = (gi & 1) ? S1 : S0;
+        // VL: the previous row's prefixes of each chunk, read one chunk ahead
+        sum_t nx[IL];
+        if (VL) {
 #pragma unroll
-        for (int m = 0; m < gn; ++m) P[m * kLdsStride + tid] = seg_prefix<WIDE>(V[g0 + m]);
+          for (int i = 0; i < IL; ++i) nx[i] = i < gn ? P[i * kLdsStride + tid] : sum_t(0);
+        }
+#pragma unroll
+        for (int m0 = 0; m0 < gn; m0 += IL) {
+          sum_t x[IL];
+          if (VL) {
+            // previous row's sums from its prefixes (own and left lanes of
+            // the segment are in this wavefront, whose reads precede its
+            // writes), then this row's update
+#pragma unroll
+            for (int i = 0; i < IL; ++i) x[i] = nx[i];
+#pragma unroll
+            for (int i = 0; i < IL; ++i)
+              nx[i] = m0 + IL + i < gn ? P[(m0 + IL + i) * kLdsStride + tid] : sum_t(0);
+            __builtin_amdgcn_sched_barrier(0);
+            sum_t lf[IL];
+#pragma unroll
+            for (int i = 0; i < IL; ++i) lf[i] = seg_left<WIDE>(x[i]);
+            sum_t dl[IL];  // this row's change of the chunk's channels
+            group_deltas<Q, C, IL>(g0 + m0, gn - m0 < IL ? gn - m0 : IL, ga, yA, gs, yS, dl);
+#pragma unroll
+            for (int i = 0; i < IL; ++i) x[i] = m0 + i < gn ? (x[i] - lf[i]) + dl[i] : sum_t(0);
+          } else {
+#pragma unroll
+            for (int i = 0; i < IL; ++i) x[i] = m0 + i < gn ? V[g0 + m0 + i] : sum_t(0);
+          }
+          seg_prefix_n<WIDE>(x);
+#pragma unroll
+          for (int i = 0; i < IL; ++i)
+            if (m0 + i < gn) P[(m0 + i) * kLdsStride + tid] = x[i];
+        }
         __syncthreads();
         if (cvalid) {
           if (MODE == W_MOMENTS && a.raw) {
@@ -628,7 +798,7 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
             for (int m = 0; m < gn; ++m)
               a.out[(1 + g0 + m) * pl + off] = (float)hwin_sum(P + m * kLdsStride, hw);
           } else {
-            centre_group<Q, C, T, chol_t>(g0, gn, P, hw, inv_n, mu, nu, Hm, R);
+            centre_group<Q, C, MG, T, chol_t>(g0, gn, P, hw, inv_n, mu, nu, Hm, R);
           }
         }
       }
@@ -805,17 +975,35 @@ __global__ void __launch_bounds__(256) apply_point_kernel(LaunchArgs a) {
   }
 }
 
-// flr_apply with averaging: a walker over coefficient planes. Lanes own
-// coefficient columns [X0 - r, X0 - r + kThreads) and keep vertical window
-// sums of all F*C coefficient planes; horizontal sums go through LDS.
-template <int Q, int C>
+// flr_apply with averaging (Sec. 3.1: each pixel's output uses the mean of
+// the coefficients of the windows that contain it). A workgroup owns a tile
+// of th <= kAvgTileRows output rows by 256 - 2r output columns; lane l owns
+// input column X0 - r + l. The coefficient planes are taken one at a time:
+// the lane streams its column's th + 2r rows of the plane once, forms the
+// vertical window sums of the tile's rows by sliding (FP64), and the
+// horizontal sums come from DPP segment prefixes staged in LDS, as in the
+// moment walkers. Each output lane accumulates
+//   out_c = (sum b_c + sum_q g_q * sum a_qc) / n
+// for all C channels of its th pixels in FP64 registers. Planes alternate
+// between two LDS buffers, one barrier each.
+// Variants of the averaging kernel: the column walk streams its rows for any
+// radius (AV_STREAM16: 16-lane prefix segments, r <= 8; AV_STREAM64:
+// wavefront segments, r > 8), or, for r = 8 and up to three channels (the
+// register budget of two workgroups per CU), loads each plane's column
+// block once and slides with compile-time offsets (AV_BLOCK8).
+enum AvgVariant : int { AV_STREAM16 = 0, AV_STREAM64 = 1, AV_BLOCK8 = 2 };
+__host__ __device__ constexpr int avg_variant(int r, int C) {
+  return (r == 8 && C <= 3) ? AV_BLOCK8 : (wide_segments(r) ? AV_STREAM64 : AV_STREAM16);
+}
+
+template <int Q, int C, int AV>
 __global__ void __launch_bounds__(kThreads, 2) apply_avg_kernel(LaunchArgs a) {
   using T = solve_t;
-  constexpr int FC = Dims<Q, C>::FC;
-  constexpr WalkLayout LAY = walk_layout(Q, C, K_APPLY_AVG);
+  constexpr bool WIDE = AV == AV_STREAM64;
+  constexpr int TH = kAvgTileRows;
   extern __shared__ float lds[];
-  T* T0 = reinterpret_cast<T*>(lds);
-  T* T1 = reinterpret_cast<T*>(reinterpret_cast<char*>(lds) + LAY.a);
+  T* P0 = reinterpret_cast<T*>(lds);
+  T* P1 = P0 + TH * kLdsStride;
   const int tid = threadIdx.x;
   const int r = a.r;
   const int H = a.H;
@@ -826,72 +1014,166 @@ __global__ void __launch_bounds__(kThreads, 2) apply_avg_kernel(LaunchArgs a) {
   const int sy = blockIdx.x / a.tiles_x;
   const int X0 = sx * tout;
   const int Y0 = sy * a.seg_rows;
-  const int Y1 = min(Y0 + a.seg_rows, H);
+  const int th = min(a.seg_rows, H - Y0);
   const int xcol = X0 - r + tid;
   const bool xin = xcol >= 0 && xcol < W;
+  const int xo = X0 + tid;
+  const bool active = tid < tout && xo < W;
+  const HWin hw = hwin<WIDE>(tid, r);
+  if (tid < 2 * TH) (tid < TH ? P0 : P1)[(tid % TH) * kLdsStride + kThreads] = T(0);
 
-  T Va[FC];
+  T acc[TH][C];
 #pragma unroll
-  for (int f = 0; f < FC; ++f) Va[f] = T(0);
-  {
-    // warm-up rows [Y0 - r, Y0 + r), loads issued one row ahead
-    float wb[FC];
-    auto wfetch = [&](int yy) {
-      const bool ok = xin && yy >= 0 && yy < H;
-      const int64_t off = (int64_t)yy * W + xcol;
+  for (int k = 0; k < TH; ++k)
 #pragma unroll
-      for (int f = 0; f < FC; ++f) wb[f] = ok ? a.planes[f * pl + off] : 0.f;
-    };
-    wfetch(Y0 - r);
-    for (int yy = Y0 - r; yy < Y0 + r; ++yy) {
-      float cur[FC];
+    for (int c = 0; c < C; ++c) acc[k][c] = T(0);
+
+  // Loads use clamped, always valid addresses (a plane base pointer plus a
+  // 32-bit offset) and zero what lies outside the image by selection, so
+  // that no load needs a branch.
+  // Raw buffer loads: a descriptor per plane, the lane's column byte offset
+  // (vector) and the row's byte offset (scalar; rows are clamped into the
+  // image, so every access is in range; planes hold at most 2^28 pixels, so
+  // offsets fit in 32 bits).
+  const int xcb = min(max(xcol, 0), W - 1) * 4;
+  const int xob = min(xo, W - 1) * 4;
+  const int pbytes = (int)(pl * 4 <= 0x7fffffff ? pl * 4 : 0x7fffffff);
+  auto at = [&](const float* base, int y, int xb) {
+    const int so = min(max(y, 0), H - 1) * W * 4;
+    return plane_load(plane_rsrc(base, pbytes), xb, so);
+  };
+  // Window sums of the tile's rows from the prefixes in P, batched four
+  // rows (twelve reads) at a time, accumulated into channel c's sums.
+  auto consume = [&](const T* P, int c, bool plain, const float (&gf)[TH]) {
+    constexpr int B = 4;
 #pragma unroll
-      for (int f = 0; f < FC; ++f) cur[f] = wb[f];
-      if (yy + 1 < Y0 + r) wfetch(yy + 1);
+    for (int k0 = 0; k0 < TH; k0 += B) {
+      T rb[B], ra[B], rt[B];
 #pragma unroll
-      for (int f = 0; f < FC; ++f) Va[f] += (T)cur[f];
-    }
-  }
-  // coefficient rows entering (yo + r) and leaving (yo - r - 1) the vertical
-  // window, loaded one step ahead
-  float ca[FC], cs[FC];
-  auto fetch = [&](int yo) {
-    const int ya = yo + r;
-    const int ys = yo - r - 1;
-    const bool oka = xin && ya < H;
-    const bool oks = xin && yo > Y0 && ys >= 0;
-    const int64_t offa = (int64_t)ya * W + xcol;
-    const int64_t offs = (int64_t)ys * W + xcol;
+      for (int i = 0; i < B; ++i) {
+        if (k0 + i < TH) {
+          const T* row = P + (k0 + i) * kLdsStride;
+          rb[i] = row[hw.ib];
+          ra[i] = row[hw.ia];
+          rt[i] = row[hw.it];
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int f = 0; f < FC; ++f) {
-      ca[f] = oka ? a.planes[f * pl + offa] : 0.f;
-      cs[f] = oks ? a.planes[f * pl + offs] : 0.f;
+      for (int i = 0; i < B; ++i) {
+        if (k0 + i < TH) {
+          const T v = (rb[i] - ra[i]) + rt[i];
+#pragma unroll
+          for (int cc = 0; cc < C; ++cc)
+            if (cc == c)
+              acc[k0 + i][cc] = plain ? acc[k0 + i][cc] + v : fma_t((T)gf[k0 + i], v, acc[k0 + i][cc]);
+        }
+      }
     }
   };
-  fetch(Y0);
-  for (int yo = Y0; yo < Y1; ++yo) {
+  // DPP segment prefixes of the tile's vertical sums into LDS buffer P
+  auto stage = [&](T* P, const T (&vs)[TH]) {
+    constexpr int IL = 4;
 #pragma unroll
-    for (int f = 0; f < FC; ++f) Va[f] += (T)ca[f] - (T)cs[f];
-    if (yo + 1 < Y1) fetch(yo + 1);
-    const int xo = X0 + tid;
-    const bool active = tid < tout && xo < W;
-    const int64_t off = (int64_t)yo * W + (active ? xo : 0);
-    T gq[Q];
-    T inv = T(0);
-    if (active) {
+    for (int k0 = 0; k0 < TH; k0 += IL) {
+      T x[IL];
 #pragma unroll
-      for (int q = 0; q < Q; ++q) gq[q] = (T)a.guides[q * pl + off];
-      inv = recip_count(win_count(yo, H, r) * win_count(xo, W, r), T(0));
-    } else {
+      for (int i = 0; i < IL; ++i) x[i] = k0 + i < TH ? vs[k0 + i] : T(0);
+      seg_prefix_n<WIDE>(x);
 #pragma unroll
-      for (int q = 0; q < Q; ++q) gq[q] = T(0);
+      for (int i = 0; i < IL; ++i)
+        if (k0 + i < TH) P[(k0 + i) * kLdsStride + tid] = x[i];
     }
-    average_and_reconstruct<Q, C, LAY.ag>(T0, T1, tout, r, a.hchunk_a, active, gq, inv, a.out + off, pl,
-                                  [&](int f0, int gn, T* dst) {
+  };
+  auto load_gf = [&](int q, float (&gf)[TH]) {
+    const float* g = a.guides + (int64_t)q * pl;
 #pragma unroll
-                                    for (int k = 0; k < gn; ++k)
-                                      dst[k * kLdsStride + tid] = Va[f0 + k];
-                                  });
+    for (int k = 0; k < TH; ++k) gf[k] = at(g, Y0 + k, xob);
+  };
+
+  int buf = 0;
+  if constexpr (AV == AV_BLOCK8) {
+    // r = 8: the lane loads its column's rows Y0 - 8 .. Y0 + TH + 7 of a
+    // plane as one block (zero outside the image), issued while the plane
+    // before it is staged and consumed.
+    constexpr int NV = TH + 16;
+    auto load_block = [&](int f, float (&v)[NV]) {
+      column_block<NV>(a.planes + (int64_t)f * pl, pbytes, xcb, Y0 - 8, H, W, xin, v);
+    };
+    // vertical window sums of rows Y0 + k: rows Y0 + k - R .. Y0 + k + R
+    auto slide = [&](auto RC, const float (&v)[NV], T (&vs)[TH]) {
+      constexpr int R = decltype(RC)::value;
+      T sum = T(0);
+#pragma unroll
+      for (int i = 8 - R; i <= 8 + R; ++i) sum += (T)v[i];
+      vs[0] = sum;
+#pragma unroll
+      for (int k = 1; k < TH; ++k) {
+        sum += (T)v[k + 8 + R] - (T)v[k + 7 - R];
+        vs[k] = sum;
+      }
+    };
+    float cur[NV];
+    load_block(0, cur);
+    float gf[TH];
+    for (int q = -1; q < Q; ++q) {
+      if (q >= 0) load_gf(q, gf);
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int f = (q + 1) * C + c;
+        T vs[TH];
+        slide(std::integral_constant<int, 8>{}, cur, vs);
+        // the next plane's block streams in during staging and consumption
+        if (f + 1 < (Q + 1) * C) load_block(f + 1, cur);
+        T* P = buf ? P1 : P0;
+        buf ^= 1;
+        stage(P, vs);
+        __syncthreads();
+        if (active) consume(P, c, q < 0, gf);
+      }
+    }
+  } else {
+    // any r: the window of the tile's first row is summed by a running
+    // loop; rows entering and leaving are loaded for each later row.
+    float gf[TH];
+    for (int q = -1; q < Q; ++q) {
+      if (q >= 0) load_gf(q, gf);
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const float* src = a.planes + (int64_t)((q + 1) * C + c) * pl;
+        T sum = T(0);
+        for (int y = max(Y0 - r, 0); y <= min(Y0 + r, H - 1); ++y) sum += (T)at(src, y, xcb);
+        if (!xin) sum = T(0);
+        T vs[TH];
+        vs[0] = sum;
+#pragma unroll
+        for (int k = 1; k < TH; ++k) {
+          const int ye = Y0 + r + k, yl = Y0 - r - 1 + k;
+          const float ve = at(src, ye, xcb), vl = at(src, yl, xcb);
+          const float e = (xin && k < th && ye < H) ? ve : 0.f;
+          const float l = (xin && k < th && yl >= 0) ? vl : 0.f;
+          sum += (T)e - (T)l;
+          vs[k] = sum;
+        }
+        T* P = buf ? P1 : P0;
+        buf ^= 1;
+        stage(P, vs);
+        __syncthreads();
+        if (active) consume(P, c, q < 0, gf);
+      }
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int k = 0; k < TH; ++k) {
+      if (k < th) {
+        const int y = Y0 + k;
+        const T inv = recip_count(win_count(y, H, r) * win_count(xo, W, r), T(0));
+        float* o = a.out + (int64_t)y * W + xo;
+#pragma unroll
+        for (int c = 0; c < C; ++c) o[c * pl] = (float)(acc[k][c] * inv);
+      }
+    }
   }
 }
 
@@ -928,7 +1210,15 @@ hipError_t launch_qc(int kind, const LaunchArgs& a, hipStream_t s) {
       return wide ? launch_with_lds(walk_kernel<Q, C, W_COEFFS, true>, wblocks, lds, a, s)
                   : launch_with_lds(walk_kernel<Q, C, W_COEFFS, false>, wblocks, lds, a, s);
     case K_APPLY_AVG:
-      return launch_with_lds(apply_avg_kernel<Q, C>, wblocks, lds, a, s);
+      switch (avg_variant(a.r, C)) {
+        case AV_BLOCK8:
+          if constexpr (C <= 3)
+            return launch_with_lds(apply_avg_kernel<Q, C, AV_BLOCK8>, wblocks, lds, a, s);
+          return hipErrorInvalidValue;
+        case AV_STREAM64:
+          return launch_with_lds(apply_avg_kernel<Q, C, AV_STREAM64>, wblocks, lds, a, s);
+        default: return launch_with_lds(apply_avg_kernel<Q, C, AV_STREAM16>, wblocks, lds, a, s);
+      }
     case K_SOLVE:
       hipLaunchKernelGGL((solve_kernel<Q, C>), dim3(pblocks), dim3(256), 0, s, a);
       return hipGetLastError();

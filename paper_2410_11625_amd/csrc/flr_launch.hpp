@@ -98,8 +98,12 @@ inline int strip_out_cols(int kind, int r) {
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 // Workgroups of a walker kernel resident per CU (LDS and registers allow two
-// for the coefficient-averaging walker, one for the others).
+// for the coefficient-averaging kernel, one for the others).
 inline int workgroups_per_cu(int kind) { return kind == K_APPLY_AVG ? 2 : 1; }
+
+// Output rows per tile of the coefficient-averaging kernel (sizes its
+// per-lane register arrays).
+constexpr int kAvgTileRows = 17;
 
 // Rows of coefficient halo a walker recomputes above and below its segment.
 inline int row_halo(int kind, int r) { return kind == K_FUSED1 ? r : 0; }
@@ -111,9 +115,29 @@ inline void plan_walk(int kind, int H, int W, int r, int tile_rows, int* tiles_x
                       int* seg_rows) {
   const int tout = strip_out_cols(kind, r);
   *tiles_x = ceil_div(W, tout);
+  const int rmax = kind == K_APPLY_AVG ? kAvgTileRows : H;
   if (tile_rows > 0) {
-    *seg_rows = tile_rows < H ? tile_rows : H;
+    int t = tile_rows < H ? tile_rows : H;
+    *seg_rows = t < rmax ? t : rmax;
     *n_seg = ceil_div(H, *seg_rows);
+    return;
+  }
+  if (kind == K_APPLY_AVG) {
+    // every tile reads its rows plus 2r halo rows of each coefficient plane
+    double best = 1e300;
+    int best_n = ceil_div(H, rmax);
+    for (int n = best_n; n <= H; ++n) {
+      const int R = ceil_div(H, n);
+      if (n > best_n && ceil_div(H, n - 1) == R) continue;
+      const double waves = (double)ceil_div(*tiles_x * n, kCUs * workgroups_per_cu(kind));
+      const double cost = waves * (double)(R + 2 * r) + 1e-3 * n;
+      if (cost < best) {
+        best = cost;
+        best_n = n;
+      }
+    }
+    *n_seg = best_n;
+    *seg_rows = ceil_div(H, best_n);
     return;
   }
   const int hc = row_halo(kind, r);
@@ -178,11 +202,9 @@ __host__ __device__ constexpr WalkLayout walk_layout(int Q, int C, int kind) {
   const int row_t = kLdsStride * (int)sizeof(solve_t);
   WalkLayout L{0, 0, false, 0, 0, 0};
   if (kind == K_APPLY_AVG) {
-    // two workgroups per CU: at most half the LDS each
-    const int ag_max = (kLdsBytes / 2) / (2 * row_t);
-    const int ng = (fc + ag_max - 1) / ag_max;
-    L.ag = (fc + ng - 1) / ng;
-    L.a = L.b = (size_t)L.ag * row_t;
+    // two buffers of segment prefixes, one row per output row of the tile
+    L.ag = fc;
+    L.a = L.b = (size_t)kAvgTileRows * row_t;
     return L;
   }
   if (kind == K_FUSED1) {

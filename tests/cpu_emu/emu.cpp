@@ -175,6 +175,8 @@ int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask, int ba
   if (ctrl > 0x110 && ctrl <= 0x11f) {
     const int k = ctrl - 0x110;
     s = rl >= k ? (int)l - k : -1;
+  } else if (ctrl == 0x138) {  // wave_shr:1
+    s = l >= 1 ? (int)l - 1 : -1;
   } else if (ctrl == 0x142) {
     s = row >= 1 ? (row - 1) * 16 + 15 : -1;
   } else if (ctrl == 0x143) {
@@ -185,6 +187,17 @@ int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask, int ba
   }
   if (s < 0) return bound_ctrl ? 0 : old;
   return wg->dpp[slot][w * kWave + (unsigned)s];
+}
+
+unsigned __builtin_amdgcn_raw_buffer_load_b32(__amdgpu_buffer_rsrc_t r, int vo, int so, int) {
+  const long long o = (long long)vo + (long long)so;
+  if (vo < 0 || so < 0 || o + 4 > (long long)r.bytes) {
+    std::fprintf(stderr, "emulator: buffer load at %lld outside [0, %d)\n", o, r.bytes);
+    std::abort();
+  }
+  unsigned v;
+  std::memcpy(&v, r.base + o, sizeof v);
+  return v;
 }
 
 namespace flr {

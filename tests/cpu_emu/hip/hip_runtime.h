@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 
 #define __global__
@@ -52,8 +53,34 @@ inline float __int_as_float(int v) {
   return x;
 }
 
-// DPP lane move of a 64-lane wavefront (row_shr:1..15, row_bcast:15,
-// row_bcast:31); every lane of the wavefront must call it at the same point.
+inline unsigned __float_as_uint(float x) {
+  unsigned v;
+  std::memcpy(&v, &x, sizeof v);
+  return v;
+}
+inline float __uint_as_float(unsigned v) {
+  float x;
+  std::memcpy(&x, &v, sizeof x);
+  return x;
+}
+
+// Raw buffer descriptor and dword load. Kernels must keep every access
+// inside the descriptor's range; the emulator aborts otherwise.
+struct __amdgpu_buffer_rsrc_t {
+  const char* base;
+  int bytes;
+};
+inline __amdgpu_buffer_rsrc_t __builtin_amdgcn_make_buffer_rsrc(void* p, short stride, int bytes,
+                                                               int) {
+  if (stride != 0) std::abort();
+  return {static_cast<const char*>(p), bytes};
+}
+unsigned __builtin_amdgcn_raw_buffer_load_b32(__amdgpu_buffer_rsrc_t r, int vo, int so, int aux);
+
+inline void __builtin_amdgcn_sched_barrier(int) {}
+
+// DPP lane move of a 64-lane wavefront (row_shr:1..15, wave_shr:1,
+// row_bcast:15, row_bcast:31); every lane of the wavefront must call it at the same point.
 int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask,
                                 bool bound_ctrl);
 using std::max;
