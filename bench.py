@@ -87,22 +87,76 @@ def load_traffic(path_name: str):
     return d.get("hbm_bytes_per_launch")
 
 
+CPU_CROP = 640  # side of the square crop the oracle is timed on (about 10-15 s)
+
+
 def cpu_baseline_child() -> None:
     """Runs in a child process with one BLAS/OpenMP thread: the oracle on a
-    256x256 crop of the 1080p workload frame."""
+    CPU_CROP x CPU_CROP crop of the 1080p workload frame, once."""
     import numpy as np
     from oracle import flr_ref
     from synth import make_config
     fr = make_config(1)
-    y0, x0 = 412, 832
-    noisy = np.ascontiguousarray(fr["noisy"][:, y0:y0 + 256, x0:x0 + 256])
-    guides = np.ascontiguousarray(fr["guides"][:, y0:y0 + 256, x0:x0 + 256])
-    times = []
-    for _ in range(2):
-        t = time.perf_counter()
-        flr_ref.flr_reference(noisy, guides, R, EPS)
-        times.append(time.perf_counter() - t)
-    print(json.dumps({"seconds": min(times), "pixels": 256 * 256, "runs": len(times)}))
+    n = CPU_CROP
+    y0, x0 = (H - n) // 2, (W - n) // 2
+    noisy = np.ascontiguousarray(fr["noisy"][:, y0:y0 + n, x0:x0 + n])
+    guides = np.ascontiguousarray(fr["guides"][:, y0:y0 + n, x0:x0 + n])
+    t = time.perf_counter()
+    flr_ref.flr_reference(noisy, guides, R, EPS)
+    print(json.dumps({"seconds": time.perf_counter() - t, "pixels": n * n, "runs": 1}))
+
+
+DOMINANT_KERNEL = {"two_pass": "walk_kernel<8, 3, 3", "fused": "walk_kernel<8, 3, 2",
+                   "stages": "walk_kernel<8, 3, 0"}
+
+
+def summarize_counters(fetch_csv: str, write_csv: str, path_name: str) -> int:
+    """HBM bytes per launch of each kernel from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of
+    ``bench.py --copy-calibration``: each counter is scaled by the ratio of
+    the 1 GiB calibration copy's true bytes to what the counter read for it.
+    Writes the dominant kernel's figure, with the digest of the kernel
+    sources it was taken on, for the benchmark line; prints a table."""
+    import csv
+
+    def per_kernel(f):
+        out = {}
+        for row in csv.DictReader(open(f)):
+            out.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]) * 1024.0)
+        return out
+
+    fetch, write = per_kernel(fetch_csv), per_kernel(write_csv)
+    # the calibration copy: the largest copy dispatches (1 GiB read, 1 GiB written)
+    copies = [k for k in write if "copyBuffer" in k]
+    big_w = max(v for k in copies for v in write[k])
+    big_f = max(v for k in copies for v in fetch[k])
+    kf, kw = COPY_BYTES / big_f, COPY_BYTES / big_w
+    rows = []
+    for k in sorted(set(fetch) & set(write)):
+        f = kf * sum(fetch[k]) / len(fetch[k])
+        w = kw * sum(write[k]) / len(write[k])
+        rows.append((k, len(fetch[k]), f, w))
+    print(f"calibration: FETCH_SIZE x {kf:.3f}, WRITE_SIZE x {kw:.3f} "
+          f"(1 GiB copy read as {big_f / 2**20:.1f} MiB fetched, {big_w / 2**20:.1f} MiB written)")
+    print("| kernel | dispatches | fetched MB | written MB |")
+    print("|---|---|---|---|")
+    for k, n, f, w in rows:
+        print(f"| `{k[:70]}` | {n} | {f / 1e6:.1f} | {w / 1e6:.1f} |")
+    dom = [r for r in rows if DOMINANT_KERNEL[path_name] in r[0]]
+    if not dom:
+        print("dominant kernel not found", file=sys.stderr)
+        return 1
+    k, n, f, w = dom[0]
+    out = {"kernel": k, "kernel_source_digest": kernel_source_digest(),
+           "fetch_bytes_per_launch": round(f), "write_bytes_per_launch": round(w),
+           "hbm_bytes_per_launch": round(f + w),
+           "calibration": {"fetch_scale": round(kf, 4), "write_scale": round(kw, 4)}}
+    dst = os.path.join(ROOT, "profiles", f"flr_{path_name}_1080p_rgb_q8_counters.json")
+    with open(dst, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    print(f"wrote {dst}")
+    return 0
 
 
 def cpu_baseline():
@@ -119,8 +173,8 @@ def cpu_baseline():
     return {"value": round(d["pixels"] / d["seconds"] / 1e6, 5), "unit": "Mpixel/s", "cores": 1,
             "kind": "oracle",
             "sample": (f"FP64 NumPy oracle (window sums as shifted adds, batched solves), one "
-                       f"256x256 crop of the 1080p workload frame, same guides/radius/eps, best "
-                       f"of {d['runs']} runs ({d['seconds']:.1f} s each), 1 thread")}
+                       f"{CPU_CROP}x{CPU_CROP} crop of the 1080p workload frame (same guides, "
+                       f"radius, eps), one run of {d['seconds']:.1f} s, 1 thread")}
 
 
 def main(argv=None):
@@ -133,12 +187,17 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter reference)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) of a "
+                         "--copy-calibration run into profiles/flr_<path>_1080p_rgb_q8_counters.json")
     ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args(argv)
 
     if args.cpu_baseline_child:
         cpu_baseline_child()
         return 0
+    if args.summarize_counters:
+        return summarize_counters(*args.summarize_counters, args.path)
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (a frame is not split across GPUs; "
               "independent frames would be distributed one per GPU). Run with --gpus 1.",
