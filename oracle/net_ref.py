@@ -7,8 +7,10 @@ The network follows Sec. 3.3 (a U-Net over the guides and the noisy input
 that produces extra guide channels for the regression) in the
 configuration's three-level form:
 
+  input: the 8 guides then the 3 noisy channels, each value v compressed to
+      sign(v) log(1 + |v|) (depth and radiance fireflies span decades)
   level 0 (full resolution, 16 channels):
-      in3  3x3 conv 11 -> 16, ReLU          (input: 8 guides then 3 noisy)
+      in3  3x3 conv 11 -> 16, ReLU
       in1  1x1 conv 16 -> 16, ReLU          = e0
   encoder:
       e1a  3x3 conv 16 -> 32, ReLU
@@ -94,11 +96,15 @@ def upsample2(x: np.ndarray, H: int, W: int) -> np.ndarray:
 
 
 def net_forward(guides: np.ndarray, noisy: np.ndarray, weights: dict,
-                logits: bool = False) -> np.ndarray:
+                logits: bool = False, compress: bool = True) -> np.ndarray:
     """The 4 extra guide planes [4][H][W] for guides [8][H][W] and noisy
-    [3][H][W] (float64 out). ``logits`` returns the out1 pre-activation."""
+    [3][H][W] (float64 out). ``logits`` returns the out1 pre-activation;
+    ``compress=False`` skips the input compression (for tests of the layers)."""
     wq = {n: (bf16_round(w), bf16_round(b)) for n, (w, b) in weights.items()}
-    x = bf16_round(np.concatenate([guides, noisy]).astype(np.float64))
+    x = np.concatenate([guides, noisy]).astype(np.float64)
+    if compress:
+        x = np.sign(x) * np.log1p(np.abs(x))
+    x = bf16_round(x)
     assert x.shape[0] == 11
     H, W = x.shape[1:]
 

@@ -2,11 +2,14 @@
 
 The windowed per-pixel regularised linear regression of "Fast Local Neural
 Regression for Low-Cost, Path Traced Lambertian Global Illumination"
-(Sec. 3.1-3.2 and the Appendix), as hand-written HIP kernels behind the C ABI
-in ``include/flr.h``. This package is the thin Python binding.
+(Sec. 3.1-3.2 and the Appendix) and the FLNR guide network (Sec. 3.3), as
+hand-written HIP kernels behind the C ABI in ``include/flr.h`` and
+``include/flr_net.h``. This package is the thin Python binding.
 """
-from .api import (PATHS, FLRError, apply, coefficients, denoise, make_params, moments,
-                  num_coeff_planes, num_moment_planes, solve, workspace_bytes)
+from .api import (PATHS, FLRError, apply, coefficients, denoise, flnr_denoise,
+                  flnr_workspace_bytes, make_params, moments, net_forward, net_num_params,
+                  net_pack, num_coeff_planes, num_moment_planes, solve, workspace_bytes)
 
-__all__ = ["PATHS", "FLRError", "apply", "coefficients", "denoise", "make_params", "moments",
-           "num_coeff_planes", "num_moment_planes", "solve", "workspace_bytes"]
+__all__ = ["PATHS", "FLRError", "apply", "coefficients", "denoise", "flnr_denoise",
+           "flnr_workspace_bytes", "make_params", "moments", "net_forward", "net_num_params",
+           "net_pack", "num_coeff_planes", "num_moment_planes", "solve", "workspace_bytes"]

@@ -172,5 +172,83 @@ def denoise(noisy: torch.Tensor, guides: torch.Tensor, radius: int = 8, eps: flo
     return out
 
 
+# --------------------------------------------------------------------------
+# FLNR guide network (include/flr_net.h)
+
+NET_IN_GUIDES, NET_IN_NOISY, NET_OUT = 8, 3, 4
+
+
+def net_num_params() -> int:
+    return int(lib().flr_net_num_params())
+
+
+def net_pack(params: torch.Tensor) -> torch.Tensor:
+    """FP32 parameter vector (layer order of include/flr_net.h) -> the packed
+    BF16 device block (uint8 tensor) that net_forward and flnr_denoise read."""
+    _need(params, "params", ndim=1)
+    if params.numel() != net_num_params():
+        raise ValueError(f"expected {net_num_params()} parameters, got {params.numel()}")
+    packed = torch.empty(int(lib().flr_net_packed_bytes()), dtype=torch.uint8,
+                         device=params.device)
+    check(lib().flr_net_pack(params.data_ptr(), packed.data_ptr(), _stream(params)),
+          "flr_net_pack")
+    return packed
+
+
+def net_forward(guides: torch.Tensor, noisy: torch.Tensor, packed: torch.Tensor,
+                out: torch.Tensor | None = None,
+                workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """The 4 extra guide planes [4,H,W] for guides [8,H,W] and noisy [3,H,W]."""
+    _need(guides, "guides")
+    _need(noisy, "noisy")
+    if guides.shape[0] != NET_IN_GUIDES or noisy.shape[0] != NET_IN_NOISY:
+        raise ValueError("the network reads 8 guide planes and 3 noisy planes")
+    _, H, W = guides.shape
+    need = int(lib().flr_net_workspace_bytes(H, W))
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=guides.device)
+    if out is None:
+        out = torch.empty((NET_OUT, H, W), dtype=torch.float32, device=guides.device)
+    _need(out, "out")
+    check(lib().flr_net_forward(H, W, guides.data_ptr(), noisy.data_ptr(), packed.data_ptr(),
+                                out.data_ptr(), workspace.data_ptr(),
+                                workspace.numel() * workspace.element_size(), _stream(guides)),
+          "flr_net_forward")
+    return out
+
+
+def flnr_workspace_bytes(p: FlrParams) -> int:
+    return int(lib().flr_flnr_workspace_bytes(ctypes.byref(p)))
+
+
+def flnr_denoise(noisy: torch.Tensor, guides12: torch.Tensor, packed: torch.Tensor,
+                 radius: int = 8, eps: float = 1e-3, mode: str = "ridge", eps_mul: float = 0.0,
+                 average: bool = True, fused="two_pass", out: torch.Tensor | None = None,
+                 workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """FLNR: guides12 [12,H,W] holds the 8 input guides in planes 0..7; the
+    network writes planes 8..11, then FLR runs over all 12 -> [3,H,W]."""
+    _need(guides12, "guides12")
+    _need(noisy, "noisy")
+    Q, H, W = guides12.shape
+    C = noisy.shape[0]
+    p = make_params(H, W, Q, C, radius, eps=eps, mode=mode, eps_mul=eps_mul, average=average,
+                    fused=fused)
+    need = flnr_workspace_bytes(p)
+    if need == 0:
+        check(lib().flr_validate_params(ctypes.byref(p)), "flr_flnr_denoise")
+        raise ValueError("FLNR needs 12 guide planes and 3 noisy channels")
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=guides12.device)
+    if out is None:
+        out = torch.empty((C, H, W), dtype=torch.float32, device=guides12.device)
+    _need(out, "out")
+    check(lib().flr_flnr_denoise(ctypes.byref(p), guides12.data_ptr(), noisy.data_ptr(),
+                                 packed.data_ptr(), out.data_ptr(), workspace.data_ptr(),
+                                 workspace.numel() * workspace.element_size(), _stream(guides12)),
+          "flr_flnr_denoise")
+    return out
+
+
 __all__ = ["FLRError", "PATHS", "make_params", "num_moment_planes", "num_coeff_planes",
-           "workspace_bytes", "moments", "solve", "coefficients", "apply", "denoise"]
+           "workspace_bytes", "moments", "solve", "coefficients", "apply", "denoise",
+           "net_num_params", "net_pack", "net_forward", "flnr_workspace_bytes", "flnr_denoise"]

@@ -1,0 +1,463 @@
+// The FLNR guide network (Sec. 3.3, the three-level 16/32/64 variant
+// declared in include/flr_net.h) on the gfx950 matrix cores, and FLNR
+// denoising (network, then FLR over the 12 guides).
+//
+// Every layer is one implicit-GEMM kernel. Activations are BF16 in HWC order
+// (channels innermost, a multiple of 16), so the 16 channels of one K step
+// of a pixel are 32 contiguous bytes. With A = weights (c_out x k) and
+// B = input (k x pixels), v_mfma_f32_16x16x16_bf16 gives lane l the
+// accumulators of output channels 4*(l/16) .. +3 of pixel l % 16: four
+// consecutive channels, stored as one 8-byte write, and exactly the B
+// operand layout of a following 1x1 layer, which is therefore fused into the
+// producing kernel (in3 + in1, out3 + out1). Upsampling and concatenation
+// are folded into the consumer's operand loads. A workgroup of four waves
+// covers 64 consecutive output pixels of one row, each wave 16 pixels and
+// all output channels; weights are packed once into the per-lane fragment
+// order, so each A operand is one contiguous 512-byte read per wave.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "flr.h"
+#include "flr_net.h"
+
+namespace flrnet {
+
+typedef short bf16x4_t __attribute__((vector_size(8)));
+typedef float f32x4_t __attribute__((vector_size(16)));
+
+enum InKind : int { IN_HWC = 0, IN_PLANAR = 1, IN_UPCAT = 2 };
+enum Fuse : int { FUSE_NONE = 0, FUSE_1X1_RELU = 1, FUSE_1X1_SIGMOID = 2 };
+
+struct ConvArgs {
+  const uint16_t* in0;  // HWC BF16 input (IN_UPCAT: the low-resolution part)
+  const uint16_t* in1;  // IN_UPCAT: the skip connection, on the conv's input grid
+  const float* g;       // IN_PLANAR: guides [8][Hi][Wi]
+  const float* y;       // IN_PLANAR: noisy [3][Hi][Wi]
+  const bf16x4_t* w;    // packed weight fragments of the layer
+  const float* b;       // BF16-rounded bias (padded output channels)
+  const bf16x4_t* w2;   // fused 1x1 layer
+  const float* b2;
+  uint16_t* out;        // HWC BF16 output
+  float* outf;          // FUSE_1X1_SIGMOID: planar FP32 output
+  int Hi, Wi;           // input grid
+  int Hl, Wl;           // IN_UPCAT: grid of in0
+  int Ho, Wo;           // output grid
+};
+
+// FP32 -> BF16, round to nearest, ties to even (NaN stays NaN).
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  const uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ bf16x4_t pack4(uint16_t a, uint16_t b, uint16_t c, uint16_t d) {
+  bf16x4_t v;
+  v[0] = (short)a;
+  v[1] = (short)b;
+  v[2] = (short)c;
+  v[3] = (short)d;
+  return v;
+}
+
+// Four consecutive input channels c..c+3 of input pixel (yi, xi); zero when
+// !ok (padding).
+template <int CIN, int CUP, int IN>
+__device__ __forceinline__ bf16x4_t load_in(const ConvArgs& a, int yi, int xi, int c, bool ok) {
+  if (!ok) return pack4(0, 0, 0, 0);
+  if (IN == IN_HWC) {
+    return *reinterpret_cast<const bf16x4_t*>(a.in0 + ((size_t)yi * a.Wi + xi) * CIN + c);
+  } else if (IN == IN_UPCAT) {
+    if (c < CUP)
+      return *reinterpret_cast<const bf16x4_t*>(a.in0 + ((size_t)(yi >> 1) * a.Wl + (xi >> 1)) * CUP + c);
+    return *reinterpret_cast<const bf16x4_t*>(a.in1 + ((size_t)yi * a.Wi + xi) * (CIN - CUP) +
+                                              (c - CUP));
+  } else {
+    const size_t pl = (size_t)a.Hi * a.Wi, off = (size_t)yi * a.Wi + xi;
+    uint16_t h[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int cc = c + j;
+      const float v = cc < FLR_NET_IN_GUIDES ? a.g[cc * pl + off]
+                    : (cc < FLR_NET_IN_GUIDES + FLR_NET_IN_NOISY ? a.y[(cc - FLR_NET_IN_GUIDES) * pl + off] : 0.f);
+      h[j] = f2bf(copysignf(log1pf(fabsf(v)), v));  // input compression
+    }
+    return pack4(h[0], h[1], h[2], h[3]);
+  }
+}
+
+// One conv layer (CIN, COUT multiples of 16; KS 1 or 3; stride ST), bias and
+// ReLU, optionally followed by a fused 1x1 layer to COUT2 channels (ReLU to
+// HWC BF16, or sigmoid to planar FP32).
+template <int CIN, int COUT, int KS, int ST, int IN, int CUP, int FUSE, int COUT2>
+__global__ void __launch_bounds__(256) conv_kernel(ConvArgs a) {
+  constexpr int NCB = CIN / 16, NB = COUT / 16, P = KS / 2;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int y = blockIdx.y;
+  const int px = blockIdx.x * 64 + wv * 16 + (lane & 15);
+  const int kq = lane >> 4;
+  const bool pin = px < a.Wo;
+  f32x4_t acc[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll
+  for (int ky = 0; ky < KS; ++ky) {
+    const int yi = y * ST + ky - P;
+    const bool oky = yi >= 0 && yi < a.Hi;
+#pragma unroll
+    for (int kx = 0; kx < KS; ++kx) {
+      const int xi = px * ST + kx - P;
+      const bool ok = pin && oky && xi >= 0 && xi < a.Wi;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const bf16x4_t bv = load_in<CIN, CUP, IN>(a, yi, xi, cb * 16 + 4 * kq, ok);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const bf16x4_t av = a.w[(((ky * KS + kx) * NCB + cb) * NB + nb) * 64 + lane];
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[nb], 0, 0, 0);
+        }
+      }
+    }
+  }
+
+  if constexpr (FUSE == FUSE_NONE) {
+    if (!pin) return;
+    uint16_t* o = a.out + ((size_t)y * a.Wo + px) * COUT + 4 * kq;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      uint16_t h[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) h[i] = f2bf(fmaxf(acc[nb][i] + a.b[nb * 16 + 4 * kq + i], 0.f));
+      *reinterpret_cast<bf16x4_t*>(o + nb * 16) = pack4(h[0], h[1], h[2], h[3]);
+    }
+  } else {
+    static_assert(COUT == 16, "a fused 1x1 layer reads 16 channels");
+    // this layer's activations are the B operand of the 1x1 layer as they are
+    uint16_t h[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) h[i] = f2bf(fmaxf(acc[0][i] + a.b[4 * kq + i], 0.f));
+    const bf16x4_t hv = pack4(h[0], h[1], h[2], h[3]);
+    constexpr int NB2 = (COUT2 + 15) / 16;
+#pragma unroll
+    for (int nb = 0; nb < NB2; ++nb) {
+      f32x4_t d = f32x4_t{0.f, 0.f, 0.f, 0.f};
+      d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.w2[nb * 64 + lane], hv, d, 0, 0, 0);
+      if (!pin) continue;
+      if (FUSE == FUSE_1X1_RELU) {
+        uint16_t q[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) q[i] = f2bf(fmaxf(d[i] + a.b2[nb * 16 + 4 * kq + i], 0.f));
+        *reinterpret_cast<bf16x4_t*>(a.out + ((size_t)y * a.Wo + px) * COUT2 + nb * 16 + 4 * kq) =
+            pack4(q[0], q[1], q[2], q[3]);
+      } else {
+        const size_t pl = (size_t)a.Ho * a.Wo, off = (size_t)y * a.Wo + px;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int c = nb * 16 + 4 * kq + i;
+          if (c < COUT2) a.outf[c * pl + off] = 1.f / (1.f + expf(-(d[i] + a.b2[c])));
+        }
+      }
+    }
+  }
+}
+
+// Packing: FP32 weight [cout][cin][k][k] -> fragments (tap, cin block,
+// cout block, lane) of 4 BF16, lane l holding output channel 16*nb + l%16
+// and input channels 16*cb + 4*(l/16) .. +3; zero in the padding.
+struct PackArgs {
+  const float* w;  // [cout][cin][ks][ks]
+  const float* b;  // [cout]
+  int cin, cout, ks, ncb, nb;
+  bf16x4_t* wp;    // fragments
+  float* bp;       // [16 * nb]
+};
+__global__ void pack_kernel(PackArgs p) {
+  const float* w = p.w;
+  const float* b = p.b;
+  const int cin = p.cin, cout = p.cout, ks = p.ks, ncb = p.ncb, nb = p.nb;
+  bf16x4_t* wp = p.wp;
+  float* bp = p.bp;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nfrag = ks * ks * ncb * nb * 64;
+  if (idx < nfrag) {
+    const int lane = idx % 64;
+    const int n = (idx / 64) % nb;
+    const int cb = (idx / 64 / nb) % ncb;
+    const int tap = idx / (64 * nb * ncb);
+    const int ky = tap / ks, kx = tap % ks;
+    const int co = n * 16 + lane % 16;
+    uint16_t h[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int ci = cb * 16 + 4 * (lane / 16) + j;
+      h[j] = (co < cout && ci < cin) ? f2bf(w[((co * cin + ci) * ks + ky) * ks + kx]) : (uint16_t)0;
+    }
+    wp[idx] = pack4(h[0], h[1], h[2], h[3]);
+  }
+  if (idx < nb * 16) bp[idx] = idx < cout ? bf2f(f2bf(b[idx])) : 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// Host side: layer table, packed-block and workspace layout, launches.
+
+struct Layer {
+  int cin, cout, k, stride;
+};
+constexpr Layer kLayers[12] = {
+    {11, 16, 3, 1},  // in3
+    {16, 16, 1, 1},  // in1
+    {16, 32, 3, 1},  // e1a
+    {32, 32, 3, 2},  // e1b
+    {32, 64, 3, 1},  // e2a
+    {64, 64, 3, 2},  // e2b
+    {96, 32, 3, 1},  // d1a
+    {32, 32, 3, 1},  // d1b
+    {48, 16, 3, 1},  // d0a
+    {16, 16, 3, 1},  // d0b
+    {16, 16, 3, 1},  // out3
+    {16, 4, 1, 1},   // out1
+};
+constexpr int pad16(int n) { return (n + 15) / 16 * 16; }
+inline size_t frag_count(const Layer& L) {
+  return (size_t)L.k * L.k * (pad16(L.cin) / 16) * (pad16(L.cout) / 16) * 64;
+}
+inline size_t packed_layer_bytes(const Layer& L) {
+  return frag_count(L) * sizeof(bf16x4_t) + pad16(L.cout) * sizeof(float);
+}
+inline size_t param_offset(int i) {
+  size_t o = 0;
+  for (int j = 0; j < i; ++j) o += (size_t)kLayers[j].cout * kLayers[j].cin * kLayers[j].k * kLayers[j].k + kLayers[j].cout;
+  return o;
+}
+inline size_t packed_offset(int i) {
+  size_t o = 0;
+  for (int j = 0; j < i; ++j) o += packed_layer_bytes(kLayers[j]);
+  return o;
+}
+inline const bf16x4_t* layer_w(const void* packed, int i) {
+  return reinterpret_cast<const bf16x4_t*>(static_cast<const char*>(packed) + packed_offset(i));
+}
+inline const float* layer_b(const void* packed, int i) {
+  return reinterpret_cast<const float*>(static_cast<const char*>(packed) + packed_offset(i) +
+                                        frag_count(kLayers[i]) * sizeof(bf16x4_t));
+}
+
+// Activation buffers in the workspace, in order: e0 (16, full), t1 (32,
+// full), e1 (32, half), t2 (64, half), e2 (64, quarter), t3 (32, half),
+// d1 (32, half), t4 (16, full), t5 (16, full).
+struct Grids {
+  int H, W, Hh, Wh, Hq, Wq;
+};
+inline Grids grids(int H, int W) {
+  Grids g{H, W, (H + 1) / 2, (W + 1) / 2, 0, 0};
+  g.Hq = (g.Hh + 1) / 2;
+  g.Wq = (g.Wh + 1) / 2;
+  return g;
+}
+inline size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+inline void act_layout(const Grids& g, size_t off[10]) {
+  const size_t full = (size_t)g.H * g.W * 2, half = (size_t)g.Hh * g.Wh * 2,
+               quarter = (size_t)g.Hq * g.Wq * 2;
+  const size_t sz[9] = {16 * full, 32 * full, 32 * half, 64 * half, 64 * quarter,
+                        32 * half, 32 * half, 16 * full, 16 * full};
+  off[0] = 0;
+  for (int i = 0; i < 9; ++i) off[i + 1] = off[i] + align256(sz[i]);
+}
+
+bool valid_dims(int H, int W) {
+  return H >= 1 && W >= 1 && H <= FLR_MAX_DIM && W <= FLR_MAX_DIM &&
+         (int64_t)H * W <= ((int64_t)1 << 28);
+}
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(a), b0 = reinterpret_cast<uintptr_t>(b);
+  return a0 < b0 + nb && b0 < a0 + na;
+}
+
+template <int CIN, int COUT, int KS, int ST, int IN, int CUP, int FUSE, int COUT2>
+hipError_t launch(const ConvArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((conv_kernel<CIN, COUT, KS, ST, IN, CUP, FUSE, COUT2>),
+                     dim3((a.Wo + 63) / 64, a.Ho), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace flrnet
+
+using namespace flrnet;
+
+extern "C" {
+
+size_t flr_net_num_params(void) { return param_offset(12); }
+
+size_t flr_net_packed_bytes(void) { return packed_offset(12); }
+
+flr_status flr_net_pack(const float* params, void* packed, void* stream) {
+  if (!params || !packed) return FLR_ERR_NULL;
+  if (!aligned16(params) || !aligned16(packed)) return FLR_ERR_ALIGN;
+  if (overlaps(params, flr_net_num_params() * sizeof(float), packed, flr_net_packed_bytes()))
+    return FLR_ERR_ALIAS;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  for (int i = 0; i < 12; ++i) {
+    const Layer& L = kLayers[i];
+    const float* w = params + param_offset(i);
+    const float* b = w + (size_t)L.cout * L.cin * L.k * L.k;
+    const int n = (int)frag_count(L);
+    const PackArgs pa = {w, b, L.cin, L.cout, L.k, pad16(L.cin) / 16, pad16(L.cout) / 16,
+                         const_cast<bf16x4_t*>(layer_w(packed, i)),
+                         const_cast<float*>(layer_b(packed, i))};
+    hipLaunchKernelGGL(pack_kernel, dim3((n + 255) / 256), dim3(256), 0, s, pa);
+    if (hipGetLastError() != hipSuccess) return FLR_ERR_HIP;
+  }
+  return FLR_OK;
+}
+
+size_t flr_net_workspace_bytes(int32_t height, int32_t width) {
+  if (!valid_dims(height, width)) return 0;
+  size_t off[10];
+  act_layout(grids(height, width), off);
+  return off[9];
+}
+
+flr_status flr_net_forward(int32_t height, int32_t width, const float* guides, const float* noisy,
+                           const void* packed, float* out, void* workspace, size_t workspace_bytes,
+                           void* stream) {
+  if (!valid_dims(height, width)) return FLR_ERR_SHAPE;
+  if (!guides || !noisy || !packed || !out) return FLR_ERR_NULL;
+  if (!aligned16(guides) || !aligned16(noisy) || !aligned16(packed) || !aligned16(out))
+    return FLR_ERR_ALIGN;
+  const size_t need = flr_net_workspace_bytes(height, width);
+  if (!workspace || workspace_bytes < need) return FLR_ERR_WORKSPACE;
+  if (!aligned16(workspace)) return FLR_ERR_ALIGN;
+  const size_t pb = (size_t)height * width * sizeof(float);
+  const size_t gb = FLR_NET_IN_GUIDES * pb, nb = FLR_NET_IN_NOISY * pb, ob = FLR_NET_OUT * pb;
+  const size_t kb = flr_net_packed_bytes();
+  if (overlaps(out, ob, guides, gb) || overlaps(out, ob, noisy, nb) || overlaps(out, ob, packed, kb) ||
+      overlaps(workspace, need, guides, gb) || overlaps(workspace, need, noisy, nb) ||
+      overlaps(workspace, need, packed, kb) || overlaps(workspace, need, out, ob))
+    return FLR_ERR_ALIAS;
+
+  const Grids g = grids(height, width);
+  size_t off[10];
+  act_layout(g, off);
+  char* ws = static_cast<char*>(workspace);
+  auto buf = [&](int i) { return reinterpret_cast<uint16_t*>(ws + off[i]); };
+  uint16_t *e0 = buf(0), *t1 = buf(1), *e1 = buf(2), *t2 = buf(3), *e2 = buf(4), *t3 = buf(5),
+           *d1 = buf(6), *t4 = buf(7), *t5 = buf(8);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  auto args = [&](int layer, int Hi, int Wi, int Ho, int Wo) {
+    ConvArgs a = {};
+    a.w = layer_w(packed, layer);
+    a.b = layer_b(packed, layer);
+    a.Hi = Hi;
+    a.Wi = Wi;
+    a.Ho = Ho;
+    a.Wo = Wo;
+    return a;
+  };
+  hipError_t e;
+  {  // in3 + in1: planar input -> e0
+    ConvArgs a = args(0, g.H, g.W, g.H, g.W);
+    a.g = guides;
+    a.y = noisy;
+    a.w2 = layer_w(packed, 1);
+    a.b2 = layer_b(packed, 1);
+    a.out = e0;
+    if ((e = launch<16, 16, 3, 1, IN_PLANAR, 0, FUSE_1X1_RELU, 16>(a, s)) != hipSuccess) return FLR_ERR_HIP;
+  }
+  {  // e1a
+    ConvArgs a = args(2, g.H, g.W, g.H, g.W);
+    a.in0 = e0;
+    a.out = t1;
+    if ((e = launch<16, 32, 3, 1, IN_HWC, 0, FUSE_NONE, 0>(a, s)) != hipSuccess) return FLR_ERR_HIP;
+  }
+  {  // e1b (stride 2)
+    ConvArgs a = args(3, g.H, g.W, g.Hh, g.Wh);
+    a.in0 = t1;
+    a.out = e1;
+    if ((e = launch<32, 32, 3, 2, IN_HWC, 0, FUSE_NONE, 0>(a, s)) != hipSuccess) return FLR_ERR_HIP;
+  }
+  {  // e2a
+    ConvArgs a = args(4, g.Hh, g.Wh, g.Hh, g.Wh);
+    a.in0 = e1;
+    a.out = t2;
+    if ((e = launch<32, 64, 3, 1, IN_HWC, 0, FUSE_NONE, 0>(a, s)) != hipSuccess) return FLR_ERR_HIP;
+  }
+  {  // e2b (stride 2)
+    ConvArgs a = args(5, g.Hh, g.Wh, g.Hq, g.Wq);
+    a.in0 = t2;
+    a.out = e2;
+    if ((e = launch<64, 64, 3, 2, IN_HWC, 0, FUSE_NONE, 0>(a, s)) != hipSuccess) return FLR_ERR_HIP;
+  }
+  {  // d1a: [up2(e2), e1]
+    ConvArgs a = args(6, g.Hh, g.Wh, g.Hh, g.Wh);
+    a.in0 = e2;
+    a.Hl = g.Hq;
+    a.Wl = g.Wq;
+    a.in1 = e1;
+    a.out = t3;
+    if ((e = launch<96, 32, 3, 1, IN_UPCAT, 64, FUSE_NONE, 0>(a, s)) != hipSuccess) return FLR_ERR_HIP;
+  }
+  {  // d1b
+    ConvArgs a = args(7, g.Hh, g.Wh, g.Hh, g.Wh);
+    a.in0 = t3;
+    a.out = d1;
+    if ((e = launch<32, 32, 3, 1, IN_HWC, 0, FUSE_NONE, 0>(a, s)) != hipSuccess) return FLR_ERR_HIP;
+  }
+  {  // d0a: [up2(d1), e0]
+    ConvArgs a = args(8, g.H, g.W, g.H, g.W);
+    a.in0 = d1;
+    a.Hl = g.Hh;
+    a.Wl = g.Wh;
+    a.in1 = e0;
+    a.out = t4;
+    if ((e = launch<48, 16, 3, 1, IN_UPCAT, 32, FUSE_NONE, 0>(a, s)) != hipSuccess) return FLR_ERR_HIP;
+  }
+  {  // d0b
+    ConvArgs a = args(9, g.H, g.W, g.H, g.W);
+    a.in0 = t4;
+    a.out = t5;
+    if ((e = launch<16, 16, 3, 1, IN_HWC, 0, FUSE_NONE, 0>(a, s)) != hipSuccess) return FLR_ERR_HIP;
+  }
+  {  // out3 + out1 (sigmoid) -> planar FP32
+    ConvArgs a = args(10, g.H, g.W, g.H, g.W);
+    a.in0 = t5;
+    a.w2 = layer_w(packed, 11);
+    a.b2 = layer_b(packed, 11);
+    a.outf = out;
+    if ((e = launch<16, 16, 3, 1, IN_HWC, 0, FUSE_1X1_SIGMOID, FLR_NET_OUT>(a, s)) != hipSuccess)
+      return FLR_ERR_HIP;
+  }
+  return FLR_OK;
+}
+
+size_t flr_flnr_workspace_bytes(const flr_params* p) {
+  if (!p || flr_validate_params(p) != FLR_OK) return 0;
+  if (p->num_guides != FLR_NET_IN_GUIDES + FLR_NET_OUT || p->num_channels != FLR_NET_IN_NOISY)
+    return 0;
+  return align256(flr_denoise_workspace_bytes(p)) + flr_net_workspace_bytes(p->height, p->width);
+}
+
+flr_status flr_flnr_denoise(const flr_params* p, float* guides12, const float* noisy,
+                            const void* packed, float* out, void* workspace,
+                            size_t workspace_bytes, void* stream) {
+  flr_status st = flr_validate_params(p);
+  if (st != FLR_OK) return st;
+  if (p->num_guides != FLR_NET_IN_GUIDES + FLR_NET_OUT || p->num_channels != FLR_NET_IN_NOISY)
+    return FLR_ERR_CHANNELS;
+  if (p->flags & FLR_FLAG_RAW_MOMENTS) return FLR_ERR_MODE;
+  if (!guides12 || !noisy || !packed || !out) return FLR_ERR_NULL;
+  const size_t need = flr_flnr_workspace_bytes(p);
+  if (!workspace || workspace_bytes < need) return FLR_ERR_WORKSPACE;
+  const size_t pl = (size_t)p->height * p->width;
+  const size_t fw = align256(flr_denoise_workspace_bytes(p));
+  char* ws = static_cast<char*>(workspace);
+  st = flr_net_forward(p->height, p->width, guides12, noisy, packed,
+                       guides12 + FLR_NET_IN_GUIDES * pl, ws + fw, need - fw, stream);
+  if (st != FLR_OK) return st;
+  return flr_denoise(p, guides12, noisy, out, fw ? ws : nullptr, fw, stream);
+}
+
+}  // extern "C"

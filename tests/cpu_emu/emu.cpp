@@ -67,6 +67,7 @@ struct Lane {
   ucontext_t ctx;
   LaneState state;
   unsigned dpp_calls;
+  unsigned mfma_calls;
   char* stack;  // kStackBytes above one guard page
 };
 
@@ -76,6 +77,7 @@ struct Workgroup {
   std::vector<Lane> lanes;
   unsigned cur = 0;
   int dpp[2][1024];
+  uint16_t mfa[2][1024][4], mfb[2][1024][4];
   std::function<void()> body;
 
   Workgroup() : lanes(1024) {
@@ -102,7 +104,7 @@ struct Workgroup {
   static void entry();
 
   // Runs `n` lanes of block `b` to completion; false on a barrier mismatch.
-  bool run(unsigned n, unsigned b, char* err, size_t errn) {
+  bool run(unsigned n, dim3 b, char* err, size_t errn) {
     for (unsigned t = 0; t < n; ++t) {
       Lane& l = lanes[t];
       getcontext(&l.ctx);
@@ -112,8 +114,9 @@ struct Workgroup {
       makecontext(&l.ctx, entry, 0);
       l.state = READY;
       l.dpp_calls = 0;
+      l.mfma_calls = 0;
     }
-    blockIdx = dim3(b);
+    blockIdx = b;
     for (;;) {
       for (unsigned t = 0; t < n; ++t) {
         if (lanes[t].state != READY) continue;
@@ -143,8 +146,8 @@ struct Workgroup {
         continue;
       }
       std::snprintf(err, errn,
-                    "block %u: lanes diverged at barriers (%u done, %u at the workgroup barrier)",
-                    b, done, at_block);
+                    "block (%u,%u): lanes diverged at barriers (%u done, %u at the workgroup "
+                    "barrier)", b.x, b.y, done, at_block);
       return false;
     }
   }
@@ -200,6 +203,34 @@ unsigned __builtin_amdgcn_raw_buffer_load_b32(__amdgpu_buffer_rsrc_t r, int vo, 
   return v;
 }
 
+emu_f32x4 __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(emu_bf16x4 a, emu_bf16x4 b, emu_f32x4 c, int,
+                                                    int, int) {
+  Workgroup* wg = t_wg;
+  const unsigned t = wg->cur, w0 = t / kWave * kWave, l = t % kWave;
+  const unsigned slot = wg->lanes[t].mfma_calls++ & 1u;
+  for (int j = 0; j < 4; ++j) {
+    wg->mfa[slot][t][j] = (uint16_t)a[j];
+    wg->mfb[slot][t][j] = (uint16_t)b[j];
+  }
+  wg->park(AT_WAVE_BARRIER);
+  auto bf = [](uint16_t h) {
+    const uint32_t u = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &u, sizeof f);
+    return (double)f;
+  };
+  emu_f32x4 d;
+  const unsigned n = l % 16;
+  for (int i = 0; i < 4; ++i) {
+    const unsigned m = 4 * (l / 16) + i;
+    double acc = c[i];
+    for (unsigned k = 0; k < 16; ++k)
+      acc += bf(wg->mfa[slot][w0 + m + 16 * (k / 4)][k % 4]) * bf(wg->mfb[slot][w0 + n + 16 * (k / 4)][k % 4]);
+    d[i] = (float)acc;
+  }
+  return d;
+}
+
 namespace flr {
 constexpr size_t kEmuLdsFloats = 163840 / 4 + 4096;
 alignas(64) thread_local float lds[kEmuLdsFloats];
@@ -207,8 +238,8 @@ alignas(64) thread_local float lds[kEmuLdsFloats];
 
 static const uint32_t kCanary = 0x7fc0dead;
 
-template <typename A>
-void emu_launch_kernel(void (*k)(A), dim3 grid, dim3 block, size_t lds_bytes, hipStream_t, A a) {
+void emu_launch_erased(void (*tramp)(const void*, const void*), const void* kernel,
+                       const void* arg, dim3 grid, dim3 block, size_t lds_bytes) {
   if (lds_bytes > 163840 || block.x == 0 || block.x > 1024) {
     set_error(hipErrorInvalidValue, "bad launch shape");
     return;
@@ -221,13 +252,13 @@ void emu_launch_kernel(void (*k)(A), dim3 grid, dim3 block, size_t lds_bytes, hi
   auto worker = [&]() {
     Workgroup wg;
     t_wg = &wg;
-    wg.body = [&]() { k(a); };
+    wg.body = [&]() { tramp(kernel, arg); };
     char err[200];
-    for (unsigned b; !failed && (b = next++) < grid.x;) {
+    for (unsigned b; !failed && (b = next++) < grid.x * grid.y;) {
       uint32_t* w = reinterpret_cast<uint32_t*>(flr::lds);
       for (size_t i = 0; i < used; ++i) w[i] = 0x7fc00000u;  // quiet NaN
       for (size_t i = used; i < flr::kEmuLdsFloats; ++i) w[i] = kCanary;
-      if (!wg.run(block.x, b, err, sizeof err)) {
+      if (!wg.run(block.x, dim3(b % grid.x, b / grid.x), err, sizeof err)) {
         set_error(hipErrorLaunchFailure, err);
         failed = true;
         break;
@@ -245,7 +276,7 @@ void emu_launch_kernel(void (*k)(A), dim3 grid, dim3 block, size_t lds_bytes, hi
     t_wg = nullptr;
   };
   const unsigned hw = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
-  const unsigned nt = std::min(hw, grid.x);
+  const unsigned nt = std::min(hw, grid.x * grid.y);
   std::vector<std::thread> ts;
   for (unsigned i = 0; i < nt; ++i) ts.emplace_back(worker);
   for (auto& th : ts) th.join();

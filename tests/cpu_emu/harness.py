@@ -33,16 +33,18 @@ from paper_2410_11625_amd._lib import FlrParams  # noqa: E402  (ctypes struct la
 
 def build(force: bool = False) -> str:
     srcs = [os.path.join(HERE, "emu.cpp"), os.path.join(CSRC, "flr_api.cpp")]
-    deps = srcs + [os.path.join(HERE, "hip", "hip_runtime.h"),
+    net_src = os.path.join(CSRC, "flr_net.hip")
+    deps = srcs + [net_src, os.path.join(HERE, "hip", "hip_runtime.h"),
                    os.path.join(CSRC, "flr_device.hpp"), os.path.join(CSRC, "flr_launch.hpp"),
-                   os.path.join(INCLUDE, "flr.h")]
+                   os.path.join(INCLUDE, "flr.h"), os.path.join(INCLUDE, "flr_net.h")]
     if not force and os.path.exists(SO) and \
             os.path.getmtime(SO) >= max(os.path.getmtime(d) for d in deps):
         return SO
     os.makedirs(BUILD, exist_ok=True)
     defs = [f"-D{d}" for d in VARIANT.split(",") if d]
     cmd = ["g++", "-std=c++20", "-O1", "-g", "-pthread", "-fno-extern-tls-init", "-shared", "-fPIC", *defs,
-           f"-I{HERE}", f"-I{INCLUDE}", f"-I{CSRC}", *srcs, "-o", SO + ".tmp"]
+           f"-I{HERE}", f"-I{INCLUDE}", f"-I{CSRC}", *srcs, "-x", "c++", net_src,
+           "-o", SO + ".tmp"]
     subprocess.run(cmd, check=True)
     os.replace(SO + ".tmp", SO)
     return SO
@@ -102,6 +104,30 @@ class Emu:
         self.check(self.L.flr_denoise(ctypes.byref(p), gp, yp, op, wp, need, None), "flr_denoise")
         return out.copy()
 
+    def net(self, guides, noisy, params):
+        """The guide network: FP32 parameters -> packed, then forward -> [4,H,W]."""
+        L = self.L
+        vp = ctypes.c_void_p
+        L.flr_net_num_params.restype = ctypes.c_size_t
+        L.flr_net_packed_bytes.restype = ctypes.c_size_t
+        L.flr_net_workspace_bytes.restype = ctypes.c_size_t
+        L.flr_net_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        L.flr_net_pack.argtypes = [vp, vp, vp]
+        L.flr_net_forward.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp,
+                                      ctypes.c_size_t, vp]
+        _, H, W = guides.shape
+        pp, _ = self.buf(params)
+        kb = int(L.flr_net_packed_bytes())
+        kp, _ = self.buf(shape=(kb // 4,))
+        self.check(L.flr_net_pack(pp, kp, None), "flr_net_pack")
+        gp, _ = self.buf(guides)
+        yp, _ = self.buf(noisy)
+        op, out = self.buf(shape=(4, H, W))
+        need = int(L.flr_net_workspace_bytes(H, W))
+        wp, _ = self.buf(shape=(need // 4,))
+        self.check(L.flr_net_forward(H, W, gp, yp, kp, op, wp, need, None), "flr_net_forward")
+        return out.copy()
+
     def moments(self, noisy, guides, p: FlrParams):
         Q, H, W = guides.shape
         C = noisy.shape[0]
@@ -155,6 +181,16 @@ def run_case(spec: dict) -> dict:
             want = np.stack(want)
             return {"exact": bool(np.array_equal(got.astype(np.float64), want)),
                     "maxabs": float(np.max(np.abs(got - want)))}
+        if kind == "net":
+            from oracle import net_ref
+            from synth.net_weights import flatten_net_weights, make_net_weights
+            fr = make_config(1, h=H, w=W)
+            wts = make_net_weights(spec.get("seed", 2))
+            got = emu.net(fr["guides"], fr["noisy"], flatten_net_weights(wts))
+            want = net_ref.net_forward(fr["guides"], fr["noisy"], wts)
+            d = np.abs(got - want)
+            return {"maxabs": float(d.max()), "median": float(np.median(d)),
+                    "within": float(np.mean(d <= 2e-3)), "shape": list(got.shape)}
         if spec.get("frame") == "config":
             fr = make_config(spec["config"], h=H, w=W)
         else:

@@ -79,6 +79,15 @@ unsigned __builtin_amdgcn_raw_buffer_load_b32(__amdgpu_buffer_rsrc_t r, int vo, 
 
 inline void __builtin_amdgcn_sched_barrier(int) {}
 
+// v_mfma_f32_16x16x16_bf16 of a 64-lane wavefront: D = C + A B with A 16x16
+// (lane l: row l%16, k = 4*(l/16)..+3), B 16x16 (lane l: k = 4*(l/16)..+3,
+// column l%16), C/D (lane l: rows 4*(l/16)..+3, column l%16). Every lane of
+// the wavefront must call it at the same point.
+typedef short emu_bf16x4 __attribute__((vector_size(8)));
+typedef float emu_f32x4 __attribute__((vector_size(16)));
+emu_f32x4 __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(emu_bf16x4 a, emu_bf16x4 b, emu_f32x4 c, int,
+                                                    int, int);
+
 // DPP lane move of a 64-lane wavefront (row_shr:1..15, wave_shr:1,
 // row_bcast:15, row_bcast:31); every lane of the wavefront must call it at the same point.
 int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask,
@@ -93,9 +102,18 @@ enum hipFuncAttribute { hipFuncAttributeMaxDynamicSharedMemorySize = 0 };
 inline hipError_t hipFuncSetAttribute(const void*, hipFuncAttribute, int) { return hipSuccess; }
 hipError_t hipGetLastError();
 
-// Runs kernel `k` over the grid on host threads (defined by the emulator).
+// Runs a kernel over the grid on host threads (defined by the emulator):
+// `tramp(kernel, arg)` executes one lane.
+void emu_launch_erased(void (*tramp)(const void*, const void*), const void* kernel,
+                       const void* arg, dim3 grid, dim3 block, size_t lds_bytes);
 template <typename A>
-void emu_launch_kernel(void (*k)(A), dim3 grid, dim3 block, size_t lds_bytes, hipStream_t, A a);
+void emu_launch_kernel(void (*k)(A), dim3 grid, dim3 block, size_t lds_bytes, hipStream_t, A a) {
+  emu_launch_erased(
+      [](const void* kf, const void* ap) {
+        reinterpret_cast<void (*)(A)>(const_cast<void*>(kf))(*static_cast<const A*>(ap));
+      },
+      reinterpret_cast<const void*>(k), &a, grid, block, lds_bytes);
+}
 
 #define hipLaunchKernelGGL(kernel, grid, block, lds, stream, ...) \
   emu_launch_kernel(kernel, dim3(grid), dim3(block), (size_t)(lds), (hipStream_t)(stream), __VA_ARGS__)

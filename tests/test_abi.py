@@ -1,6 +1,7 @@
 """The C ABI library: it loads, exports every declared entry point, and
 rejects bad arguments on the host before any HIP call (no GPU needed)."""
 import ctypes
+import glob
 import os
 import re
 
@@ -24,13 +25,41 @@ def L():
     return _lib.lib()
 
 
-def test_header_declares_what_the_library_exports(L):
-    hdr = open(os.path.join(ROOT, "include", "flr.h")).read()
-    declared = set(re.findall(r"^\s*(?:const char\*|size_t|flr_status)\s+(flr_\w+)\s*\(", hdr,
-                              re.M))
+def test_headers_declare_what_the_library_exports(L):
+    declared = set()
+    for h in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))):
+        hdr = open(h).read()
+        declared |= set(re.findall(r"^\s*(?:const char\*|size_t|flr_status)\s+(flr_\w+)\s*\(",
+                                   hdr, re.M))
     assert declared == set(_lib.EXPORTED)
     for name in declared:
         assert hasattr(L, name), name
+
+
+def test_net_parameter_count_and_sizes(L):
+    from synth.net_weights import flatten_net_weights, make_net_weights
+    assert L.flr_net_num_params() == flatten_net_weights(make_net_weights(2)).size
+    assert L.flr_net_packed_bytes() % 16 == 0 and L.flr_net_packed_bytes() > 0
+    assert L.flr_net_workspace_bytes(0, 5) == 0 and L.flr_net_workspace_bytes(5, 40000) == 0
+    # 9 BF16 activation buffers: 124 channel-bytes/2 per full-resolution pixel (rounded up)
+    assert L.flr_net_workspace_bytes(64, 64) >= 64 * 64 * 2 * 124
+    p = FlrParams(height=32, width=32, num_guides=12, num_channels=3, radius=8, eps=1e-3,
+                  eps_mul=0.0, reg_mode=0, average_coeffs=1, fused=2, flags=0, tile_rows=0)
+    assert L.flr_flnr_workspace_bytes(ctypes.byref(p)) >= L.flr_net_workspace_bytes(32, 32)
+    p.num_guides = 8
+    assert L.flr_flnr_workspace_bytes(ctypes.byref(p)) == 0
+
+
+def test_net_entry_points_validate_before_launch(L):
+    buf = ctypes.create_string_buffer(64)
+    a16 = ctypes.addressof(buf) + (-ctypes.addressof(buf)) % 16
+    assert L.flr_net_pack(None, a16, None) == 1                       # FLR_ERR_NULL
+    assert L.flr_net_pack(a16 + 4, a16 + 4, None) == 7                # FLR_ERR_ALIGN
+    assert L.flr_net_forward(0, 8, a16, a16, a16, a16, a16, 64, None) == 2   # FLR_ERR_SHAPE
+    assert L.flr_net_forward(8, 8, a16, a16, a16, a16, a16, 0, None) == 8    # FLR_ERR_WORKSPACE
+    p = FlrParams(height=8, width=8, num_guides=8, num_channels=3, radius=2, eps=1e-3,
+                  eps_mul=0.0, reg_mode=0, average_coeffs=1, fused=2, flags=0, tile_rows=0)
+    assert L.flr_flnr_denoise(ctypes.byref(p), a16, a16, a16, a16, a16, 64, None) == 5  # CHANNELS
 
 
 def test_params_struct_layout_matches_header():

@@ -51,3 +51,13 @@ def test_emulated_stages_match_oracle():
     assert res["moments_err"] < 1e-6
     assert res["solve_err"] < 1e-5
     assert res["apply_err"] < 1e-5
+
+
+# The guide network's kernels (MFMA emulated per the 16x16x16 BF16 lane layout)
+# against the FP64 network oracle with its BF16 rounding points.
+@pytest.mark.parametrize("H,W", [(20, 70), (33, 131), (1, 1), (7, 3)])
+def test_emulated_net_matches_oracle(H, W):
+    res = run_in_subprocess(dict(kind="net", H=H, W=W, Q=8, C=3, r=0))
+    assert res["shape"] == [4, H, W]
+    # criteria and their reasons: tests/test_gpu_net.py
+    assert res["median"] <= 1e-5 and res["within"] >= 0.99 and res["maxabs"] <= 2e-2, res

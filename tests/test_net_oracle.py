@@ -101,6 +101,8 @@ def _frame(H, W, seed):
 
 @pytest.mark.parametrize("H,W", [(16, 24), (13, 21), (1, 1), (2, 3)])
 def test_output_shape_and_range(H, W):
+    """Sigmoid outputs lie in (0, 1); odd sizes go through the stride-2 and
+    upsampling steps."""
     g, y = _frame(H, W, H + W)
     out = net_ref.net_forward(g, y, make_net_weights(2))
     assert out.shape == (4, H, W)
@@ -108,12 +110,13 @@ def test_output_shape_and_range(H, W):
 
 
 def test_bias_free_network_is_positively_homogeneous():
-    """Without biases a ReLU network satisfies f(2x) = 2 f(x); scaling by two
-    also commutes with BF16 rounding, so the logits match exactly."""
+    """Without biases the layers form a ReLU network, which satisfies
+    f(2x) = 2 f(x); scaling by two also commutes with BF16 rounding, so the
+    logits match exactly (input compression bypassed)."""
     g, y = _frame(20, 28, 5)
     wts = make_net_weights(2, zero_bias=True)
-    z1 = net_ref.net_forward(g, y, wts, logits=True)
-    z2 = net_ref.net_forward(2 * g, 2 * y, wts, logits=True)
+    z1 = net_ref.net_forward(g, y, wts, logits=True, compress=False)
+    z2 = net_ref.net_forward(2 * g, 2 * y, wts, logits=True, compress=False)
     assert np.array_equal(z2, 2 * z1)
 
 
@@ -201,3 +204,19 @@ def _upsample_shifted(x, H, W):
 def test_planted_net_mistake_is_caught(monkeypatch, name, fn):
     monkeypatch.setattr(net_ref, name, fn)
     assert not _net_battery()
+
+
+def test_input_compression():
+    """Scaling the inputs changes the output (the compression is not linear),
+    and the compression maps v to sign(v) log(1 + |v|) before BF16 rounding:
+    an input of e - 1 reaches the first layer as exactly 1."""
+    g, y = _frame(12, 12, 13)
+    wts = make_net_weights(2, zero_bias=True)
+    z1 = net_ref.net_forward(g, y, wts, logits=True)
+    z2 = net_ref.net_forward(2 * g, 2 * y, wts, logits=True)
+    assert not np.allclose(z2, 2 * z1)
+    g1 = np.full_like(g, np.e - 1.0)
+    y1 = np.full_like(y, np.e - 1.0)
+    assert np.array_equal(net_ref.net_forward(g1, y1, wts, logits=True),
+                          net_ref.net_forward(np.ones_like(g), np.ones_like(y), wts, logits=True,
+                                              compress=False))
