@@ -159,6 +159,62 @@ def summarize_counters(fetch_csv: str, write_csv: str, path_name: str) -> int:
     return 0
 
 
+def time_flnr(flr, torch, np, sets, nsets, dev, stream, args):
+    """FLNR per frame: guide network (BF16 MFMA) then two-pass FLR over the 8
+    input guides and the network's 4. Events around each part; the 12-guide
+    buffers hold the input guides in planes 0..7 (resident before timing)."""
+    from synth.net_weights import flatten_net_weights, make_net_weights
+    packed = flr.net_pack(torch.from_numpy(flatten_net_weights(make_net_weights(2))).to(dev))
+    g12s = []
+    for k in range(nsets):
+        g12 = torch.empty((12, H, W), dtype=torch.float32, device=dev)
+        g12[:8] = sets[k][1]
+        g12s.append(g12)
+    p = flr.make_params(H, W, 12, C, R, eps=EPS, average=True, fused="two_pass")
+    nws = torch.empty(int(flr.api.lib().flr_net_workspace_bytes(H, W)), dtype=torch.uint8,
+                      device=dev)
+    coeffs = torch.empty((flr.num_coeff_planes(12, C), H, W), dtype=torch.float32, device=dev)
+
+    def step(k, evs=None):
+        noisy, guides, out = sets[k % nsets]
+        g12 = g12s[k % nsets]
+        if evs is not None:
+            evs[0].record(stream)
+        flr.net_forward(guides, noisy, packed, out=g12[8:], workspace=nws)
+        if evs is not None:
+            evs[1].record(stream)
+        flr.coefficients(g12, noisy, R, eps=EPS, out=coeffs)
+        flr.apply(g12, coeffs, R, average=True, out=out)
+        if evs is not None:
+            evs[2].record(stream)
+
+    for k in range(3):
+        step(k)
+    torch.cuda.synchronize()
+    ev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3))
+          for _ in range(args.flnr_steps)]
+    for k in range(args.flnr_steps):
+        step(k, ev[k])
+    torch.cuda.synchronize()
+    per = np.array([a.elapsed_time(c) for a, b, c in ev])
+    net = np.array([a.elapsed_time(b) for a, b, c in ev])
+    ms = float(np.mean(per))
+    # multiply-adds per full-resolution pixel, layer by layer (half-resolution
+    # layers count 1/4, quarter-resolution 1/16; exact for 1920x1080)
+    macs = (11 * 16 * 9 + 16 * 16 + 16 * 32 * 9 + 32 * 32 * 9 / 4 + 32 * 64 * 9 / 4
+            + 64 * 64 * 9 / 16 + 96 * 32 * 9 / 4 + 32 * 32 * 9 / 4 + 48 * 16 * 9
+            + 16 * 16 * 9 + 16 * 16 * 9 + 16 * 4)
+    net_flop = 2 * macs * H * W
+    return {"ms_per_frame": round(ms, 5), "value": round(H * W / (ms / 1e3) / 1e6, 2),
+            "unit": "Mpixel/s", "net_ms": round(float(np.mean(net)), 5),
+            "regression_ms": round(float(np.mean(per - net)), 5),
+            "net_tflops": round(net_flop / (float(np.mean(net)) / 1e3) / 1e12, 2),
+            "net_mfma_frac_bf16": round(net_flop / (float(np.mean(net)) / 1e3) / 2.5e15, 4),
+            "config": "guide net 11->4 channels (16/32/64, BF16 weights and activations, FP32 "
+                      "accumulation) + FLR over 12 guides, r 8, eps 1e-3, two-pass",
+            "steps": args.flnr_steps}
+
+
 def cpu_baseline():
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
@@ -185,6 +241,8 @@ def main(argv=None):
     ap.add_argument("--path", default="two_pass", choices=["two_pass", "fused", "stages"],
                     help="flr_denoise execution path to time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-flnr", action="store_true", help="skip the FLNR timing")
+    ap.add_argument("--flnr-steps", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter reference)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -291,6 +349,13 @@ def main(argv=None):
     achieved = dom_flops / (dom_ms / 1e3) / 1e12
     hbm_gbps = dom_bytes / (dom_ms / 1e3) / 1e9
 
+    # FLNR (the guide network, then FLR over 12 guides) on the same frames,
+    # with the network's parameters drawn as in the workload definition
+    flnr = None
+    if not args.no_flnr:
+        flnr = time_flnr(flr, torch, np, sets, nsets, dev, stream, args)
+        flnr["vs_flr_ms"] = round(flnr["ms_per_frame"] - ms_per_step, 5)
+
     if args.copy_calibration:
         src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -345,6 +410,7 @@ def main(argv=None):
                      "hbm_algo_GBps": round(hbm_gbps, 1),
                      "hbm_frac": round(hbm_gbps / PEAK_HBM_GBPS, 4)},
         "cpu_baseline": cpu,
+        "flnr": flnr,
     }
     print(json.dumps(line))
     return 0

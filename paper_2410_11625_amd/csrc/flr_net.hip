@@ -26,14 +26,12 @@ namespace flrnet {
 typedef short bf16x4_t __attribute__((vector_size(8)));
 typedef float f32x4_t __attribute__((vector_size(16)));
 
-enum InKind : int { IN_HWC = 0, IN_PLANAR = 1, IN_UPCAT = 2 };
+enum InKind : int { IN_HWC = 0, IN_UPCAT = 2 };
 enum Fuse : int { FUSE_NONE = 0, FUSE_1X1_RELU = 1, FUSE_1X1_SIGMOID = 2 };
 
 struct ConvArgs {
   const uint16_t* in0;  // HWC BF16 input (IN_UPCAT: the low-resolution part)
   const uint16_t* in1;  // IN_UPCAT: the skip connection, on the conv's input grid
-  const float* g;       // IN_PLANAR: guides [8][Hi][Wi]
-  const float* y;       // IN_PLANAR: noisy [3][Hi][Wi]
   const bf16x4_t* w;    // packed weight fragments of the layer
   const float* b;       // BF16-rounded bias (padded output channels)
   const bf16x4_t* w2;   // fused 1x1 layer
@@ -62,67 +60,69 @@ __device__ __forceinline__ bf16x4_t pack4(uint16_t a, uint16_t b, uint16_t c, ui
   return v;
 }
 
-// Four consecutive input channels c..c+3 of input pixel (yi, xi); zero when
-// !ok (padding).
-template <int CIN, int CUP, int IN>
-__device__ __forceinline__ bf16x4_t load_in(const ConvArgs& a, int yi, int xi, int c, bool ok) {
-  if (!ok) return pack4(0, 0, 0, 0);
-  if (IN == IN_HWC) {
-    return *reinterpret_cast<const bf16x4_t*>(a.in0 + ((size_t)yi * a.Wi + xi) * CIN + c);
-  } else if (IN == IN_UPCAT) {
-    if (c < CUP)
-      return *reinterpret_cast<const bf16x4_t*>(a.in0 + ((size_t)(yi >> 1) * a.Wl + (xi >> 1)) * CUP + c);
+// Four consecutive input channels c..c+3 of input pixel (yi, xi), which
+// the caller has clamped into the input grid; the caller zeroes padding.
+// CB: the 16-channel block (compile-time, so the source choice folds);
+// c4 = 4 * (lane / 16), the lane's channel quad within the block.
+template <int CIN, int CUP, int IN, int CB>
+__device__ __forceinline__ bf16x4_t load_in(const ConvArgs& a, int yi, int xi, int c4) {
+  constexpr int c0 = CB * 16;
+  if constexpr (IN == IN_UPCAT && c0 < CUP)
+    return *reinterpret_cast<const bf16x4_t*>(a.in0 + ((size_t)(yi >> 1) * a.Wl + (xi >> 1)) * CUP +
+                                              c0 + c4);
+  else if constexpr (IN == IN_UPCAT)
     return *reinterpret_cast<const bf16x4_t*>(a.in1 + ((size_t)yi * a.Wi + xi) * (CIN - CUP) +
-                                              (c - CUP));
-  } else {
-    const size_t pl = (size_t)a.Hi * a.Wi, off = (size_t)yi * a.Wi + xi;
-    uint16_t h[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int cc = c + j;
-      const float v = cc < FLR_NET_IN_GUIDES ? a.g[cc * pl + off]
-                    : (cc < FLR_NET_IN_GUIDES + FLR_NET_IN_NOISY ? a.y[(cc - FLR_NET_IN_GUIDES) * pl + off] : 0.f);
-      h[j] = f2bf(copysignf(log1pf(fabsf(v)), v));  // input compression
-    }
-    return pack4(h[0], h[1], h[2], h[3]);
+                                              (c0 - CUP) + c4);
+  else
+    return *reinterpret_cast<const bf16x4_t*>(a.in0 + ((size_t)yi * a.Wi + xi) * CIN + c0 + c4);
+}
+
+// All NCB channel blocks of one input pixel (zero where !ok).
+template <int CIN, int CUP, int IN, int NCB, int CB = 0>
+__device__ __forceinline__ void load_blocks(const ConvArgs& a, int yi, int xi, int c4, bool ok,
+                                            bf16x4_t (&dst)[NCB]) {
+  if constexpr (CB < NCB) {
+    const bf16x4_t v = load_in<CIN, CUP, IN, CB>(a, yi, xi, c4);
+    dst[CB] = ok ? v : pack4(0, 0, 0, 0);
+    load_blocks<CIN, CUP, IN, NCB, CB + 1>(a, yi, xi, c4, ok, dst);
   }
+}
+
+// Network input: the 8 guides and 3 noisy planes (planar FP32) of one pixel,
+// each compressed to sign(v) log(1 + |v|), rounded to BF16 and written as
+// one HWC row of 16 channels (the last 5 zero).
+struct PrepArgs {
+  const float* g;
+  const float* y;
+  uint16_t* out;
+  int H, W;
+};
+__global__ void __launch_bounds__(256) prep_kernel(PrepArgs a) {
+  const size_t pl = (size_t)a.H * a.W;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= pl) return;
+  uint16_t h[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    float v = 0.f;
+    if (c < FLR_NET_IN_GUIDES) v = a.g[c * pl + i];
+    else if (c < FLR_NET_IN_GUIDES + FLR_NET_IN_NOISY) v = a.y[(c - FLR_NET_IN_GUIDES) * pl + i];
+    h[c] = f2bf(copysignf(log1pf(fabsf(v)), v));
+  }
+  bf16x4_t* o = reinterpret_cast<bf16x4_t*>(a.out + i * 16);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) o[q] = pack4(h[4 * q], h[4 * q + 1], h[4 * q + 2], h[4 * q + 3]);
 }
 
 // One conv layer (CIN, COUT multiples of 16; KS 1 or 3; stride ST), bias and
 // ReLU, optionally followed by a fused 1x1 layer to COUT2 channels (ReLU to
 // HWC BF16, or sigmoid to planar FP32).
-template <int CIN, int COUT, int KS, int ST, int IN, int CUP, int FUSE, int COUT2>
-__global__ void __launch_bounds__(256) conv_kernel(ConvArgs a) {
-  constexpr int NCB = CIN / 16, NB = COUT / 16, P = KS / 2;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int y = blockIdx.y;
-  const int px = blockIdx.x * 64 + wv * 16 + (lane & 15);
-  const int kq = lane >> 4;
-  const bool pin = px < a.Wo;
-  f32x4_t acc[NB];
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-
-#pragma unroll
-  for (int ky = 0; ky < KS; ++ky) {
-    const int yi = y * ST + ky - P;
-    const bool oky = yi >= 0 && yi < a.Hi;
-#pragma unroll
-    for (int kx = 0; kx < KS; ++kx) {
-      const int xi = px * ST + kx - P;
-      const bool ok = pin && oky && xi >= 0 && xi < a.Wi;
-#pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) {
-        const bf16x4_t bv = load_in<CIN, CUP, IN>(a, yi, xi, cb * 16 + 4 * kq, ok);
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          const bf16x4_t av = a.w[(((ky * KS + kx) * NCB + cb) * NB + nb) * 64 + lane];
-          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[nb], 0, 0, 0);
-        }
-      }
-    }
-  }
-
+// Bias, ReLU and store of one tile (lane l: channels 4*(l/16)..+3 of each
+// 16-channel block, pixel px), or the fused 1x1 layer on those activations.
+template <int COUT, int FUSE, int COUT2>
+__device__ __forceinline__ void epilogue(const ConvArgs& a, int y, int px, bool pin, int kq,
+                                         int lane, const f32x4_t (&acc)[COUT / 16]) {
+  constexpr int NB = COUT / 16;
   if constexpr (FUSE == FUSE_NONE) {
     if (!pin) return;
     uint16_t* o = a.out + ((size_t)y * a.Wo + px) * COUT + 4 * kq;
@@ -162,6 +162,81 @@ __global__ void __launch_bounds__(256) conv_kernel(ConvArgs a) {
       }
     }
   }
+}
+
+// Four tiles of 16 output pixels per wave: the input fragments of the four
+// tiles for one kernel row are in flight together and each weight fragment
+// is reused across them.
+__host__ __device__ constexpr int tiles_per_wave(int) { return 4; }
+
+template <int CIN, int COUT, int KS, int ST, int IN, int CUP, int FUSE, int COUT2>
+__global__ void __launch_bounds__(256) conv_kernel(ConvArgs a) {
+  constexpr int NCB = CIN / 16, NB = COUT / 16, P = KS / 2, TPW = tiles_per_wave(CIN);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int y = blockIdx.y;
+  const int kq = lane >> 4;
+  int px[TPW];
+  bool pin[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    px[t] = (blockIdx.x * 4 + wv) * TPW * 16 + t * 16 + (lane & 15);
+    pin[t] = px[t] < a.Wo;
+  }
+  // partial sums (K steps round-robin) so that at least 8 independent MFMA
+  // chains are in flight per wave
+  constexpr int KSPL = (TPW * NB >= 8) ? 1 : 8 / (TPW * NB);
+  f32x4_t acc[TPW][NB][KSPL];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int k = 0; k < KSPL; ++k) acc[t][nb][k] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ky = 0; ky < KS; ++ky) {
+    const int yi = y * ST + ky - P;
+    const bool oky = yi >= 0 && yi < a.Hi;
+    const int yc = min(max(yi, 0), a.Hi - 1);
+    // this kernel row's input fragments of every tile, then their products
+    bf16x4_t bv[TPW][KS][NCB];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+#pragma unroll
+      for (int kx = 0; kx < KS; ++kx) {
+        const int xi = px[t] * ST + kx - P;
+        const bool ok = pin[t] && oky && xi >= 0 && xi < a.Wi;
+        const int xc = min(max(xi, 0), a.Wi - 1);
+        load_blocks<CIN, CUP, IN, NCB>(a, yc, xc, 4 * kq, ok, bv[t][kx]);
+      }
+    }
+#pragma unroll
+    for (int kx = 0; kx < KS; ++kx) {
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const int tap = ky * KS + kx;
+        const int ks = (tap * NCB + cb) % KSPL;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const bf16x4_t av = a.w[((tap * NCB + cb) * NB + nb) * 64 + lane];
+#pragma unroll
+          for (int t = 0; t < TPW; ++t)
+            acc[t][nb][ks] =
+                __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv[t][kx][cb], acc[t][nb][ks], 0, 0, 0);
+        }
+      }
+    }
+  }
+  f32x4_t sum[TPW][NB];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      sum[t][nb] = acc[t][nb][0];
+#pragma unroll
+      for (int k = 1; k < KSPL; ++k) sum[t][nb] += acc[t][nb][k];
+    }
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) epilogue<COUT, FUSE, COUT2>(a, y, px[t], pin[t], kq, lane, sum[t]);
 }
 
 // Packing: FP32 weight [cout][cin][k][k] -> fragments (tap, cin block,
@@ -245,9 +320,10 @@ inline const float* layer_b(const void* packed, int i) {
                                         frag_count(kLayers[i]) * sizeof(bf16x4_t));
 }
 
-// Activation buffers in the workspace, in order: e0 (16, full), t1 (32,
-// full), e1 (32, half), t2 (64, half), e2 (64, quarter), t3 (32, half),
-// d1 (32, half), t4 (16, full), t5 (16, full).
+// Activation buffers in the workspace, in order: x0 (the prepared input,
+// 16, full), e0 (16, full), t1 (32, full), e1 (32, half), t2 (64, half),
+// e2 (64, quarter), t3 (32, half), d1 (32, half), t4 (16, full), t5 (16,
+// full).
 struct Grids {
   int H, W, Hh, Wh, Hq, Wq;
 };
@@ -258,13 +334,14 @@ inline Grids grids(int H, int W) {
   return g;
 }
 inline size_t align256(size_t n) { return (n + 255) / 256 * 256; }
-inline void act_layout(const Grids& g, size_t off[10]) {
+constexpr int kActBufs = 10;
+inline void act_layout(const Grids& g, size_t off[kActBufs + 1]) {
   const size_t full = (size_t)g.H * g.W * 2, half = (size_t)g.Hh * g.Wh * 2,
                quarter = (size_t)g.Hq * g.Wq * 2;
-  const size_t sz[9] = {16 * full, 32 * full, 32 * half, 64 * half, 64 * quarter,
-                        32 * half, 32 * half, 16 * full, 16 * full};
+  const size_t sz[kActBufs] = {16 * full, 16 * full, 32 * full, 32 * half, 64 * half,
+                               64 * quarter, 32 * half, 32 * half, 16 * full, 16 * full};
   off[0] = 0;
-  for (int i = 0; i < 9; ++i) off[i + 1] = off[i] + align256(sz[i]);
+  for (int i = 0; i < kActBufs; ++i) off[i + 1] = off[i] + align256(sz[i]);
 }
 
 bool valid_dims(int H, int W) {
@@ -279,8 +356,9 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 
 template <int CIN, int COUT, int KS, int ST, int IN, int CUP, int FUSE, int COUT2>
 hipError_t launch(const ConvArgs& a, hipStream_t s) {
+  constexpr int px_per_block = 4 * tiles_per_wave(CIN) * 16;
   hipLaunchKernelGGL((conv_kernel<CIN, COUT, KS, ST, IN, CUP, FUSE, COUT2>),
-                     dim3((a.Wo + 63) / 64, a.Ho), dim3(256), 0, s, a);
+                     dim3((a.Wo + px_per_block - 1) / px_per_block, a.Ho), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -316,9 +394,9 @@ flr_status flr_net_pack(const float* params, void* packed, void* stream) {
 
 size_t flr_net_workspace_bytes(int32_t height, int32_t width) {
   if (!valid_dims(height, width)) return 0;
-  size_t off[10];
+  size_t off[kActBufs + 1];
   act_layout(grids(height, width), off);
-  return off[9];
+  return off[kActBufs];
 }
 
 flr_status flr_net_forward(int32_t height, int32_t width, const float* guides, const float* noisy,
@@ -340,12 +418,12 @@ flr_status flr_net_forward(int32_t height, int32_t width, const float* guides, c
     return FLR_ERR_ALIAS;
 
   const Grids g = grids(height, width);
-  size_t off[10];
+  size_t off[kActBufs + 1];
   act_layout(g, off);
   char* ws = static_cast<char*>(workspace);
   auto buf = [&](int i) { return reinterpret_cast<uint16_t*>(ws + off[i]); };
-  uint16_t *e0 = buf(0), *t1 = buf(1), *e1 = buf(2), *t2 = buf(3), *e2 = buf(4), *t3 = buf(5),
-           *d1 = buf(6), *t4 = buf(7), *t5 = buf(8);
+  uint16_t *x0 = buf(0), *e0 = buf(1), *t1 = buf(2), *e1 = buf(3), *t2 = buf(4), *e2 = buf(5),
+           *t3 = buf(6), *d1 = buf(7), *t4 = buf(8), *t5 = buf(9);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   auto args = [&](int layer, int Hi, int Wi, int Ho, int Wo) {
     ConvArgs a = {};
@@ -358,14 +436,19 @@ flr_status flr_net_forward(int32_t height, int32_t width, const float* guides, c
     return a;
   };
   hipError_t e;
-  {  // in3 + in1: planar input -> e0
+  {  // input compression and layout
+    const PrepArgs pa = {guides, noisy, x0, g.H, g.W};
+    const size_t n = (size_t)g.H * g.W;
+    hipLaunchKernelGGL(prep_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pa);
+    if (hipGetLastError() != hipSuccess) return FLR_ERR_HIP;
+  }
+  {  // in3 + in1 -> e0
     ConvArgs a = args(0, g.H, g.W, g.H, g.W);
-    a.g = guides;
-    a.y = noisy;
+    a.in0 = x0;
     a.w2 = layer_w(packed, 1);
     a.b2 = layer_b(packed, 1);
     a.out = e0;
-    if ((e = launch<16, 16, 3, 1, IN_PLANAR, 0, FUSE_1X1_RELU, 16>(a, s)) != hipSuccess) return FLR_ERR_HIP;
+    if ((e = launch<16, 16, 3, 1, IN_HWC, 0, FUSE_1X1_RELU, 16>(a, s)) != hipSuccess) return FLR_ERR_HIP;
   }
   {  // e1a
     ConvArgs a = args(2, g.H, g.W, g.H, g.W);
