@@ -128,8 +128,10 @@ size_t flr_denoise_workspace_bytes(const flr_params* p) {
   if (p->fused == FLR_PATH_STAGES)
     return unfused_coeff_offset(p) + flr_num_coeff_planes(p->num_guides, p->num_channels) * pb;
   if (!p->average_coeffs) return 0;
-  if (p->fused == FLR_PATH_TWO_PASS)
+  if (p->fused == FLR_PATH_TWO_PASS && !flr::split_walk(p->num_guides, p->num_channels))
     return flr_num_coeff_planes(p->num_guides, p->num_channels) * pb;
+  if (p->fused == FLR_PATH_TWO_PASS)  // split walks take the stage sequence
+    return unfused_coeff_offset(p) + flr_num_coeff_planes(p->num_guides, p->num_channels) * pb;
   return ring_bytes(p);
 }
 
@@ -148,6 +150,12 @@ flr_status flr_moments(const flr_params* p, const float* guides, const float* no
   a.noisy = noisy;
   a.out = moments;
   plan(p, flr::K_MOMENTS, &a);
+  if (flr::split_walk(p->num_guides, p->num_channels)) {
+    // two walks over halves of the product channels, each LDS-resident
+    if ((st = dispatch(p->num_guides, p->num_channels, flr::K_MOMENTS_A, a, stream)) != FLR_OK)
+      return st;
+    return dispatch(p->num_guides, p->num_channels, flr::K_MOMENTS_B, a, stream);
+  }
   return dispatch(p->num_guides, p->num_channels, flr::K_MOMENTS, a, stream);
 }
 
@@ -224,12 +232,16 @@ flr_status flr_denoise(const flr_params* p, const float* guides, const float* no
       return FLR_ERR_ALIAS;
   }
   const int Q = p->num_guides, C = p->num_channels;
-  if (p->fused == FLR_PATH_TWO_PASS && p->average_coeffs) {
+  if (p->fused == FLR_PATH_TWO_PASS && p->average_coeffs && !flr::split_walk(Q, C)) {
     float* coeffs = static_cast<float*>(workspace);
     if ((st = flr_coefficients(p, guides, noisy, coeffs, stream)) != FLR_OK) return st;
     return flr_apply(p, guides, coeffs, out, stream);
   }
-  if (p->fused) {
+  // Too many moment channels for one LDS-resident walk: the two-pass path
+  // takes the stage sequence, whose moment walk is split into two slices.
+  const bool stages = p->fused == FLR_PATH_STAGES ||
+                      (p->fused == FLR_PATH_TWO_PASS && p->average_coeffs);
+  if (!stages) {
     LaunchArgs a = base_args(p);
     a.guides = guides;
     a.noisy = noisy;

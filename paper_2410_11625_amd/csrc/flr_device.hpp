@@ -102,50 +102,70 @@ __device__ __forceinline__ void regularise(T (&Hm)[Q * (Q + 1) / 2], const T (&m
   }
 }
 
+// f(std::integral_constant<int, I>) for I = B .. E-1: loop bodies with
+// compile-time indices, whatever the trip count (the compiler otherwise
+// keeps short inner loops of the larger systems as loops over arrays in
+// scratch memory).
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
 // Solve H X = R for C right-hand sides (R is [Q][C] row-major, overwritten
 // by X). H = U^T U with U upper triangular, built in place in Hm; only the
 // reciprocals of the diagonal of U are kept.
 template <int Q, int C, typename T>
 __device__ __forceinline__ void chol_solve(T (&Hm)[Q * (Q + 1) / 2], T (&R)[Q * C]) {
   T inv[Q];
-#pragma unroll
-  for (int j = 0; j < Q; ++j) {
+  static_for<0, Q>([&](auto J) {
+    constexpr int j = decltype(J)::value;
     T d = Hm[tri<Q>(j, j)];
-#pragma unroll
-    for (int k = 0; k < j; ++k) d = fma_t(-Hm[tri<Q>(k, j)], Hm[tri<Q>(k, j)], d);
+    static_for<0, j>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      d = fma_t(-Hm[tri<Q>(k, j)], Hm[tri<Q>(k, j)], d);
+    });
     if (d < T(1e-30)) d = T(1e-30);
     const T ij = rsqrt_t(d);
     inv[j] = ij;
-#pragma unroll
-    for (int i = j + 1; i < Q; ++i) {
+    static_for<j + 1, Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
       T s = Hm[tri<Q>(j, i)];
-#pragma unroll
-      for (int k = 0; k < j; ++k) s = fma_t(-Hm[tri<Q>(k, j)], Hm[tri<Q>(k, i)], s);
+      static_for<0, j>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        s = fma_t(-Hm[tri<Q>(k, j)], Hm[tri<Q>(k, i)], s);
+      });
       Hm[tri<Q>(j, i)] = s * ij;
-    }
-  }
+    });
+  });
   // U^T z = R
-#pragma unroll
-  for (int j = 0; j < Q; ++j) {
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
+  static_for<0, Q>([&](auto J) {
+    constexpr int j = decltype(J)::value;
+    static_for<0, C>([&](auto Cc) {
+      constexpr int c = decltype(Cc)::value;
       T s = R[j * C + c];
-#pragma unroll
-      for (int k = 0; k < j; ++k) s = fma_t(-Hm[tri<Q>(k, j)], R[k * C + c], s);
+      static_for<0, j>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        s = fma_t(-Hm[tri<Q>(k, j)], R[k * C + c], s);
+      });
       R[j * C + c] = s * inv[j];
-    }
-  }
+    });
+  });
   // U x = z
-#pragma unroll
-  for (int j = Q - 1; j >= 0; --j) {
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
+  static_for<0, Q>([&](auto JJ) {
+    constexpr int j = Q - 1 - decltype(JJ)::value;
+    static_for<0, C>([&](auto Cc) {
+      constexpr int c = decltype(Cc)::value;
       T s = R[j * C + c];
-#pragma unroll
-      for (int k = j + 1; k < Q; ++k) s = fma_t(-Hm[tri<Q>(j, k)], R[k * C + c], s);
+      static_for<j + 1, Q>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        s = fma_t(-Hm[tri<Q>(j, k)], R[k * C + c], s);
+      });
       R[j * C + c] = s * inv[j];
-    }
-  }
+    });
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -379,9 +399,18 @@ __device__ __forceinline__ void shift_raw(const float (&v)[Q + C], bool ok, cons
 }
 
 // Channel order: sum g[Q] | sum y[C] | sum g_p g_q (p<=q) | sum g_q y_c.
+// A walker may carry only a slice of the product channels: products
+// [POFF, POFF + PCNT) of the Q(Q+1)/2 + QC, after the Q + C first moments,
+// which every walker carries. chan_local maps a channel to its index in
+// the walker (-1 when outside the slice); it folds at compile time.
+template <int Q, int C, int POFF, int PCNT>
+__host__ __device__ constexpr int chan_local(int m) {
+  return m < Q + C ? m : ((m - Q - C >= POFF && m - Q - C < POFF + PCNT) ? m - POFF : -1);
+}
+
 // V += products of the entering pixel (ga, ya) - those of the leaving one.
-template <int Q, int C>
-__device__ __forceinline__ void vupdate(sum_t (&V)[num_sums(Q, C)], const sum_t (&ga)[Q],
+template <int Q, int C, int POFF, int PCNT>
+__device__ __forceinline__ void vupdate(sum_t (&V)[Q + C + PCNT], const sum_t (&ga)[Q],
                                         const sum_t (&ya)[C], const sum_t (&gs)[Q],
                                         const sum_t (&ys)[C]) {
 #pragma unroll
@@ -393,7 +422,8 @@ __device__ __forceinline__ void vupdate(sum_t (&V)[num_sums(Q, C)], const sum_t 
   for (int p = 0; p < Q; ++p) {
 #pragma unroll
     for (int q = p; q < Q; ++q) {
-      V[k] = fma_t(-gs[p], gs[q], fma_t(ga[p], ga[q], V[k]));
+      const int l = chan_local<Q, C, POFF, PCNT>(k);
+      if (l >= 0) V[l] = fma_t(-gs[p], gs[q], fma_t(ga[p], ga[q], V[l]));
       ++k;
     }
   }
@@ -401,7 +431,8 @@ __device__ __forceinline__ void vupdate(sum_t (&V)[num_sums(Q, C)], const sum_t 
   for (int q = 0; q < Q; ++q) {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      V[k] = fma_t(-gs[q], ys[c], fma_t(ga[q], ya[c], V[k]));
+      const int l = chan_local<Q, C, POFF, PCNT>(k);
+      if (l >= 0) V[l] = fma_t(-gs[q], ys[c], fma_t(ga[q], ya[c], V[l]));
       ++k;
     }
   }
@@ -410,23 +441,27 @@ __device__ __forceinline__ void vupdate(sum_t (&V)[num_sums(Q, C)], const sum_t 
 // Change of channels [g0, g0 + gn) of the running vertical sums when the
 // entering pixel (ga, ya) is added and the leaving one (gs, ys) removed
 // (channel order as in vupdate); every index folds at compile time.
-template <int Q, int C, int MG>
+template <int Q, int C, int MG, int POFF, int PCNT>
 __device__ __forceinline__ void group_deltas(int g0, int gn, const sum_t (&ga)[Q],
                                              const sum_t (&ya)[C], const sum_t (&gs)[Q],
                                              const sum_t (&ys)[C], sum_t (&dl)[MG]) {
-  auto in = [&](int m) { return m >= g0 && m < g0 + gn; };
+  // local index of channel m within [g0, g0 + gn), else -1
+  auto at = [&](int m) {
+    const int l = chan_local<Q, C, POFF, PCNT>(m);
+    return (l >= g0 && l < g0 + gn) ? l - g0 : -1;
+  };
 #pragma unroll
   for (int q = 0; q < Q; ++q)
-    if (in(q)) dl[q - g0] = ga[q] - gs[q];
+    if (at(q) >= 0) dl[at(q)] = ga[q] - gs[q];
 #pragma unroll
   for (int c = 0; c < C; ++c)
-    if (in(Q + c)) dl[Q + c - g0] = ya[c] - ys[c];
+    if (at(Q + c) >= 0) dl[at(Q + c)] = ya[c] - ys[c];
   int k = Q + C;
 #pragma unroll
   for (int p = 0; p < Q; ++p) {
 #pragma unroll
     for (int q = p; q < Q; ++q) {
-      if (in(k)) dl[k - g0] = fma_t(-gs[p], gs[q], ga[p] * ga[q]);
+      if (at(k) >= 0) dl[at(k)] = fma_t(-gs[p], gs[q], ga[p] * ga[q]);
       ++k;
     }
   }
@@ -434,7 +469,7 @@ __device__ __forceinline__ void group_deltas(int g0, int gn, const sum_t (&ga)[Q
   for (int q = 0; q < Q; ++q) {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      if (in(k)) dl[k - g0] = fma_t(-gs[q], ys[c], ga[q] * ya[c]);
+      if (at(k) >= 0) dl[at(k)] = fma_t(-gs[q], ys[c], ga[q] * ya[c]);
       ++k;
     }
   }
@@ -447,7 +482,7 @@ __device__ __forceinline__ void group_deltas(int g0, int gn, const sum_t (&ga)[Q
 // (shifted guides). Groups arrive in increasing order and the first holds all
 // Q + C first moments, so the means are complete before any covariance needs
 // them. All loops unroll and every group test folds at compile time.
-template <int Q, int C, int MG, typename T, typename U>
+template <int Q, int C, int MG, int POFF, int PCNT, typename T, typename U>
 __device__ __forceinline__ void centre_group(int g0, int gn, const sum_t* P, const HWin& h,
                                              T inv_n, T (&mu)[Q], T (&nu)[C],
                                              U (&Hm)[Q * (Q + 1) / 2], U (&R)[Q * C]) {
@@ -473,23 +508,23 @@ __device__ __forceinline__ void centre_group(int g0, int gn, const sum_t* P, con
     for (int i = 0; i < B; ++i)
       if (k0 + i < gn) ws[k0 + i] = (T)((rb[i] - ra[i]) + rt[i]);
   }
-  auto win = [&](int m) { return ws[m - g0]; };
+  // index into ws of channel m when it is in this group, else -1
+  auto at = [&](int m) {
+    const int l = chan_local<Q, C, POFF, PCNT>(m);
+    return (l >= g0 && l < g0 + gn) ? l - g0 : -1;
+  };
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int m = q;
-    if (m >= g0 && m < g0 + gn) mu[q] = win(m) * inv_n;
-  }
+  for (int q = 0; q < Q; ++q)
+    if (at(q) >= 0) mu[q] = ws[at(q)] * inv_n;
 #pragma unroll
-  for (int c = 0; c < C; ++c) {
-    const int m = Q + c;
-    if (m >= g0 && m < g0 + gn) nu[c] = win(m) * inv_n;
-  }
+  for (int c = 0; c < C; ++c)
+    if (at(Q + c) >= 0) nu[c] = ws[at(Q + c)] * inv_n;
 #pragma unroll
   for (int p = 0; p < Q; ++p) {
 #pragma unroll
     for (int q = p; q < Q; ++q) {
       const int m = Q + C + tri<Q>(p, q);
-      if (m >= g0 && m < g0 + gn) Hm[tri<Q>(p, q)] = (U)fma_t(win(m), inv_n, -mu[p] * mu[q]);
+      if (at(m) >= 0) Hm[tri<Q>(p, q)] = (U)fma_t(ws[at(m)], inv_n, -mu[p] * mu[q]);
     }
   }
 #pragma unroll
@@ -497,7 +532,7 @@ __device__ __forceinline__ void centre_group(int g0, int gn, const sum_t* P, con
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int m = Q + C + NP + q * C + c;
-      if (m >= g0 && m < g0 + gn) R[q * C + c] = (U)fma_t(win(m), inv_n, -mu[q] * nu[c]);
+      if (at(m) >= 0) R[q * C + c] = (U)fma_t(ws[at(m)], inv_n, -mu[q] * nu[c]);
     }
   }
 }
@@ -573,17 +608,23 @@ enum WalkMode : int { W_MOMENTS = 0, W_FUSED0 = 1, W_FUSED1 = 2, W_COEFFS = 3 };
 //              reconstruct with the averaged coefficients. The segment is
 //              extended by r coefficient rows above and below and the strip
 //              by r columns each side, so no data crosses workgroups.
-template <int Q, int C, int MODE, bool WIDE>
+// POFF, PCNT: the slice of product channels this walker carries (all by
+// default); W_MOMENTS over a slice writes that slice's planes (and, for the
+// first slice, n and the means).
+template <int Q, int C, int MODE, bool WIDE, int POFF = 0, int PCNT = -1>
 __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
   using D = Dims<Q, C>;
   using T = solve_t;
-  constexpr int NS = D::NS;
+  constexpr int NPQ = D::NP + D::NQC;              // product channels
+  constexpr int PC = PCNT < 0 ? NPQ : PCNT;
+  constexpr int NS = Q + C + PC;                   // channels of this walker
   constexpr int FC = D::FC;
   constexpr int NP = D::NP;
   constexpr WalkLayout LAY = walk_layout(
       Q, C,
       MODE == W_FUSED1 ? K_FUSED1
-                       : (MODE == W_FUSED0 ? K_FUSED0 : (MODE == W_COEFFS ? K_COEFFS : K_MOMENTS)));
+                       : (MODE == W_FUSED0 ? K_FUSED0 : (MODE == W_MOMENTS ? K_MOMENTS : K_COEFFS)),
+      NS);
   constexpr int MG = LAY.mg;
   constexpr bool VA_LDS = MODE == W_FUSED1 && LAY.va_lds;
   extern __shared__ float lds[];
@@ -659,7 +700,7 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
       }
       sum_t g[Q], y[C];
       shift_raw<Q, C>(cur, cok, cg, g, y);
-      vupdate<Q, C>(V, g, y, zg, zy);
+      vupdate<Q, C, POFF, PC>(V, g, y, zg, zy);
     }
   }
 
@@ -727,7 +768,7 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
     sum_t ga[Q], yA[C], gs[Q], yS[C];
     shift_raw<Q, C>(fa, okA, cg, ga, yA);
     shift_raw<Q, C>(fs, okS, cg, gs, yS);
-    if (!VL) vupdate<Q, C>(V, ga, yA, gs, yS);
+    if (!VL) vupdate<Q, C, POFF, PC>(V, ga, yA, gs, yS);
     if (ym + 1 < ym1) fetch(ym + 1);
 
     const int slot = MODE == W_FUSED1 ? (ym - ym0) % (2 * r + 1) : 0;
@@ -745,6 +786,7 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
       // means in solve_t; the centred system (formed in solve_t) in chol_t
       T mu[Q], nu[C];
       chol_t Hm[NP], R[Q * C];
+
       // Groups of channels alternate between the two LDS buffers, so one
       // barrier per group separates its prefix writes from its window reads
       // and the reads of the group before last from this group's writes.
@@ -779,7 +821,7 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
 #pragma unroll
             for (int i = 0; i < IL; ++i) lf[i] = seg_left<WIDE>(x[i]);
             sum_t dl[IL];  // this row's change of the chunk's channels
-            group_deltas<Q, C, IL>(g0 + m0, gn - m0 < IL ? gn - m0 : IL, ga, yA, gs, yS, dl);
+            group_deltas<Q, C, IL, POFF, PC>(g0 + m0, gn - m0 < IL ? gn - m0 : IL, ga, yA, gs, yS, dl);
 #pragma unroll
             for (int i = 0; i < IL; ++i) x[i] = m0 + i < gn ? (x[i] - lf[i]) + dl[i] : sum_t(0);
           } else {
@@ -795,25 +837,31 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
         if (cvalid) {
           if (MODE == W_MOMENTS && a.raw) {
 #pragma unroll
-            for (int m = 0; m < gn; ++m)
-              a.out[(1 + g0 + m) * pl + off] = (float)hwin_sum(P + m * kLdsStride, hw);
+            for (int m = 0; m < gn; ++m) {
+              const int l = g0 + m;  // local channel -> global channel
+              const int gch = l < Q + C ? l : l + POFF;
+              if (POFF == 0 || l >= Q + C)
+                a.out[(1 + gch) * pl + off] = (float)hwin_sum(P + m * kLdsStride, hw);
+            }
           } else {
-            centre_group<Q, C, MG, T, chol_t>(g0, gn, P, hw, inv_n, mu, nu, Hm, R);
+            centre_group<Q, C, MG, POFF, PC, T, chol_t>(g0, gn, P, hw, inv_n, mu, nu, Hm, R);
           }
         }
       }
       if (cvalid) {
         if (MODE == W_MOMENTS) {
-          a.out[off] = (float)ni;
+          // a slice writes its own product planes; the first one also n, mu, nu
+          if (POFF == 0) a.out[off] = (float)ni;
           if (!a.raw) {
+            if (POFF == 0) {
 #pragma unroll
-            for (int q = 0; q < Q; ++q) a.out[(1 + q) * pl + off] = (float)(mu[q] + (T)cg[q]);
+              for (int q = 0; q < Q; ++q) a.out[(1 + q) * pl + off] = (float)(mu[q] + (T)cg[q]);
 #pragma unroll
-            for (int c = 0; c < C; ++c) a.out[(1 + Q + c) * pl + off] = (float)nu[c];
+              for (int c = 0; c < C; ++c) a.out[(1 + Q + c) * pl + off] = (float)nu[c];
+            }
 #pragma unroll
-            for (int k = 0; k < NP; ++k) a.out[(1 + Q + C + k) * pl + off] = (float)Hm[k];
-#pragma unroll
-            for (int k = 0; k < Q * C; ++k) a.out[(1 + Q + C + NP + k) * pl + off] = (float)R[k];
+            for (int k = POFF; k < POFF + PC; ++k)
+              a.out[(1 + Q + C + k) * pl + off] = k < NP ? (float)Hm[k] : (float)R[k - NP];
           }
         } else {
           T mu_o[Q];
@@ -1209,6 +1257,20 @@ hipError_t launch_qc(int kind, const LaunchArgs& a, hipStream_t s) {
     case K_COEFFS:
       return wide ? launch_with_lds(walk_kernel<Q, C, W_COEFFS, true>, wblocks, lds, a, s)
                   : launch_with_lds(walk_kernel<Q, C, W_COEFFS, false>, wblocks, lds, a, s);
+    case K_MOMENTS_A:
+    case K_MOMENTS_B:
+      if constexpr (split_walk(Q, C)) {
+        constexpr int PA = split_first(Q, C), NPQ = num_products(Q, C);
+        if (kind == K_MOMENTS_A) {
+          const size_t l2 = walk_lds_bytes(K_MOMENTS, Q, C, Q + C + PA);
+          return wide ? launch_with_lds(walk_kernel<Q, C, W_MOMENTS, true, 0, PA>, wblocks, l2, a, s)
+                      : launch_with_lds(walk_kernel<Q, C, W_MOMENTS, false, 0, PA>, wblocks, l2, a, s);
+        }
+        const size_t l2 = walk_lds_bytes(K_MOMENTS, Q, C, Q + C + NPQ - PA);
+        return wide ? launch_with_lds(walk_kernel<Q, C, W_MOMENTS, true, PA, NPQ - PA>, wblocks, l2, a, s)
+                    : launch_with_lds(walk_kernel<Q, C, W_MOMENTS, false, PA, NPQ - PA>, wblocks, l2, a, s);
+      }
+      return hipErrorInvalidValue;
     case K_APPLY_AVG:
       switch (avg_variant(a.r, C)) {
         case AV_BLOCK8:

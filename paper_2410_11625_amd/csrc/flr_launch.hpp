@@ -69,6 +69,8 @@ enum Kind : int {
   K_FUSED0 = 4,       // moments -> solve -> apply, no averaging, one kernel
   K_FUSED1 = 5,       // moments -> solve -> average -> apply, one kernel
   K_COEFFS = 6,       // moments -> solve -> coefficient planes, one kernel
+  K_MOMENTS_A = 7,    // K_MOMENTS over the first slice of the product channels
+  K_MOMENTS_B = 8,    // K_MOMENTS over the rest (split walks)
 };
 
 struct LaunchArgs {
@@ -195,8 +197,8 @@ struct WalkLayout {
   size_t a, b, va; // region sizes in bytes
 };
 
-__host__ __device__ constexpr WalkLayout walk_layout(int Q, int C, int kind) {
-  const int ns = num_sums(Q, C);
+__host__ __device__ constexpr WalkLayout walk_layout(int Q, int C, int kind, int ns_walk = -1) {
+  const int ns = ns_walk > 0 ? ns_walk : num_sums(Q, C);
   const int fc = (Q + 1) * C;
   const int row_s = kLdsStride * (int)sizeof(sum_t);
   const int row_t = kLdsStride * (int)sizeof(solve_t);
@@ -231,9 +233,21 @@ __host__ __device__ constexpr WalkLayout walk_layout(int Q, int C, int kind) {
   return L;
 }
 
-inline size_t walk_lds_bytes(int kind, int Q, int C) {
-  const WalkLayout L = walk_layout(Q, C, kind);
+inline size_t walk_lds_bytes(int kind, int Q, int C, int ns_walk = -1) {
+  const WalkLayout L = walk_layout(Q, C, kind, ns_walk);
   return L.a + L.b + L.va;
+}
+
+// Split walks: when a moment walker's channels exceed what stays resident in
+// LDS between rows (two groups of max_lds_rows FP64 rows for 256 columns),
+// the product channels are walked in two slices, each with the first
+// moments: [0, split_first) then the rest. Only where both slices fit.
+__host__ __device__ constexpr int num_products(int Q, int C) { return Q * (Q + 1) / 2 + Q * C; }
+__host__ __device__ constexpr int resident_channels() { return 2 * max_lds_rows(8); }
+__host__ __device__ constexpr int split_first(int Q, int C) { return (num_products(Q, C) + 1) / 2; }
+__host__ __device__ constexpr bool split_walk(int Q, int C) {
+  return num_sums(Q, C) > resident_channels() &&
+         Q + C + split_first(Q, C) <= resident_channels();
 }
 
 inline size_t ring_bytes_per_block(int Q, int C, int r) {

@@ -24,6 +24,8 @@ CASES = [
     dict(kind="both", H=41, W=260, Q=8, C=3, r=8, tile_rows=9, frame="config", config=1),
     # no averaging, Appendix regulariser
     dict(kind="both", H=33, W=250, Q=3, C=2, r=5, average=0, tile_rows=6),
+    # 80 moment channels: the two-pass path splits the walk into two slices
+    dict(kind="two_pass", H=29, W=270, Q=8, C=4, r=8, tile_rows=10),
     dict(kind="both", H=25, W=90, Q=3, C=2, r=3, mode="paper", eps_mul=0.2, offset=2.0),
 ]
 
@@ -39,6 +41,8 @@ def test_emulated_denoise_matches_oracle(spec):
 @pytest.mark.parametrize("spec", [
     dict(kind="raw_moments", H=37, W=300, Q=3, C=2, r=3, tile_rows=10),
     dict(kind="raw_moments", H=5, W=7, Q=1, C=1, r=8),
+    # 80 channels: two walks over halves of the products
+    dict(kind="raw_moments", H=21, W=280, Q=8, C=4, r=4, tile_rows=6),
 ])
 def test_emulated_raw_moments_bit_exact(spec):
     res = run_in_subprocess(spec)
