@@ -160,9 +160,10 @@ def summarize_counters(fetch_csv: str, write_csv: str, path_name: str) -> int:
 
 
 def time_flnr(flr, torch, np, sets, nsets, dev, stream, args):
-    """FLNR per frame: guide network (BF16 MFMA) then two-pass FLR over the 8
-    input guides and the network's 4. Events around each part; the 12-guide
-    buffers hold the input guides in planes 0..7 (resident before timing)."""
+    """FLNR per frame: guide network (BF16 MFMA) then FLR (flr_denoise,
+    two-pass path) over the 8 input guides and the network's 4. Events around
+    each part; the 12-guide buffers hold the input guides in planes 0..7
+    (resident before timing)."""
     from synth.net_weights import flatten_net_weights, make_net_weights
     packed = flr.net_pack(torch.from_numpy(flatten_net_weights(make_net_weights(2))).to(dev))
     g12s = []
@@ -173,7 +174,7 @@ def time_flnr(flr, torch, np, sets, nsets, dev, stream, args):
     p = flr.make_params(H, W, 12, C, R, eps=EPS, average=True, fused="two_pass")
     nws = torch.empty(int(flr.api.lib().flr_net_workspace_bytes(H, W)), dtype=torch.uint8,
                       device=dev)
-    coeffs = torch.empty((flr.num_coeff_planes(12, C), H, W), dtype=torch.float32, device=dev)
+    rws = torch.empty(flr.workspace_bytes(p), dtype=torch.uint8, device=dev)
     outs = [torch.empty((C, H, W), dtype=torch.float32, device=dev) for _ in range(nsets)]
 
     def step(k, evs=None):
@@ -185,8 +186,10 @@ def time_flnr(flr, torch, np, sets, nsets, dev, stream, args):
         flr.net_forward(guides, noisy, packed, out=g12[8:], workspace=nws)
         if evs is not None:
             evs[1].record(stream)
-        flr.coefficients(g12, noisy, R, eps=EPS, out=coeffs)
-        flr.apply(g12, coeffs, R, average=True, out=out)
+        # flr_denoise's two-pass path over 12 guides (the regression of
+        # flr_flnr_denoise): its moment walk is split into two slices
+        flr.denoise(noisy, g12, radius=R, eps=EPS, average=True, fused="two_pass", out=out,
+                    workspace=rws)
         if evs is not None:
             evs[2].record(stream)
 
