@@ -220,6 +220,40 @@ def time_flnr(flr, torch, np, sets, nsets, dev, stream, args):
             "steps": args.flnr_steps}
 
 
+def time_adjoint(flr, torch, np, sets, nsets, dev, stream, args):
+    """FLR adjoint per frame (flr_denoise_backward): dL/d(guides), dL/d(noisy)
+    and dL/d(eps) for a resident dL/d(out), on the FLR workload's frames."""
+    p = flr.make_params(H, W, Q, C, R, eps=EPS, average=True)
+    ws = torch.empty(flr.backward_workspace_bytes(p), dtype=torch.uint8, device=dev)
+    gen = torch.Generator(device=dev).manual_seed(5)
+    gout = torch.randn((C, H, W), generator=gen, device=dev, dtype=torch.float32)
+    gy = torch.empty((C, H, W), dtype=torch.float32, device=dev)
+    gg = torch.empty((Q, H, W), dtype=torch.float32, device=dev)
+    gr = torch.empty(2, dtype=torch.float64, device=dev)
+
+    def step(k):
+        noisy, guides, _ = sets[k % nsets]
+        flr.denoise_backward(noisy, guides, gout, R, EPS, workspace=ws, grad_noisy=gy,
+                             grad_guides=gg, grad_reg=gr)
+
+    for k in range(2):
+        step(k)
+    torch.cuda.synchronize()
+    ev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(2))
+          for _ in range(args.adjoint_steps)]
+    for k in range(args.adjoint_steps):
+        ev[k][0].record(stream)
+        step(k)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    return {"ms_per_frame": round(ms, 5), "value": round(H * W / (ms / 1e3) / 1e6, 2),
+            "unit": "Mpixel/s",
+            "config": "FLR adjoint (dL/dguides, dL/dnoisy, dL/deps) of the FLR workload, FP64 "
+                      "moments and fields recomputed from the inputs",
+            "workspace_bytes": int(ws.numel()), "steps": args.adjoint_steps}
+
+
 def cpu_baseline():
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
@@ -248,6 +282,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-flnr", action="store_true", help="skip the FLNR timing")
     ap.add_argument("--flnr-steps", type=int, default=20)
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--adjoint-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter reference)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -361,6 +397,10 @@ def main(argv=None):
         flnr = time_flnr(flr, torch, np, sets, nsets, dev, stream, args)
         flnr["vs_flr_ms"] = round(flnr["ms_per_frame"] - ms_per_step, 5)
 
+    adjoint = None
+    if not args.no_adjoint:
+        adjoint = time_adjoint(flr, torch, np, sets, nsets, dev, stream, args)
+
     if args.copy_calibration:
         src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -417,6 +457,7 @@ def main(argv=None):
                      "hbm_frac": round(hbm_gbps / PEAK_HBM_GBPS, 4)},
         "cpu_baseline": cpu,
         "flnr": flnr,
+        "adjoint": adjoint,
     }
     print(json.dumps(line))
     return 0

@@ -18,7 +18,9 @@
  *                reconstruction I_k = x_k A_k (Sec. 3.1);
  *   flr_denoise  all of the above: in one fused kernel, in two kernels
  *                (moments + solve, then average + reconstruction), or as the
- *                three stage entry points (see flr_path).
+ *                three stage entry points (see flr_path);
+ *   flr_denoise_backward  its adjoint: gradients with respect to the guides,
+ *                the noisy image and the regularisers.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -133,7 +135,9 @@ size_t flr_num_coeff_planes(int32_t num_guides, int32_t num_channels);
  * FLR_PATH_STAGES: the moment and coefficient images, (M + F*C)*H*W floats
  * (the coefficient image starts at the next 256-byte boundary);
  * FLR_PATH_FUSED with averaging: a per-workgroup ring of 2r+1 coefficient rows;
- * FLR_PATH_TWO_PASS with averaging: the coefficient image, F*C*H*W floats;
+ * FLR_PATH_TWO_PASS with averaging: the coefficient image, F*C*H*W floats
+ * (as STAGES when Q + C + Q(Q+1)/2 + Q*C exceeds 78 moment channels: the
+ * path then runs the stage sequence with its moment walk split in two);
  * without averaging: 0 (STAGES aside). Depends on the launch geometry only. */
 size_t flr_denoise_workspace_bytes(const flr_params* p);
 
@@ -164,6 +168,29 @@ flr_status flr_apply(const flr_params* p, const float* guides, const float* coef
  * workspaces. */
 flr_status flr_denoise(const flr_params* p, const float* guides, const float* noisy,
                        float* out, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Workspace bytes of flr_denoise_backward (0 if invalid): FP64 images of
+ * the window moments and of the adjoint's per-pixel fields, about
+ * (2*(M - 1) + (2 if averaging, else 1)*(C + 2*Q*C))*8 bytes per pixel. */
+size_t flr_denoise_backward_workspace_bytes(const flr_params* p);
+
+/* Gradients of flr_denoise (its adjoint; Sec. 3.3 trains the guide network
+ * through FLR, the Appendix learns eps and eps_mul by backpropagation). For a
+ * loss L with grad_out = dL/d(out) [C][H][W], out = flr_denoise(p, guides,
+ * noisy), writes grad_guides = dL/d(guides) [Q][H][W] and grad_noisy =
+ * dL/d(noisy) [C][H][W] (FP32) and, unless grad_reg is NULL, grad_reg[0] =
+ * dL/d(eps) and grad_reg[1] = dL/d(eps_mul) (device FP64; the latter is 0
+ * in ridge mode). The moments and coefficients are recomputed from guides
+ * and noisy, in FP64; nothing of the forward call is needed. Where the forward
+ * clamped a guide's rounded-negative window variance to 0, no gradient
+ * flows through that variance. p->fused is ignored; p->flags must be 0.
+ * workspace must hold flr_denoise_backward_workspace_bytes(p) bytes.
+ * Errors as flr_denoise, and FLR_ERR_ALIAS when an output overlaps an
+ * input, another output or the workspace. */
+flr_status flr_denoise_backward(const flr_params* p, const float* guides, const float* noisy,
+                                const float* grad_out, float* grad_guides, float* grad_noisy,
+                                double* grad_reg, void* workspace, size_t workspace_bytes,
+                                void* stream);
 
 /* Static description of a status code. */
 const char* flr_status_str(flr_status s);

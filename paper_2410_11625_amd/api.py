@@ -173,6 +173,95 @@ def denoise(noisy: torch.Tensor, guides: torch.Tensor, radius: int = 8, eps: flo
 
 
 # --------------------------------------------------------------------------
+# Adjoint (flr_denoise_backward) and autograd
+
+
+def backward_workspace_bytes(p: FlrParams) -> int:
+    return int(lib().flr_denoise_backward_workspace_bytes(ctypes.byref(p)))
+
+
+def denoise_backward(noisy: torch.Tensor, guides: torch.Tensor, grad_out: torch.Tensor,
+                     radius: int = 8, eps: float = 1e-3, mode: str = "ridge",
+                     eps_mul: float = 0.0, average: bool = True,
+                     workspace: torch.Tensor | None = None,
+                     grad_noisy: torch.Tensor | None = None,
+                     grad_guides: torch.Tensor | None = None,
+                     grad_reg: torch.Tensor | None = None):
+    """Gradients of ``denoise`` for dL/d(out) = ``grad_out`` [C,H,W]:
+    (dL/d(noisy) [C,H,W], dL/d(guides) [Q,H,W], [dL/d(eps), dL/d(eps_mul)]
+    as a float64 device tensor of 2). Moments are recomputed; the forward
+    call's results are not needed."""
+    _need(guides, "guides")
+    _need(noisy, "noisy")
+    _need(grad_out, "grad_out")
+    Q, H, W = guides.shape
+    C = noisy.shape[0]
+    if noisy.shape[1:] != guides.shape[1:] or grad_out.shape != noisy.shape:
+        raise ValueError("noisy, guides and grad_out must share height and width; "
+                         "grad_out must have the shape of noisy")
+    p = make_params(H, W, Q, C, radius, eps=eps, mode=mode, eps_mul=eps_mul, average=average)
+    check(lib().flr_validate_params(ctypes.byref(p)), "flr_denoise_backward")
+    need = backward_workspace_bytes(p)
+    dev = guides.device
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    if grad_noisy is None:
+        grad_noisy = torch.empty((C, H, W), dtype=torch.float32, device=dev)
+    if grad_guides is None:
+        grad_guides = torch.empty((Q, H, W), dtype=torch.float32, device=dev)
+    if grad_reg is None:
+        grad_reg = torch.empty(2, dtype=torch.float64, device=dev)
+    _need(grad_noisy, "grad_noisy")
+    _need(grad_guides, "grad_guides")
+    if grad_reg.dtype != torch.float64 or grad_reg.numel() < 2 or grad_reg.device.type != "cuda":
+        raise ValueError("grad_reg must be a float64 device tensor of at least 2 elements")
+    check(lib().flr_denoise_backward(
+        ctypes.byref(p), guides.data_ptr(), noisy.data_ptr(), grad_out.data_ptr(),
+        grad_guides.data_ptr(), grad_noisy.data_ptr(), grad_reg.data_ptr(),
+        workspace.data_ptr(), workspace.numel() * workspace.element_size(), _stream(guides)),
+        "flr_denoise_backward")
+    return grad_noisy, grad_guides, grad_reg
+
+
+class _FLRFunction(torch.autograd.Function):
+    """out = denoise(noisy, guides, ...) with its gradients from
+    flr_denoise_backward. Saves only the inputs; the backward recomputes the
+    window moments."""
+
+    @staticmethod
+    def forward(ctx, noisy, guides, eps, eps_mul, radius, mode, average, fused):
+        e = float(eps)
+        m = float(eps_mul)
+        ctx.cfg = (radius, e, mode, m, average)
+        ctx.save_for_backward(noisy, guides)
+        return denoise(noisy, guides, radius=radius, eps=e, mode=mode, eps_mul=m,
+                       average=average, fused=fused)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        noisy, guides = ctx.saved_tensors
+        radius, e, mode, m, average = ctx.cfg
+        gy, gg, gr = denoise_backward(noisy, guides, grad_out.contiguous().float(), radius, e,
+                                      mode, m, average)
+        need = ctx.needs_input_grad
+        ge = gr[0].float() if need[2] else None
+        gm = gr[1].float() if need[3] else None
+        return (gy if need[0] else None, gg if need[1] else None, ge, gm, None, None, None, None)
+
+
+def flr(noisy: torch.Tensor, guides: torch.Tensor, radius: int = 8, eps=1e-3,
+        mode: str = "ridge", eps_mul=0.0, average: bool = True, fused="two_pass") -> torch.Tensor:
+    """Differentiable FLR: ``denoise`` under torch autograd. ``eps`` and
+    ``eps_mul`` may be 0-d tensors that require grad (their values are read
+    on the host each call); gradients reach noisy, guides and both."""
+    if not torch.is_tensor(eps):
+        eps = torch.tensor(float(eps), dtype=torch.float32)
+    if not torch.is_tensor(eps_mul):
+        eps_mul = torch.tensor(float(eps_mul), dtype=torch.float32)
+    return _FLRFunction.apply(noisy, guides, eps, eps_mul, radius, mode, average, fused)
+
+
+# --------------------------------------------------------------------------
 # FLNR guide network (include/flr_net.h)
 
 NET_IN_GUIDES, NET_IN_NOISY, NET_OUT = 8, 3, 4

@@ -1,0 +1,210 @@
+// Window sums and a fixed-order reduction of FP64 planes, for the FLR adjoint.
+//
+// The adjoint recomputes the window moments as FP64 sums of anchored input
+// products, and sums its per-pixel fields over the same clipped window (the
+// window sum is its own adjoint). One workgroup owns
+// a strip of kThreads input columns (kThreads - 2r output columns) of one
+// plane and walks down a segment of rows: each lane keeps the running
+// vertical sum of its column (add the row entering the window, subtract the
+// row leaving it), stages it in LDS, and the lanes that own output columns
+// add the 2r+1 staged values of their window. Columns outside the image
+// stage 0, which clips the window at the left and right borders.
+#include <hip/hip_runtime.h>
+
+#include "flr_launch.hpp"
+
+namespace flr {
+
+constexpr int kBoxSegRows = 64;
+
+struct AdjBoxArgs {
+  const double* src;   // FP64 planes, or NULL for the product channels below
+  const float* guides; // product channels: guides [Q][H][W]
+  const float* noisy;  // product channels: noisy [C][H][W]
+  double* dst;
+  int64_t plane;  // elements per plane
+  int H, W, r, seg_rows, tiles_x;
+  int Q, C;
+};
+
+// Input plane v of the product channels: a guide (v < Q) or a noisy channel.
+__device__ __forceinline__ const float* input_plane(const AdjBoxArgs& a, int v) {
+  return v < a.Q ? a.guides + (int64_t)v * a.plane : a.noisy + (int64_t)(v - a.Q) * a.plane;
+}
+
+// Factors of product channel ch in the moment order g_q | y_c | g_p g_q
+// (p <= q) | g_q y_c: input planes u and v (v = -1 for a first moment).
+__device__ __forceinline__ void channel_factors(int ch, int Q, int C, int* u, int* v) {
+  if (ch < Q + C) {
+    *u = ch;
+    *v = -1;
+    return;
+  }
+  ch -= Q + C;
+  const int np = Q * (Q + 1) / 2;
+  if (ch < np) {
+    int p = 0;
+    while (ch >= Q - p) {
+      ch -= Q - p;
+      ++p;
+    }
+    *u = p;
+    *v = p + ch;
+    return;
+  }
+  ch -= np;
+  *u = ch / C;
+  *v = Q + ch % C;
+}
+
+// Window sums of FP64 planes (a.src) or, with a.src NULL, of the anchored
+// products of the inputs: channel blockIdx.y is (x_u - c_u)(x_v - c_v) or
+// x_u - c_u, with c the plane's value at pixel (0, 0).
+template <bool PRODUCTS>
+__global__ void __launch_bounds__(256) adj_box_kernel(AdjBoxArgs a) {
+  extern __shared__ float lds[];
+  double* rows = reinterpret_cast<double*>(lds);  // two rows of kThreads
+  const int tid = threadIdx.x;
+  const int r = a.r, H = a.H, W = a.W;
+  const int tile = blockIdx.x % a.tiles_x, seg = blockIdx.x / a.tiles_x;
+  const int x = tile * (kThreads - 2 * r) - r + tid;
+  const bool inx = x >= 0 && x < W;
+  const int y0 = seg * a.seg_rows;
+  const int y1 = y0 + a.seg_rows < H ? y0 + a.seg_rows : H;
+  const int64_t col = inx ? x : 0;
+  const double* src = nullptr;
+  const float *pu = nullptr, *pv = nullptr;
+  double cu = 0.0, cv = 0.0;
+  if constexpr (PRODUCTS) {
+    int u, v;
+    channel_factors(blockIdx.y, a.Q, a.C, &u, &v);
+    pu = input_plane(a, u);
+    cu = pu[0];
+    if (v >= 0) {
+      pv = input_plane(a, v);
+      cv = pv[0];
+    }
+    pu += col;
+    if (pv) pv += col;
+  } else {
+    src = a.src + (int64_t)blockIdx.y * a.plane + col;
+  }
+  auto value = [&](int yy) -> double {
+    if constexpr (PRODUCTS) {
+      const double t = (double)pu[(int64_t)yy * W] - cu;
+      return pv ? t * ((double)pv[(int64_t)yy * W] - cv) : t;
+    } else {
+      return src[(int64_t)yy * W];
+    }
+  };
+  double* dst = a.dst + (int64_t)blockIdx.y * a.plane;
+  const bool owner = inx && tid >= r && tid < kThreads - r;
+  double v = 0.0;
+  if (inx) {
+    const int lo = y0 - r > 0 ? y0 - r : 0;
+    const int hi = y0 + r < H - 1 ? y0 + r : H - 1;
+    for (int yy = lo; yy <= hi; ++yy) v += value(yy);
+  }
+  for (int y = y0; y < y1; ++y) {
+    if (y > y0 && inx) {
+      if (y + r < H) v += value(y + r);
+      if (y - r - 1 >= 0) v -= value(y - r - 1);
+    }
+    // alternate buffers: one barrier per row orders this row's writes
+    // before its reads, and the reads of two rows back before these writes
+    double* buf = rows + ((y - y0) & 1) * kThreads;
+    buf[tid] = v;
+    __syncthreads();
+    if (owner) {
+      double s = 0.0;
+      for (int d = -r; d <= r; ++d) s += buf[tid + d];
+      dst[(int64_t)y * W + x] = s;
+    }
+  }
+}
+
+struct AdjPairArgs {
+  const double* src;
+  double* dst;
+  int n;
+};
+
+__global__ void __launch_bounds__(256) adj_pair_sum_kernel(AdjPairArgs a) {
+  extern __shared__ float lds[];
+  double* part = reinterpret_cast<double*>(lds);  // [2][kThreads]
+  const int tid = threadIdx.x;
+  double s0 = 0.0, s1 = 0.0;
+  for (int i = tid; i < a.n; i += kThreads) {
+    s0 += a.src[2 * i];
+    s1 += a.src[2 * i + 1];
+  }
+  part[tid] = s0;
+  part[kThreads + tid] = s1;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      part[tid] += part[tid + s];
+      part[kThreads + tid] += part[kThreads + tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    a.dst[0] = part[0];
+    a.dst[1] = part[kThreads];
+  }
+}
+
+static hipError_t box_launch(AdjBoxArgs a, int planes, hipStream_t s) {
+  if (planes <= 0 || planes > 65535 || a.H < 1 || a.W < 1 || a.r < 0 || 2 * a.r >= kThreads)
+    return hipErrorInvalidValue;
+  a.plane = (int64_t)a.H * a.W;
+  a.seg_rows = kBoxSegRows < a.H ? kBoxSegRows : a.H;
+  a.tiles_x = (a.W + (kThreads - 2 * a.r) - 1) / (kThreads - 2 * a.r);
+  const int n_seg = (a.H + a.seg_rows - 1) / a.seg_rows;
+  const dim3 grid(a.tiles_x * n_seg, planes);
+  const size_t lds = 2 * kThreads * sizeof(double);
+  if (a.src)
+    hipLaunchKernelGGL(adj_box_kernel<false>, grid, dim3(kThreads), lds, s, a);
+  else
+    hipLaunchKernelGGL(adj_box_kernel<true>, grid, dim3(kThreads), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_box(const double* src, double* dst, int planes, int H, int W, int r,
+                      hipStream_t s) {
+  if (!src) return hipErrorInvalidValue;
+  AdjBoxArgs a = {};
+  a.src = src;
+  a.dst = dst;
+  a.H = H;
+  a.W = W;
+  a.r = r;
+  return box_launch(a, planes, s);
+}
+
+hipError_t launch_box_products(const float* guides, const float* noisy, int Q, int C, int H,
+                               int W, int r, double* dst, hipStream_t s) {
+  AdjBoxArgs a = {};
+  a.guides = guides;
+  a.noisy = noisy;
+  a.dst = dst;
+  a.H = H;
+  a.W = W;
+  a.r = r;
+  a.Q = Q;
+  a.C = C;
+  return box_launch(a, num_sums(Q, C), s);
+}
+
+hipError_t launch_pair_sum(const double* src, int n, double* dst, hipStream_t s) {
+  if (n < 0) return hipErrorInvalidValue;
+  AdjPairArgs a;
+  a.src = src;
+  a.dst = dst;
+  a.n = n;
+  hipLaunchKernelGGL(adj_pair_sum_kernel, dim3(1), dim3(kThreads), 2 * kThreads * sizeof(double), s,
+                     a);
+  return hipGetLastError();
+}
+
+}  // namespace flr

@@ -89,6 +89,37 @@ size_t unfused_coeff_offset(const flr_params* p) {
   return (mb + 255) / 256 * 256;
 }
 
+// Workspace of flr_denoise_backward, byte offsets of 256-aligned FP64
+// regions: the window sums of the anchored input products (later reused for
+// the window sums of the solve fields), the averaging fields, their window
+// sums (with averaging only), the solve fields, and the per-workgroup sums
+// of the regulariser gradients.
+struct BackwardLayout {
+  size_t sums, f1, s1, f2, red, total;
+};
+
+BackwardLayout backward_layout(const flr_params* p) {
+  const int Q = p->num_guides, C = p->num_channels;
+  const size_t pl = (size_t)p->height * p->width;
+  const size_t pblocks = (pl + 255) / 256;
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  const size_t ns = (size_t)flr::num_sums(Q, C), nf1 = (size_t)flr::num_avg_fields(Q, C);
+  BackwardLayout L{};
+  size_t o = 0;
+  L.sums = o;
+  o += al(ns * pl * sizeof(double));
+  L.f1 = o;
+  o += al(nf1 * pl * sizeof(double));
+  L.s1 = o;
+  if (p->average_coeffs) o += al(nf1 * pl * sizeof(double));
+  L.f2 = o;
+  o += al(ns * pl * sizeof(double));
+  L.red = o;
+  o += al(2 * pblocks * sizeof(double));
+  L.total = o;
+  return L;
+}
+
 }  // namespace
 
 extern "C" {
@@ -256,6 +287,79 @@ flr_status flr_denoise(const flr_params* p, const float* guides, const float* no
   if ((st = flr_moments(p, guides, noisy, moments, stream)) != FLR_OK) return st;
   if ((st = flr_solve(p, moments, coeffs, stream)) != FLR_OK) return st;
   return flr_apply(p, guides, coeffs, out, stream);
+}
+
+size_t flr_denoise_backward_workspace_bytes(const flr_params* p) {
+  if (flr_validate_params(p) != FLR_OK) return 0;
+  return backward_layout(p).total;
+}
+
+flr_status flr_denoise_backward(const flr_params* p, const float* guides, const float* noisy,
+                                const float* grad_out, float* grad_guides, float* grad_noisy,
+                                double* grad_reg, void* workspace, size_t workspace_bytes,
+                                void* stream) {
+  flr_status st = flr_validate_params(p);
+  if (st != FLR_OK) return st;
+  if ((st = check_ptrs({guides, noisy, grad_out, grad_guides, grad_noisy})) != FLR_OK) return st;
+  if (grad_reg && !aligned16(grad_reg)) return FLR_ERR_ALIGN;
+  if (p->flags) return FLR_ERR_MODE;
+  const BackwardLayout L = backward_layout(p);
+  if (!workspace || workspace_bytes < L.total) return FLR_ERR_WORKSPACE;
+  if (!aligned16(workspace)) return FLR_ERR_ALIGN;
+  const int Q = p->num_guides, C = p->num_channels;
+  const size_t pb = plane_bytes(p);
+  const void* ins[3] = {guides, noisy, grad_out};
+  const size_t nin[3] = {Q * pb, C * pb, C * pb};
+  const void* outs[4] = {grad_guides, grad_noisy, grad_reg, workspace};
+  const size_t nout[4] = {Q * pb, C * pb, grad_reg ? 2 * sizeof(double) : 0, L.total};
+  for (int o = 0; o < 4; ++o) {
+    if (!nout[o]) continue;
+    for (int i = 0; i < 3; ++i)
+      if (overlaps(outs[o], nout[o], ins[i], nin[i])) return FLR_ERR_ALIAS;
+    for (int o2 = o + 1; o2 < 4; ++o2)
+      if (nout[o2] && overlaps(outs[o], nout[o], outs[o2], nout[o2])) return FLR_ERR_ALIAS;
+  }
+  char* ws = static_cast<char*>(workspace);
+  double* sums = reinterpret_cast<double*>(ws + L.sums);
+  double* f1 = reinterpret_cast<double*>(ws + L.f1);
+  double* s1 = reinterpret_cast<double*>(ws + L.s1);
+  double* f2 = reinterpret_cast<double*>(ws + L.f2);
+  double* s2 = sums;  // the moment sums are dead once the solve fields exist
+  double* red = reinterpret_cast<double*>(ws + L.red);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int H = p->height, W = p->width, r = p->radius;
+  // moments: FP64 window sums of the anchored products
+  if (flr::launch_box_products(guides, noisy, Q, C, H, W, r, sums, s) != hipSuccess)
+    return FLR_ERR_HIP;
+  LaunchArgs a = base_args(p);
+  a.guides = guides;
+  a.noisy = noisy;
+  a.gout = grad_out;
+  a.sums = sums;
+  a.average = p->average_coeffs;
+  a.fout = f1;
+  if ((st = dispatch(Q, C, flr::K_ADJ_COEF, a, stream)) != FLR_OK) return st;
+  if (p->average_coeffs) {
+    if (flr::launch_box(f1, s1, flr::num_avg_fields(Q, C), H, W, r, s) != hipSuccess)
+      return FLR_ERR_HIP;
+    a.fin = s1;
+  }
+  a.fout = f2;
+  a.red = red;
+  if ((st = dispatch(Q, C, flr::K_ADJ_SOLVE, a, stream)) != FLR_OK) return st;
+  if (flr::launch_box(f2, s2, flr::num_sums(Q, C), H, W, r, s) != hipSuccess) return FLR_ERR_HIP;
+  a.sums = nullptr;
+  a.fin = s2;
+  a.fin2 = p->average_coeffs ? s1 : f1;
+  a.fout = nullptr;
+  a.out = grad_guides;
+  a.out2 = grad_noisy;
+  if ((st = dispatch(Q, C, flr::K_ADJ_GATHER, a, stream)) != FLR_OK) return st;
+  if (grad_reg) {
+    const int pblocks = (int)(((size_t)H * W + 255) / 256);
+    if (flr::launch_pair_sum(red, pblocks, grad_reg, s) != hipSuccess) return FLR_ERR_HIP;
+  }
+  return FLR_OK;
 }
 
 const char* flr_status_str(flr_status s) {

@@ -1225,6 +1225,12 @@ __global__ void __launch_bounds__(kThreads, 2) apply_avg_kernel(LaunchArgs a) {
   }
 }
 
+}  // namespace flr
+
+#include "flr_adjoint.hpp"
+
+namespace flr {
+
 // ---------------------------------------------------------------------------
 // Host-side launch of one kernel kind for a fixed (Q, C).
 template <typename K>
@@ -1286,6 +1292,15 @@ hipError_t launch_qc(int kind, const LaunchArgs& a, hipStream_t s) {
       return hipGetLastError();
     case K_APPLY_POINT:
       hipLaunchKernelGGL((apply_point_kernel<Q, C>), dim3(pblocks), dim3(256), 0, s, a);
+      return hipGetLastError();
+    case K_ADJ_COEF:
+      hipLaunchKernelGGL((adj_coef_kernel<Q, C>), dim3(pblocks), dim3(256), 0, s, a);
+      return hipGetLastError();
+    case K_ADJ_SOLVE:
+      hipLaunchKernelGGL((adj_solve_kernel<Q, C>), dim3(pblocks), dim3(256), 0, s, a);
+      return hipGetLastError();
+    case K_ADJ_GATHER:
+      hipLaunchKernelGGL((adj_gather_kernel<Q, C>), dim3(pblocks), dim3(256), 0, s, a);
       return hipGetLastError();
     default:
       return hipErrorInvalidValue;

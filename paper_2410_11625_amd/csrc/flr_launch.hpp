@@ -71,6 +71,10 @@ enum Kind : int {
   K_COEFFS = 6,       // moments -> solve -> coefficient planes, one kernel
   K_MOMENTS_A = 7,    // K_MOMENTS over the first slice of the product channels
   K_MOMENTS_B = 8,    // K_MOMENTS over the rest (split walks)
+  // adjoint (flr_denoise_backward)
+  K_ADJ_COEF = 9,     // coefficients from FP64 moment sums + the averaging fields
+  K_ADJ_SOLVE = 10,   // per-pixel solve adjoint -> fields whose window sums give dL/dg, dL/dy
+  K_ADJ_GATHER = 11,  // window sums of those fields contracted with g and y
 };
 
 struct LaunchArgs {
@@ -85,7 +89,36 @@ struct LaunchArgs {
   float eps, eps_mul;
   int reg_mode;
   int raw;
+  // adjoint kernels only
+  const float* gout;     // dL/d(output) [C][H][W]
+  const float* coeffs;   // unaveraged coefficient planes (b | a)
+  const double* sums;    // FP64 window sums of the anchored input products
+  const double* fin;     // FP64 field planes read (window sums)
+  const double* fin2;    // K_ADJ_GATHER: window sums of the averaging fields
+  double* fout;          // FP64 field planes written
+  double* red;           // K_ADJ_SOLVE: per-workgroup sums of dL/deps, dL/deps_mul
+  float* out2;           // K_ADJ_GATHER: dL/d(noisy)
+  int average;
 };
+
+// Adjoint field planes (FP64, [planes][H][W]).
+//  averaging fields, K_ADJ_COEF: G_c / n (C), g~_q G_c / n (Q*C), a_qc (Q*C);
+//  solve fields, K_ADJ_SOLVE: 2 dW / n (upper triangle), Gv / n (Q*C),
+//  e (Q), f (C) -- num_sums(Q, C) planes.
+__host__ __device__ constexpr int num_avg_fields(int Q, int C) { return C + 2 * Q * C; }
+
+// FP64 clipped window sums of `planes` planes of H x W (separable: running
+// column sums, then a row pass through LDS). src and dst must not overlap.
+hipError_t launch_box(const double* src, double* dst, int planes, int H, int W, int r,
+                      hipStream_t s);
+// FP64 clipped window sums of the num_sums(Q, C) anchored products of the
+// inputs, in the moment order g_q | y_c | g_p g_q (p <= q) | g_q y_c, each
+// input plane shifted by its value at pixel (0, 0).
+hipError_t launch_box_products(const float* guides, const float* noisy, int Q, int C, int H,
+                               int W, int r, double* dst, hipStream_t s);
+// dst[0..1] = sums over n entries of the interleaved pairs src[2i], src[2i+1]
+// (fixed order; one workgroup).
+hipError_t launch_pair_sum(const double* src, int n, double* dst, hipStream_t s);
 
 __host__ __device__ constexpr int num_sums(int Q, int C) {
   return Q + C + Q * (Q + 1) / 2 + Q * C;

@@ -34,8 +34,10 @@ from paper_2410_11625_amd._lib import FlrParams  # noqa: E402  (ctypes struct la
 def build(force: bool = False) -> str:
     srcs = [os.path.join(HERE, "emu.cpp"), os.path.join(CSRC, "flr_api.cpp")]
     net_src = os.path.join(CSRC, "flr_net.hip")
-    deps = srcs + [net_src, os.path.join(HERE, "hip", "hip_runtime.h"),
+    adj_src = os.path.join(CSRC, "flr_adjoint.hip")
+    deps = srcs + [net_src, adj_src, os.path.join(HERE, "hip", "hip_runtime.h"),
                    os.path.join(CSRC, "flr_device.hpp"), os.path.join(CSRC, "flr_launch.hpp"),
+                   os.path.join(CSRC, "flr_adjoint.hpp"),
                    os.path.join(INCLUDE, "flr.h"), os.path.join(INCLUDE, "flr_net.h")]
     if not force and os.path.exists(SO) and \
             os.path.getmtime(SO) >= max(os.path.getmtime(d) for d in deps):
@@ -43,7 +45,7 @@ def build(force: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     defs = [f"-D{d}" for d in VARIANT.split(",") if d]
     cmd = ["g++", "-std=c++20", "-O1", "-g", "-pthread", "-fno-extern-tls-init", "-shared", "-fPIC", *defs,
-           f"-I{HERE}", f"-I{INCLUDE}", f"-I{CSRC}", *srcs, "-x", "c++", net_src,
+           f"-I{HERE}", f"-I{INCLUDE}", f"-I{CSRC}", *srcs, "-x", "c++", net_src, adj_src,
            "-o", SO + ".tmp"]
     subprocess.run(cmd, check=True)
     os.replace(SO + ".tmp", SO)
@@ -128,6 +130,26 @@ class Emu:
         self.check(L.flr_net_forward(H, W, gp, yp, kp, op, wp, need, None), "flr_net_forward")
         return out.copy()
 
+    def backward(self, noisy, guides, grad_out, p: FlrParams):
+        """flr_denoise_backward -> (d_noisy, d_guides, [d_eps, d_eps_mul])."""
+        L = self.L
+        vp = ctypes.c_void_p
+        L.flr_denoise_backward_workspace_bytes.argtypes = [ctypes.POINTER(FlrParams)]
+        L.flr_denoise_backward_workspace_bytes.restype = ctypes.c_size_t
+        L.flr_denoise_backward.argtypes = [ctypes.POINTER(FlrParams), vp, vp, vp, vp, vp, vp, vp,
+                                           ctypes.c_size_t, vp]
+        gp, _ = self.buf(guides)
+        yp, _ = self.buf(noisy)
+        op, _ = self.buf(grad_out)
+        dgp, dg = self.buf(shape=guides.shape)
+        dyp, dy = self.buf(shape=noisy.shape)
+        rp, reg = self.buf(shape=(4,))
+        need = int(L.flr_denoise_backward_workspace_bytes(ctypes.byref(p)))
+        wp, _ = self.buf(shape=(need // 4,))
+        self.check(L.flr_denoise_backward(ctypes.byref(p), gp, yp, op, dgp, dyp, rp, wp, need,
+                                          None), "flr_denoise_backward")
+        return dy.copy(), dg.copy(), reg.copy().view(np.float64).copy()
+
     def moments(self, noisy, guides, p: FlrParams):
         Q, H, W = guides.shape
         C = noisy.shape[0]
@@ -158,6 +180,13 @@ def params(H, W, Q, C, r, eps=1e-3, mode=0, eps_mul=0.0, average=1, fused=1, raw
     return FlrParams(height=H, width=W, num_guides=Q, num_channels=C, radius=r, eps=eps,
                      eps_mul=eps_mul, reg_mode=mode, average_coeffs=average, fused=fused,
                      flags=1 if raw else 0, tile_rows=tile_rows)
+
+
+def _rel_err(got, want) -> float:
+    """max |got - want| / max(|want|, 1e-3 rms(want))."""
+    scale = max(float(np.sqrt(np.mean(np.asarray(want, np.float64) ** 2))), 1e-30)
+    den = np.maximum(np.abs(want), 1e-3 * scale)
+    return float(np.max(np.abs(got - want) / den))
 
 
 def run_case(spec: dict) -> dict:
@@ -191,6 +220,33 @@ def run_case(spec: dict) -> dict:
             d = np.abs(got - want)
             return {"maxabs": float(d.max()), "median": float(np.median(d)),
                     "within": float(np.mean(d <= 2e-3)), "shape": list(got.shape)}
+        if kind == "adjoint":
+            from oracle import flr_adjoint
+            if spec.get("frame") == "config":
+                fr = make_config(spec["config"], h=H, w=W)
+            else:
+                fr = random_frame(H, W, Q, C, seed=spec.get("seed", 0), smooth=1.5,
+                                  offset=spec.get("offset", 0.0))
+            noisy = fr["noisy"].astype(np.float32)
+            guides = fr["guides"].astype(np.float32)
+            G = np.random.default_rng(spec.get("seed", 0) + 11).standard_normal(
+                noisy.shape).astype(np.float32)
+            mname = spec.get("mode", "ridge")
+            eps, em = spec.get("eps", 1e-3), spec.get("eps_mul", 0.0)
+            avg = spec.get("average", 1)
+            p = params(H, W, Q, C, r, eps, {"ridge": 0, "paper": 1}[mname], em, avg, 0)
+            dy, dg, reg = emu.backward(noisy, guides, G, p)
+            # the ABI carries eps and eps_mul as FP32: the oracle takes the same values
+            ry, rg, re, rm = flr_adjoint.flr_backward(noisy, guides, G, r, float(np.float32(eps)),
+                                                      mname, float(np.float32(em)), bool(avg))
+            if spec.get("absolute"):
+                return {"dy_max": float(np.max(np.abs(dy - ry))),
+                        "dg_max": float(np.max(np.abs(dg - rg))),
+                        "reg_max": float(np.max(np.abs(reg - [re, rm]))),
+                        "g_max": float(np.max(np.abs(G)))}
+            return {"dy_rel": _rel_err(dy, ry), "dg_rel": _rel_err(dg, rg),
+                    "deps_rel": abs(reg[0] - re) / max(abs(re), 1e-30),
+                    "deps_mul_abs": abs(reg[1] - rm) / max(abs(rm), 1.0)}
         if spec.get("frame") == "config":
             fr = make_config(spec["config"], h=H, w=W)
         else:

@@ -149,3 +149,38 @@ def test_status_strings(L):
     for s in range(11):
         assert len(L.flr_status_str(s)) > 0
     assert L.flr_status_str(99) == b"unknown status"
+
+
+def test_backward_validates_before_launch(L):
+    p = _params()
+    H, W, Q, C = 64, 80, 4, 3
+    plane = H * W * 4
+    g, y, go = 0x10000000, 0x20000000, 0x30000000
+    dg, dy, reg, ws = 0x40000000, 0x50000000, 0x60000000, 0x70000000
+    need = L.flr_denoise_backward_workspace_bytes(ctypes.byref(p))
+    # FP64 moment sums and solve fields (num_sums planes each) plus the
+    # averaging fields and their sums (C + 2QC planes each)
+    ns, nf1 = Q + C + Q * (Q + 1) // 2 + Q * C, C + 2 * Q * C
+    assert need >= (2 * ns + 2 * nf1) * H * W * 8
+    p0 = _params(average_coeffs=0)
+    assert L.flr_denoise_backward_workspace_bytes(ctypes.byref(p0)) < need
+    assert L.flr_denoise_backward_workspace_bytes(ctypes.byref(_params(radius=-1))) == 0
+    bw = L.flr_denoise_backward
+    pp = ctypes.byref(p)
+    assert bw(pp, None, y, go, dg, dy, reg, ws, need, None) == 1
+    assert bw(pp, g, y, None, dg, dy, reg, ws, need, None) == 1
+    assert bw(pp, g, y, go, dg, None, reg, ws, need, None) == 1
+    assert bw(pp, g, y, go + 4, dg, dy, reg, ws, need, None) == 7
+    assert bw(pp, g, y, go, dg, dy, reg + 8, ws, need, None) == 7
+    # workspace missing or too small
+    assert bw(pp, g, y, go, dg, dy, reg, None, need, None) == 8
+    assert bw(pp, g, y, go, dg, dy, reg, ws, need - 16, None) == 8
+    # outputs overlapping an input, each other or the workspace
+    assert bw(pp, g, y, go, g + plane, dy, reg, ws, need, None) == 6
+    assert bw(pp, g, y, go, dg, go, reg, ws, need, None) == 6
+    assert bw(pp, g, y, go, dg, dg + 16, reg, ws, need, None) == 6
+    assert bw(pp, g, y, go, dg, dy, ws + 256, ws, need, None) == 6
+    assert bw(pp, g, y, go, dg, dy, reg, y, need, None) == 6
+    # the raw-moments flag and invalid parameters
+    assert bw(ctypes.byref(_params(flags=1)), g, y, go, dg, dy, reg, ws, need, None) == 9
+    assert bw(ctypes.byref(_params(num_guides=0)), g, y, go, dg, dy, reg, ws, need, None) == 5

@@ -65,3 +65,36 @@ def test_emulated_net_matches_oracle(H, W):
     assert res["shape"] == [4, H, W]
     # criteria and their reasons: tests/test_gpu_net.py
     assert res["median"] <= 1e-5 and res["within"] >= 0.99 and res["maxabs"] <= 2e-2, res
+
+
+# The adjoint (flr_denoise_backward) against the FP64 adjoint oracle given
+# the same FP32 eps and eps_mul. Its arithmetic is FP64 throughout (moments
+# from FP64 window sums of anchored products, FP64 fields and sums), so the
+# only difference left is the rounding of the FP32 outputs.
+ADJ_TOL = 1e-6
+
+
+@pytest.mark.parametrize("spec", [
+    dict(kind="adjoint", H=40, W=300, Q=8, C=3, r=8, frame="config", config=1),
+    dict(kind="adjoint", H=30, W=270, Q=4, C=1, r=8, frame="config", config=0),
+    dict(kind="adjoint", H=21, W=40, Q=3, C=2, r=3, mode="paper", eps=1e-2, eps_mul=0.2,
+         offset=2.0),
+    dict(kind="adjoint", H=21, W=40, Q=3, C=2, r=3, average=0),
+    dict(kind="adjoint", H=1, W=300, Q=2, C=1, r=2),
+    dict(kind="adjoint", H=70, W=1, Q=1, C=2, r=3),
+    dict(kind="adjoint", H=9, W=11, Q=2, C=1, r=20),
+    dict(kind="adjoint", H=25, W=520, Q=8, C=4, r=12, mode="paper", eps=1e-3, eps_mul=0.05),
+], ids=lambda s: "-".join(f"{k}{v}" for k, v in s.items() if k in ("H", "W", "Q", "C", "r",
+                                                                    "mode", "average")))
+def test_emulated_adjoint_matches_oracle(spec):
+    res = run_in_subprocess(spec)
+    assert res["dy_rel"] <= ADJ_TOL and res["dg_rel"] <= ADJ_TOL, res
+    assert res["deps_rel"] <= 1e-9 and res["deps_mul_abs"] <= 1e-9, res
+
+
+def test_emulated_adjoint_radius_zero():
+    """r = 0: out = noisy, so dL/dnoisy = G exactly and nothing reaches the
+    guides or the regularisers."""
+    res = run_in_subprocess(dict(kind="adjoint", H=7, W=9, Q=2, C=2, r=0, absolute=1))
+    assert res["dy_max"] == 0.0
+    assert res["dg_max"] <= 1e-12 * res["g_max"] and res["reg_max"] <= 1e-12, res
