@@ -254,6 +254,42 @@ def time_adjoint(flr, torch, np, sets, nsets, dev, stream, args):
             "workspace_bytes": int(ws.numel()), "steps": args.adjoint_steps}
 
 
+def time_lowres(flr, torch, np, sets, nsets, dev, stream, args):
+    """The paper's fast variant on the FLR workload's frames: 8x8 block
+    moments, Gaussian sigma 1.25 (taps -4..4) at the low resolution, solve,
+    bilinear model interpolation. Algorithmic HBM bytes per pixel: the
+    inputs read by the block sums (4 (Q + C)), the guides read and the
+    output written by the reconstruction (4 Q + 4 C); the low-resolution
+    planes (1/64 of the pixels) are not counted."""
+    p = flr.make_params(H, W, Q, C, 0, eps=EPS, average=False)
+    ws = torch.empty(flr.lowres_workspace_bytes(p, 8, 1.25, 4), dtype=torch.uint8, device=dev)
+    outs = [torch.empty((C, H, W), dtype=torch.float32, device=dev) for _ in range(nsets)]
+
+    def step(k):
+        noisy, guides, _ = sets[k % nsets]
+        flr.denoise_lowres(noisy, guides, 8, 1.25, 4, eps=EPS, out=outs[k % nsets], workspace=ws)
+
+    for k in range(3):
+        step(k)
+    torch.cuda.synchronize()
+    ev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(2))
+          for _ in range(args.lowres_steps)]
+    for k in range(args.lowres_steps):
+        ev[k][0].record(stream)
+        step(k)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    algo = (4 * (Q + C) + 4 * Q + 4 * C) * H * W
+    gbps = algo / (ms / 1e3) / 1e9
+    return {"ms_per_frame": round(ms, 5), "value": round(H * W / (ms / 1e3) / 1e6, 2),
+            "unit": "Mpixel/s", "algo_hbm_bytes": algo, "hbm_algo_GBps": round(gbps, 1),
+            "hbm_frac": round(gbps / PEAK_HBM_GBPS, 4),
+            "config": "the paper's fast variant: 8x8 block moments, Gaussian sigma 1.25 "
+                      "(taps -4..4) at 240x135, FP64 solve, bilinear models; eps 1e-3, ridge",
+            "paper_rtx2080ti_ms": 0.636, "steps": args.lowres_steps}
+
+
 def cpu_baseline():
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
@@ -283,6 +319,8 @@ def main(argv=None):
     ap.add_argument("--no-flnr", action="store_true", help="skip the FLNR timing")
     ap.add_argument("--flnr-steps", type=int, default=20)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--no-lowres", action="store_true", help="skip the fast-variant timing")
+    ap.add_argument("--lowres-steps", type=int, default=50)
     ap.add_argument("--adjoint-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter reference)")
@@ -397,6 +435,10 @@ def main(argv=None):
         flnr = time_flnr(flr, torch, np, sets, nsets, dev, stream, args)
         flnr["vs_flr_ms"] = round(flnr["ms_per_frame"] - ms_per_step, 5)
 
+    lowres = None
+    if not args.no_lowres:
+        lowres = time_lowres(flr, torch, np, sets, nsets, dev, stream, args)
+
     adjoint = None
     if not args.no_adjoint:
         adjoint = time_adjoint(flr, torch, np, sets, nsets, dev, stream, args)
@@ -458,6 +500,7 @@ def main(argv=None):
         "cpu_baseline": cpu,
         "flnr": flnr,
         "adjoint": adjoint,
+        "lowres": lowres,
     }
     print(json.dumps(line))
     return 0

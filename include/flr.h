@@ -20,7 +20,10 @@
  *                (moments + solve, then average + reconstruction), or as the
  *                three stage entry points (see flr_path);
  *   flr_denoise_backward  its adjoint: gradients with respect to the guides,
- *                the noisy image and the regularisers.
+ *                the noisy image and the regularisers;
+ *   flr_denoise_lowres  the paper's fast variant: block-downsampled moments,
+ *                a low-resolution Gaussian blur and solve, bilinearly
+ *                interpolated models.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -191,6 +194,28 @@ flr_status flr_denoise_backward(const flr_params* p, const float* guides, const 
                                 const float* grad_out, float* grad_guides, float* grad_noisy,
                                 double* grad_reg, void* workspace, size_t workspace_bytes,
                                 void* stream);
+
+/* The paper's fast variant (Sec. 3.2, its four-stage implementation): the
+ * outer-product moments summed over block x block pixel blocks (a strided
+ * box filter), a Gaussian blur of the low-resolution moment planes with
+ * weights exp(-d^2 / (2 sigma_low^2)) for |d| <= radius_low along each axis
+ * (zero outside the low-resolution grid; sigma_low = 0 keeps the block
+ * alone), one regularised solve per low-resolution pixel (reg_mode, eps,
+ * eps_mul in covariance scale, as flr_solve), and the models interpolated
+ * bilinearly at every full-resolution pixel (low-resolution coordinate
+ * (i + 0.5) / block - 0.5, clamped to the grid) and applied there:
+ * out_c = b_c + sum_q g_q a_qc. The last block row/column is ragged when
+ * the size is not a multiple of block. p->radius, p->average_coeffs and
+ * p->fused are not used; p->flags must be 0. block: 1, 2, 4, 8 or 16
+ * (else FLR_ERR_MODE); sigma_low finite and >= 0 (else FLR_ERR_EPS);
+ * radius_low 0..8 (else FLR_ERR_RADIUS). Workspace: FP64 low-resolution
+ * planes, flr_lowres_workspace_bytes(). Other errors as flr_denoise. */
+size_t flr_lowres_workspace_bytes(const flr_params* p, int32_t block, float sigma_low,
+                                  int32_t radius_low);
+flr_status flr_denoise_lowres(const flr_params* p, int32_t block, float sigma_low,
+                              int32_t radius_low, const float* guides, const float* noisy,
+                              float* out, void* workspace, size_t workspace_bytes,
+                              void* stream);
 
 /* Static description of a status code. */
 const char* flr_status_str(flr_status s);

@@ -30,7 +30,7 @@ STATUS_NAMES = {
 EXPORTED = ("flr_num_moment_planes", "flr_num_coeff_planes", "flr_denoise_workspace_bytes",
             "flr_moments", "flr_solve", "flr_coefficients", "flr_apply", "flr_denoise",
             "flr_status_str", "flr_validate_params", "flr_denoise_backward_workspace_bytes",
-            "flr_denoise_backward",
+            "flr_denoise_backward", "flr_lowres_workspace_bytes", "flr_denoise_lowres",
             # include/flr_net.h
             "flr_net_num_params", "flr_net_packed_bytes", "flr_net_pack", "flr_net_workspace_bytes",
             "flr_net_forward", "flr_flnr_workspace_bytes", "flr_flnr_denoise")
@@ -97,6 +97,11 @@ def lib() -> ctypes.CDLL:
     L.flr_denoise_backward_workspace_bytes.restype = ctypes.c_size_t
     L.flr_denoise_backward.argtypes = [P, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     L.flr_denoise_backward.restype = ctypes.c_int
+    L.flr_lowres_workspace_bytes.argtypes = [P, ctypes.c_int32, ctypes.c_float, ctypes.c_int32]
+    L.flr_lowres_workspace_bytes.restype = ctypes.c_size_t
+    L.flr_denoise_lowres.argtypes = [P, ctypes.c_int32, ctypes.c_float, ctypes.c_int32, vp, vp, vp,
+                                     vp, ctypes.c_size_t, vp]
+    L.flr_denoise_lowres.restype = ctypes.c_int
     L.flr_net_num_params.restype = ctypes.c_size_t
     L.flr_net_packed_bytes.restype = ctypes.c_size_t
     L.flr_net_pack.argtypes = [vp, vp, vp]

@@ -173,6 +173,47 @@ def denoise(noisy: torch.Tensor, guides: torch.Tensor, radius: int = 8, eps: flo
 
 
 # --------------------------------------------------------------------------
+# The paper's fast variant (flr_denoise_lowres)
+
+
+def lowres_workspace_bytes(p: FlrParams, block: int = 8, sigma_low: float = 1.25,
+                           radius_low: int = 4) -> int:
+    return int(lib().flr_lowres_workspace_bytes(ctypes.byref(p), block, sigma_low, radius_low))
+
+
+def denoise_lowres(noisy: torch.Tensor, guides: torch.Tensor, block: int = 8,
+                   sigma_low: float = 1.25, radius_low: int = 4, eps: float = 1e-3,
+                   mode: str = "ridge", eps_mul: float = 0.0, out: torch.Tensor | None = None,
+                   workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Block-downsampled moments, a low-resolution Gaussian blur (sigma_low,
+    taps -radius_low..radius_low) and solve, bilinearly interpolated models
+    -> [C,H,W]."""
+    _need(guides, "guides")
+    _need(noisy, "noisy")
+    Q, H, W = guides.shape
+    C = noisy.shape[0]
+    if noisy.shape[1:] != guides.shape[1:]:
+        raise ValueError("noisy and guides must have the same height and width")
+    p = make_params(H, W, Q, C, 0, eps=eps, mode=mode, eps_mul=eps_mul, average=False)
+    need = lowres_workspace_bytes(p, block, sigma_low, radius_low)
+    if need == 0:
+        st = lib().flr_denoise_lowres(ctypes.byref(p), block, sigma_low, radius_low, None, None,
+                                      None, None, 0, None)
+        check(st, "flr_denoise_lowres")
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=guides.device)
+    if out is None:
+        out = torch.empty((C, H, W), dtype=torch.float32, device=guides.device)
+    _need(out, "out")
+    check(lib().flr_denoise_lowres(ctypes.byref(p), block, sigma_low, radius_low,
+                                   guides.data_ptr(), noisy.data_ptr(), out.data_ptr(),
+                                   workspace.data_ptr(),
+                                   workspace.numel() * workspace.element_size(),
+                                   _stream(guides)), "flr_denoise_lowres")
+    return out
+
+
+# --------------------------------------------------------------------------
 # Adjoint (flr_denoise_backward) and autograd
 
 

@@ -75,50 +75,76 @@ __global__ void __launch_bounds__(256) adj_box_kernel(AdjBoxArgs a) {
   const double* src = nullptr;
   const float *pu = nullptr, *pv = nullptr;
   double cu = 0.0, cv = 0.0;
+  bool single = false;  // a first moment: the second factor is 1
   if constexpr (PRODUCTS) {
     int u, v;
     channel_factors(blockIdx.y, a.Q, a.C, &u, &v);
+    single = v < 0;
     pu = input_plane(a, u);
+    pv = single ? pu : input_plane(a, v);  // read either way, used only for products
     cu = pu[0];
-    if (v >= 0) {
-      pv = input_plane(a, v);
-      cv = pv[0];
-    }
+    cv = pv[0];
     pu += col;
-    if (pv) pv += col;
+    pv += col;
   } else {
     src = a.src + (int64_t)blockIdx.y * a.plane + col;
   }
   auto value = [&](int yy) -> double {
     if constexpr (PRODUCTS) {
       const double t = (double)pu[(int64_t)yy * W] - cu;
-      return pv ? t * ((double)pv[(int64_t)yy * W] - cv) : t;
+      const double w = (double)pv[(int64_t)yy * W] - cv;
+      return single ? t : t * w;
     } else {
       return src[(int64_t)yy * W];
     }
   };
+  auto clamp_row = [&](int yy) { return yy < 0 ? 0 : (yy >= H ? H - 1 : yy); };
   double* dst = a.dst + (int64_t)blockIdx.y * a.plane;
   const bool owner = inx && tid >= r && tid < kThreads - r;
+  // Loads are unconditional from clamped rows and masked afterwards, in
+  // batches of kRowBatch rows, so that a batch's loads are in flight
+  // together instead of one round trip per row.
+  constexpr int kRowBatch = 8;
   double v = 0.0;
-  if (inx) {
-    const int lo = y0 - r > 0 ? y0 - r : 0;
-    const int hi = y0 + r < H - 1 ? y0 + r : H - 1;
-    for (int yy = lo; yy <= hi; ++yy) v += value(yy);
-  }
-  for (int y = y0; y < y1; ++y) {
-    if (y > y0 && inx) {
-      if (y + r < H) v += value(y + r);
-      if (y - r - 1 >= 0) v -= value(y - r - 1);
+  {
+    const int lo = y0 - r, hi = y0 + r;
+    for (int yb = lo; yb <= hi; yb += kRowBatch) {
+      double t[kRowBatch];
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u) t[u] = value(clamp_row(yb + u));
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u) {
+        const int yy = yb + u;
+        v += (inx && yy <= hi && yy >= 0 && yy < H) ? t[u] : 0.0;
+      }
     }
-    // alternate buffers: one barrier per row orders this row's writes
-    // before its reads, and the reads of two rows back before these writes
-    double* buf = rows + ((y - y0) & 1) * kThreads;
-    buf[tid] = v;
-    __syncthreads();
-    if (owner) {
-      double s = 0.0;
-      for (int d = -r; d <= r; ++d) s += buf[tid + d];
-      dst[(int64_t)y * W + x] = s;
+  }
+  for (int yc = y0; yc < y1; yc += kRowBatch) {
+    double ent[kRowBatch], lea[kRowBatch];
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) {
+      const int y = yc + u;
+      const bool step = inx && y > y0 && y < y1;
+      const double e = value(clamp_row(y + r));
+      const double l = value(clamp_row(y - r - 1));
+      ent[u] = step && y + r < H ? e : 0.0;
+      lea[u] = step && y - r - 1 >= 0 ? l : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) {
+      const int y = yc + u;
+      if (y >= y1) break;  // uniform across the workgroup
+      v += ent[u] - lea[u];
+      // alternate buffers: one barrier per row orders this row's writes
+      // before its reads, and the reads of two rows back before these writes
+      double* buf = rows + ((y - y0) & 1) * kThreads;
+      buf[tid] = v;
+      __syncthreads();
+      if (owner) {
+        double s = 0.0;
+        for (int d = -r; d <= r; ++d) s += buf[tid + d];
+        dst[(int64_t)y * W + x] = s;
+      }
     }
   }
 }

@@ -54,29 +54,38 @@ __device__ __forceinline__ void load_anchors(const LaunchArgs& a, int64_t pl, do
 }
 
 // Anchored window means mu~, nu~, the central moments W (upper triangle)
-// and V of pixel idx from the FP64 window sums of the anchored products.
-template <int Q, int C>
-__device__ __forceinline__ void centred_moments(const double* S, int64_t pl, double inv_n,
-                                                double (&mu)[Q], double (&nu)[C],
-                                                double (&Hm)[Q * (Q + 1) / 2], double* V,
-                                                int vstride) {
+// and V from the raw sums of the anchored products, channel ch (moment
+// order g | y | g g^T upper | g y^T) read as sum(ch).
+template <int Q, int C, typename F>
+__device__ __forceinline__ void centred_from(F&& sum, double inv_n, double (&mu)[Q],
+                                             double (&nu)[C], double (&Hm)[Q * (Q + 1) / 2],
+                                             double* V, int vstride) {
   constexpr int NP = Q * (Q + 1) / 2;
 #pragma unroll
-  for (int q = 0; q < Q; ++q) mu[q] = S[q * pl] * inv_n;
+  for (int q = 0; q < Q; ++q) mu[q] = sum(q) * inv_n;
 #pragma unroll
-  for (int c = 0; c < C; ++c) nu[c] = S[(Q + c) * pl] * inv_n;
+  for (int c = 0; c < C; ++c) nu[c] = sum(Q + c) * inv_n;
 #pragma unroll
   for (int p = 0; p < Q; ++p) {
 #pragma unroll
     for (int q = p; q < Q; ++q)
-      Hm[tri<Q>(p, q)] = fma(S[(Q + C + tri<Q>(p, q)) * pl], inv_n, -mu[p] * mu[q]);
+      Hm[tri<Q>(p, q)] = fma(sum(Q + C + tri<Q>(p, q)), inv_n, -mu[p] * mu[q]);
   }
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
 #pragma unroll
     for (int c = 0; c < C; ++c)
-      V[q * vstride + c] = fma(S[(Q + C + NP + q * C + c) * pl], inv_n, -mu[q] * nu[c]);
+      V[q * vstride + c] = fma(sum(Q + C + NP + q * C + c), inv_n, -mu[q] * nu[c]);
   }
+}
+
+// The same from FP64 sum planes [num_sums][H][W] at pixel S.
+template <int Q, int C>
+__device__ __forceinline__ void centred_moments(const double* S, int64_t pl, double inv_n,
+                                                double (&mu)[Q], double (&nu)[C],
+                                                double (&Hm)[Q * (Q + 1) / 2], double* V,
+                                                int vstride) {
+  centred_from<Q, C>([&](int ch) { return S[ch * pl]; }, inv_n, mu, nu, Hm, V, vstride);
 }
 
 // Coefficients a of pixel j (FP64, from the moment sums) and the averaging
@@ -145,17 +154,27 @@ __global__ void __launch_bounds__(256) adj_solve_kernel(LaunchArgs a) {
       clamped[q] = Hm[tri<Q>(q, q)] < T(0);
       mo[q] = mu[q] + cg[q];
     }
+    // A~ and B: window sums of the averaging fields, or formed at the pixel
+    // (two wave-uniform paths, each with its loads issued together)
+    T A[Q * C];
+    if (a.average) {
 #pragma unroll
-    for (int c = 0; c < C; ++c)
-      B[c] = a.average ? a.fin[c * pl + idx] : (T)a.gout[c * pl + idx];
+      for (int c = 0; c < C; ++c) B[c] = a.fin[c * pl + idx];
+#pragma unroll
+      for (int k = 0; k < Q * C; ++k) A[k] = a.fin[(C + k) * pl + idx];
+    } else {
+      T gq[Q];
+#pragma unroll
+      for (int c = 0; c < C; ++c) B[c] = a.gout[c * pl + idx];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) gq[q] = (T)a.guides[q * pl + idx] - cg[q];
+#pragma unroll
+      for (int k = 0; k < Q * C; ++k) A[k] = gq[k / C] * B[k % C];
+    }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const T gq = a.average ? T(0) : (T)a.guides[q * pl + idx] - cg[q];
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const T Aqc = a.average ? a.fin[(C + q * C + c) * pl + idx] : gq * B[c];
-        R[q * C2 + C + c] = fma(-mu[q], B[c], Aqc);
-      }
+      for (int c = 0; c < C; ++c) R[q * C2 + C + c] = fma(-mu[q], B[c], A[q * C + c]);
     }
     regularise<Q, T>(Hm, mo, (T)a.eps, (T)a.eps_mul, a.reg_mode);
     T hd[Q];

@@ -120,6 +120,42 @@ BackwardLayout backward_layout(const flr_params* p) {
   return L;
 }
 
+// Workspace of flr_denoise_lowres: FP64 low-resolution planes, the block
+// sums (count + num_sums channels), their row-blurred copy and the models.
+struct LowresLayout {
+  int Hl, Wl;
+  size_t sums, tmp, coef, total;
+};
+
+LowresLayout lowres_layout(const flr_params* p, int block) {
+  const int Q = p->num_guides, C = p->num_channels;
+  LowresLayout L{};
+  L.Hl = (p->height + block - 1) / block;
+  L.Wl = (p->width + block - 1) / block;
+  const size_t pll = (size_t)L.Hl * L.Wl;
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  const size_t np = 1 + (size_t)flr::num_sums(Q, C);
+  size_t o = 0;
+  L.sums = o;
+  o += al(np * pll * sizeof(double));
+  L.tmp = o;
+  o += al(np * pll * sizeof(double));
+  L.coef = o;
+  o += al((size_t)(Q + 1) * C * pll * sizeof(double));
+  L.total = o;
+  return L;
+}
+
+flr_status validate_lowres(const flr_params* p, int block, float sigma, int radius_low) {
+  flr_status st = flr_validate_params(p);
+  if (st != FLR_OK) return st;
+  if (block < 1 || block > 16 || (block & (block - 1))) return FLR_ERR_MODE;
+  if (!isfinite(sigma) || sigma < 0.f) return FLR_ERR_EPS;
+  if (radius_low < 0 || radius_low > flr::kMaxLowresRadius) return FLR_ERR_RADIUS;
+  if (p->flags) return FLR_ERR_MODE;
+  return FLR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -360,6 +396,57 @@ flr_status flr_denoise_backward(const flr_params* p, const float* guides, const 
     if (flr::launch_pair_sum(red, pblocks, grad_reg, s) != hipSuccess) return FLR_ERR_HIP;
   }
   return FLR_OK;
+}
+
+size_t flr_lowres_workspace_bytes(const flr_params* p, int32_t block, float sigma_low,
+                                  int32_t radius_low) {
+  if (validate_lowres(p, block, sigma_low, radius_low) != FLR_OK) return 0;
+  return lowres_layout(p, block).total;
+}
+
+flr_status flr_denoise_lowres(const flr_params* p, int32_t block, float sigma_low,
+                              int32_t radius_low, const float* guides, const float* noisy,
+                              float* out, void* workspace, size_t workspace_bytes,
+                              void* stream) {
+  flr_status st = validate_lowres(p, block, sigma_low, radius_low);
+  if (st != FLR_OK) return st;
+  if ((st = check_ptrs({guides, noisy, out, workspace})) != FLR_OK) return st;
+  const LowresLayout L = lowres_layout(p, block);
+  if (workspace_bytes < L.total) return FLR_ERR_WORKSPACE;
+  const int Q = p->num_guides, C = p->num_channels;
+  const size_t pb = plane_bytes(p);
+  if (overlaps(out, C * pb, guides, Q * pb) || overlaps(out, C * pb, noisy, C * pb) ||
+      overlaps(workspace, L.total, guides, Q * pb) ||
+      overlaps(workspace, L.total, noisy, C * pb) || overlaps(workspace, L.total, out, C * pb))
+    return FLR_ERR_ALIAS;
+  char* ws = static_cast<char*>(workspace);
+  double* sums = reinterpret_cast<double*>(ws + L.sums);
+  double* tmp = reinterpret_cast<double*>(ws + L.tmp);
+  double* coef = reinterpret_cast<double*>(ws + L.coef);
+  LaunchArgs a = base_args(p);
+  a.guides = guides;
+  a.noisy = noisy;
+  a.block = block;
+  a.Hl = L.Hl;
+  a.Wl = L.Wl;
+  a.lr_R = radius_low;
+  for (int d = -radius_low; d <= radius_low; ++d)
+    a.taps[d + radius_low] =
+        sigma_low > 0.f ? exp(-(double)(d * d) / (2.0 * (double)sigma_low * (double)sigma_low))
+                        : (d == 0 ? 1.0 : 0.0);
+  a.fout = sums;
+  if ((st = dispatch(Q, C, flr::K_LR_BLOCK, a, stream)) != FLR_OK) return st;
+  if (flr::launch_lr_blur(sums, tmp, 1 + flr::num_sums(Q, C), L.Hl, L.Wl, radius_low, a.taps,
+                          reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
+    return FLR_ERR_HIP;
+  a.fin = tmp;
+  a.fout = coef;
+  if ((st = dispatch(Q, C, flr::K_LR_SOLVE, a, stream)) != FLR_OK) return st;
+  a.fin = coef;
+  a.fout = nullptr;
+  a.out = out;
+  a.lr_rows = flr::lr_apply_rows(Q, C, block);
+  return dispatch(Q, C, flr::K_LR_APPLY, a, stream);
 }
 
 const char* flr_status_str(flr_status s) {

@@ -1228,6 +1228,7 @@ __global__ void __launch_bounds__(kThreads, 2) apply_avg_kernel(LaunchArgs a) {
 }  // namespace flr
 
 #include "flr_adjoint.hpp"
+#include "flr_lowres.hpp"
 
 namespace flr {
 
@@ -1240,6 +1241,16 @@ static hipError_t launch_with_lds(K kernel, int blocks, size_t lds, const Launch
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kThreads), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename K>
+static hipError_t launch_with_lds_grid(K kernel, dim3 grid, size_t lds, const LaunchArgs& a,
+                                       hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kernel, grid, dim3(kThreads), lds, s, a);
   return hipGetLastError();
 }
 
@@ -1301,6 +1312,24 @@ hipError_t launch_qc(int kind, const LaunchArgs& a, hipStream_t s) {
       return hipGetLastError();
     case K_ADJ_GATHER:
       hipLaunchKernelGGL((adj_gather_kernel<Q, C>), dim3(pblocks), dim3(256), 0, s, a);
+      return hipGetLastError();
+    case K_LR_BLOCK: {
+      const int nx = (a.W + kThreads - 1) / kThreads;
+      hipLaunchKernelGGL((lr_block_kernel<Q, C>), dim3(nx, a.Hl), dim3(kThreads), 0, s, a);
+      return hipGetLastError();
+    }
+    case K_LR_SOLVE: {
+      const int lb = (int)(((int64_t)a.Hl * a.Wl + 255) / 256);
+      hipLaunchKernelGGL((lr_solve_kernel<Q, C>), dim3(lb), dim3(256), 0, s, a);
+      return hipGetLastError();
+    }
+    case K_LR_APPLY:
+      if (a.lr_rows > 0) {
+        const size_t l = lr_apply_lds_bytes(Q, C, a.block, a.lr_rows);
+        const dim3 grid((a.W + kThreads - 1) / kThreads, (a.H + a.lr_rows - 1) / a.lr_rows);
+        return launch_with_lds_grid(lr_apply_staged_kernel<Q, C>, grid, l, a, s);
+      }
+      hipLaunchKernelGGL((lr_apply_kernel<Q, C>), dim3(pblocks), dim3(256), 0, s, a);
       return hipGetLastError();
     default:
       return hipErrorInvalidValue;

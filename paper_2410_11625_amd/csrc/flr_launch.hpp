@@ -75,7 +75,14 @@ enum Kind : int {
   K_ADJ_COEF = 9,     // coefficients from FP64 moment sums + the averaging fields
   K_ADJ_SOLVE = 10,   // per-pixel solve adjoint -> fields whose window sums give dL/dg, dL/dy
   K_ADJ_GATHER = 11,  // window sums of those fields contracted with g and y
+  // the downsampled-moment variant (flr_denoise_lowres)
+  K_LR_BLOCK = 12,    // block sums of the anchored products -> low-resolution planes
+  K_LR_SOLVE = 13,    // Gaussian pass along columns + solve per low-resolution pixel
+  K_LR_APPLY = 14,    // bilinear model interpolation + reconstruction
 };
+
+// Longest Gaussian of the downsampled-moment variant (taps -R..R).
+constexpr int kMaxLowresRadius = 8;
 
 struct LaunchArgs {
   const float* guides;   // [Q][H][W]
@@ -99,7 +106,33 @@ struct LaunchArgs {
   double* red;           // K_ADJ_SOLVE: per-workgroup sums of dL/deps, dL/deps_mul
   float* out2;           // K_ADJ_GATHER: dL/d(noisy)
   int average;
+  // downsampled-moment variant only
+  int block, Hl, Wl, lr_R;
+  int lr_rows;  // K_LR_APPLY: full-resolution rows per workgroup (0: one lane per pixel)
+  double taps[2 * kMaxLowresRadius + 1];
 };
+
+// LDS of the staged model interpolation: rows x models x low-resolution
+// columns of FP64 (a workgroup's kThreads columns span at most
+// (kThreads - 1) / block + 3 low-resolution columns).
+inline size_t lr_apply_lds_bytes(int Q, int C, int block, int rows) {
+  return (size_t)rows * (Q + 1) * C * ((kThreads - 1) / block + 3) * sizeof(double);
+}
+// Rows per workgroup of the staged interpolation: the most of 8, 4, 2, 1
+// whose staging fits in 64 KiB; 0 when none does (one lane per pixel then).
+inline int lr_apply_rows(int Q, int C, int block) {
+  for (int rows = 8; rows >= 1; rows /= 2)
+    if (lr_apply_lds_bytes(Q, C, block, rows) <= 65536) return rows;
+  return 0;
+}
+
+// The downsampled-moment variant's low-resolution planes: the pixel count
+// n then the num_sums(Q, C) anchored product sums (FP64, [planes][Hl][Wl]);
+// models b~ (C) then a (Q*C) in anchored units (FP64).
+// dst[p][I][J] = sum_{|d|, |e| <= R} taps[d + R] taps[e + R] src[p][I + d][J + e]
+// (zero outside the grid): the separable low-resolution blur.
+hipError_t launch_lr_blur(const double* src, double* dst, int planes, int Hl, int Wl, int R,
+                          const double* taps, hipStream_t s);
 
 // Adjoint field planes (FP64, [planes][H][W]).
 //  averaging fields, K_ADJ_COEF: G_c / n (C), g~_q G_c / n (Q*C), a_qc (Q*C);

@@ -175,7 +175,13 @@ int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask, int ba
   const int row = (int)(l / 16), rl = (int)(l % 16);
   if (!((row_mask >> row) & 1) || !((bank_mask >> (rl / 4)) & 1)) return old;
   int s = -1;
-  if (ctrl > 0x110 && ctrl <= 0x11f) {
+  if (ctrl >= 0 && ctrl <= 0xff) {  // quad_perm: lane 4q + i reads 4q + sel_i
+    s = (int)(l & ~3u) + ((ctrl >> (2 * (rl & 3))) & 3);
+  } else if (ctrl == 0x140) {  // row_mirror
+    s = row * 16 + (15 - rl);
+  } else if (ctrl == 0x141) {  // row_half_mirror
+    s = row * 16 + (rl & 8) + (7 - (rl & 7));
+  } else if (ctrl > 0x110 && ctrl <= 0x11f) {
     const int k = ctrl - 0x110;
     s = rl >= k ? (int)l - k : -1;
   } else if (ctrl == 0x138) {  // wave_shr:1

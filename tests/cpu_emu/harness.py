@@ -35,9 +35,10 @@ def build(force: bool = False) -> str:
     srcs = [os.path.join(HERE, "emu.cpp"), os.path.join(CSRC, "flr_api.cpp")]
     net_src = os.path.join(CSRC, "flr_net.hip")
     adj_src = os.path.join(CSRC, "flr_adjoint.hip")
-    deps = srcs + [net_src, adj_src, os.path.join(HERE, "hip", "hip_runtime.h"),
+    lr_src = os.path.join(CSRC, "flr_lowres.hip")
+    deps = srcs + [net_src, adj_src, lr_src, os.path.join(HERE, "hip", "hip_runtime.h"),
                    os.path.join(CSRC, "flr_device.hpp"), os.path.join(CSRC, "flr_launch.hpp"),
-                   os.path.join(CSRC, "flr_adjoint.hpp"),
+                   os.path.join(CSRC, "flr_adjoint.hpp"), os.path.join(CSRC, "flr_lowres.hpp"),
                    os.path.join(INCLUDE, "flr.h"), os.path.join(INCLUDE, "flr_net.h")]
     if not force and os.path.exists(SO) and \
             os.path.getmtime(SO) >= max(os.path.getmtime(d) for d in deps):
@@ -45,7 +46,7 @@ def build(force: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     defs = [f"-D{d}" for d in VARIANT.split(",") if d]
     cmd = ["g++", "-std=c++20", "-O1", "-g", "-pthread", "-fno-extern-tls-init", "-shared", "-fPIC", *defs,
-           f"-I{HERE}", f"-I{INCLUDE}", f"-I{CSRC}", *srcs, "-x", "c++", net_src, adj_src,
+           f"-I{HERE}", f"-I{INCLUDE}", f"-I{CSRC}", *srcs, "-x", "c++", net_src, adj_src, lr_src,
            "-o", SO + ".tmp"]
     subprocess.run(cmd, check=True)
     os.replace(SO + ".tmp", SO)
@@ -150,6 +151,24 @@ class Emu:
                                           None), "flr_denoise_backward")
         return dy.copy(), dg.copy(), reg.copy().view(np.float64).copy()
 
+    def lowres(self, noisy, guides, p: FlrParams, block, sigma, radius_low):
+        """flr_denoise_lowres -> [C,H,W]."""
+        L = self.L
+        vp = ctypes.c_void_p
+        P = ctypes.POINTER(FlrParams)
+        L.flr_lowres_workspace_bytes.argtypes = [P, ctypes.c_int32, ctypes.c_float, ctypes.c_int32]
+        L.flr_lowres_workspace_bytes.restype = ctypes.c_size_t
+        L.flr_denoise_lowres.argtypes = [P, ctypes.c_int32, ctypes.c_float, ctypes.c_int32, vp, vp,
+                                         vp, vp, ctypes.c_size_t, vp]
+        gp, _ = self.buf(guides)
+        yp, _ = self.buf(noisy)
+        op, out = self.buf(shape=noisy.shape)
+        need = int(L.flr_lowres_workspace_bytes(ctypes.byref(p), block, sigma, radius_low))
+        wp, _ = self.buf(shape=(need // 4,))
+        self.check(L.flr_denoise_lowres(ctypes.byref(p), block, sigma, radius_low, gp, yp, op, wp,
+                                        need, None), "flr_denoise_lowres")
+        return out.copy()
+
     def moments(self, noisy, guides, p: FlrParams):
         Q, H, W = guides.shape
         C = noisy.shape[0]
@@ -220,6 +239,24 @@ def run_case(spec: dict) -> dict:
             d = np.abs(got - want)
             return {"maxabs": float(d.max()), "median": float(np.median(d)),
                     "within": float(np.mean(d <= 2e-3)), "shape": list(got.shape)}
+        if kind == "lowres":
+            from oracle import flr_lowres
+            if spec.get("frame") == "config":
+                fr = make_config(spec["config"], h=H, w=W)
+            else:
+                fr = random_frame(H, W, Q, C, seed=spec.get("seed", 0), smooth=1.5,
+                                  offset=spec.get("offset", 0.0))
+            noisy = fr["noisy"].astype(np.float32)
+            guides = fr["guides"].astype(np.float32)
+            mname = spec.get("mode", "ridge")
+            eps, em = spec.get("eps", 1e-3), spec.get("eps_mul", 0.0)
+            B, sig, RL = spec.get("block", 8), spec.get("sigma", 1.25), spec.get("radius_low", 4)
+            p = params(H, W, Q, C, 0, eps, {"ridge": 0, "paper": 1}[mname], em, 0, 0)
+            got = emu.lowres(noisy, guides, p, B, sig, RL)
+            f32 = lambda v: float(np.float32(v))  # noqa: E731  (the ABI's FP32 scalars)
+            want = flr_lowres.lowres_reference(noisy, guides, B, f32(sig), RL, f32(eps), mname,
+                                               f32(em))
+            return {"rel": _rel_err(got, want)}
         if kind == "adjoint":
             from oracle import flr_adjoint
             if spec.get("frame") == "config":

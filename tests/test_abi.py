@@ -184,3 +184,25 @@ def test_backward_validates_before_launch(L):
     # the raw-moments flag and invalid parameters
     assert bw(ctypes.byref(_params(flags=1)), g, y, go, dg, dy, reg, ws, need, None) == 9
     assert bw(ctypes.byref(_params(num_guides=0)), g, y, go, dg, dy, reg, ws, need, None) == 5
+
+
+def test_lowres_validates_before_launch(L):
+    p = _params(height=100, width=90, num_guides=4, num_channels=3)
+    g, y, o, ws = 0x10000000, 0x20000000, 0x30000000, 0x40000000
+    need = L.flr_lowres_workspace_bytes(ctypes.byref(p), 8, 1.25, 4)
+    Hl, Wl, ns = 13, 12, 4 + 3 + 10 + 12
+    assert need >= (2 * (1 + ns) + 5 * 3) * Hl * Wl * 8
+    assert L.flr_lowres_workspace_bytes(ctypes.byref(p), 3, 1.25, 4) == 0
+    lw = L.flr_denoise_lowres
+    pp = ctypes.byref(p)
+    assert lw(pp, 6, 1.25, 4, g, y, o, ws, need, None) == 9      # block not a power of two
+    assert lw(pp, 32, 1.25, 4, g, y, o, ws, need, None) == 9     # block > 16
+    assert lw(pp, 8, -1.0, 4, g, y, o, ws, need, None) == 4      # negative sigma
+    assert lw(pp, 8, float("nan"), 4, g, y, o, ws, need, None) == 4
+    assert lw(pp, 8, 1.25, 9, g, y, o, ws, need, None) == 3      # radius_low > 8
+    assert lw(pp, 8, 1.25, 4, None, y, o, ws, need, None) == 1
+    assert lw(pp, 8, 1.25, 4, g, y, o + 4, ws, need, None) == 7
+    assert lw(pp, 8, 1.25, 4, g, y, o, ws, need - 8, None) == 8
+    assert lw(pp, 8, 1.25, 4, g, y, g, ws, need, None) == 6
+    assert lw(pp, 8, 1.25, 4, g, y, o, y, need, None) == 6
+    assert lw(ctypes.byref(_params(flags=1)), 8, 1.25, 4, g, y, o, ws, need, None) == 9

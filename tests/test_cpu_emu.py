@@ -98,3 +98,23 @@ def test_emulated_adjoint_radius_zero():
     res = run_in_subprocess(dict(kind="adjoint", H=7, W=9, Q=2, C=2, r=0, absolute=1))
     assert res["dy_max"] == 0.0
     assert res["dg_max"] <= 1e-12 * res["g_max"] and res["reg_max"] <= 1e-12, res
+
+
+# The paper's fast variant (flr_denoise_lowres) against its FP64 oracle with
+# the same FP32 eps, eps_mul and sigma; FP64 throughout but the FP32 output.
+@pytest.mark.parametrize("spec", [
+    dict(kind="lowres", H=40, W=300, Q=8, C=3, r=0, frame="config", config=1),
+    dict(kind="lowres", H=37, W=41, Q=3, C=2, r=0, block=4, sigma=1.0, radius_low=2,
+         mode="paper", eps=1e-2, eps_mul=0.2, offset=2.0),
+    dict(kind="lowres", H=1, W=300, Q=2, C=1, r=0),
+    dict(kind="lowres", H=70, W=5, Q=1, C=2, r=0, block=16, sigma=0.0, radius_low=0),
+    dict(kind="lowres", H=33, W=270, Q=4, C=4, r=0, block=2, sigma=2.0, radius_low=8),
+    # block 1: staged interpolation over two rows; with Q=8, C=4 it does not
+    # fit in LDS and one lane per pixel interpolates instead
+    dict(kind="lowres", H=45, W=600, Q=4, C=2, r=0, block=1, sigma=0.7, radius_low=3),
+    dict(kind="lowres", H=20, W=270, Q=8, C=4, r=0, block=1, sigma=0.7, radius_low=1),
+], ids=lambda s: "-".join(f"{k}{v}" for k, v in s.items() if k in ("H", "W", "Q", "C", "block",
+                                                                    "mode")))
+def test_emulated_lowres_matches_oracle(spec):
+    res = run_in_subprocess(spec)
+    assert res["rel"] <= 1e-6, res
