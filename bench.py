@@ -290,6 +290,75 @@ def time_lowres(flr, torch, np, sets, nsets, dev, stream, args):
             "paper_rtx2080ti_ms": 0.636, "steps": args.lowres_steps}
 
 
+def time_batch(flr, torch, np, sets, nsets, dev, stream, args):
+    """Batched serving of 16 frames: 4 at 1280x720, 6 at 1920x1080, 4 at
+    2560x1440 and 2 joint 1920x1080 frames from 960x540 noisy inputs (2x
+    upsampling), 8 guides + constant, r 8, eps 1e-3. Segment lengths from
+    the autotuner; the batch (one launch per stage) captured in a HIP graph
+    and replayed. Frames of one size are shifted copies of one synthetic
+    frame (distinct memory, same statistics)."""
+    from paper_2410_11625_amd import autotune
+    from synth import make_config
+
+    def dev_frame(fr):
+        return (torch.from_numpy(fr["guides"]).to(dev), torch.from_numpy(fr["noisy"]).to(dev))
+
+    g720, y720 = dev_frame(make_config(1, seed=400, h=720, w=1280))
+    g1440, y1440 = dev_frame(make_config(1, seed=402, h=1440, w=2560))
+    glo, ylo = dev_frame(make_config(1, seed=412, h=540, w=960))
+    frames = []
+    for k in range(4):
+        frames.append(dict(guides=g720.roll(k, dims=2).contiguous(),
+                           noisy=y720.roll(k, dims=2).contiguous()))
+    for k in range(6):
+        y, g, _ = sets[k % nsets]
+        frames.append(dict(guides=g.roll(k // nsets, dims=2).contiguous(),
+                           noisy=y.roll(k // nsets, dims=2).contiguous()))
+    for k in range(4):
+        frames.append(dict(guides=g1440.roll(k, dims=2).contiguous(),
+                           noisy=y1440.roll(k, dims=2).contiguous()))
+    for k in range(2):
+        frames.append(dict(guides=sets[k][1], guides_low=glo.roll(k, dims=2).contiguous(),
+                           noisy=ylo.roll(k, dims=2).contiguous()))
+    frames = autotune.tune_frames(frames, radius=R, eps=EPS)
+    b = flr.Batch(frames, radius=R, eps=EPS)
+    for _ in range(3):
+        b.run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.batch_steps):
+        b.run()
+    e1.record()
+    torch.cuda.synchronize()
+    eager_ms = e0.elapsed_time(e1) / args.batch_steps
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        b.run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        b.run()
+    g.replay()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.batch_steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.batch_steps
+    pix = sum(int(f["guides"].shape[1]) * int(f["guides"].shape[2]) for f in frames)
+    rows = {f"{f['noisy'].shape[1]}x{f['noisy'].shape[2]}": f["tile_rows"] for f in frames}
+    return {"ms_per_batch": round(ms, 5), "value": round(pix / (ms / 1e3) / 1e6, 2),
+            "unit": "Mpixel/s", "frames": len(frames), "output_pixels": pix,
+            "eager_ms_per_batch": round(eager_ms, 5), "tile_rows": rows,
+            "config": "4x1280x720 + 6x1920x1080 + 4x2560x1440 + 2 joint 1920x1080 from "
+                      "960x540 (2x), 8 guides + constant, r 8, eps 1e-3; graph replay",
+            "steps": args.batch_steps}
+
+
 def cpu_baseline():
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
@@ -320,6 +389,8 @@ def main(argv=None):
     ap.add_argument("--flnr-steps", type=int, default=20)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-lowres", action="store_true", help="skip the fast-variant timing")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-serving timing")
+    ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--lowres-steps", type=int, default=50)
     ap.add_argument("--adjoint-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -439,6 +510,10 @@ def main(argv=None):
     if not args.no_lowres:
         lowres = time_lowres(flr, torch, np, sets, nsets, dev, stream, args)
 
+    batch = None
+    if not args.no_batch:
+        batch = time_batch(flr, torch, np, sets, nsets, dev, stream, args)
+
     adjoint = None
     if not args.no_adjoint:
         adjoint = time_adjoint(flr, torch, np, sets, nsets, dev, stream, args)
@@ -501,6 +576,7 @@ def main(argv=None):
         "flnr": flnr,
         "adjoint": adjoint,
         "lowres": lowres,
+        "batch": batch,
     }
     print(json.dumps(line))
     return 0

@@ -217,6 +217,74 @@ flr_status flr_denoise_lowres(const flr_params* p, int32_t block, float sigma_lo
                               float* out, void* workspace, size_t workspace_bytes,
                               void* stream);
 
+/* Batched serving (Sec. 3.2 measures whole frames; joint denoising and
+ * upsampling, Sec. 3.2, is one of the frame kinds): frames of uneven size
+ * through the two-pass path with coefficient averaging, each stage one
+ * launch over the tiles of every frame. A plain frame has its noisy input
+ * on the output grid. A joint frame has it on a grid `up` times coarser in
+ * each direction (up = 2, 4 or 8, height = up * noisy_height, width =
+ * up * noisy_width) together with guides rasterised on that grid
+ * (guides_low): its coefficients are fitted and window-averaged there (in
+ * FP64: the models are then applied to guides the fit did not see, which
+ * exposes the error an FP32 factorisation leaves in them), interpolated
+ * bilinearly (half-pixel centres, clamped) at every output pixel and
+ * applied to the full-resolution guides. */
+#define FLR_BATCH_MAX 64
+
+typedef struct {
+  int32_t height, width;              /* output grid, and the guides' */
+  int32_t noisy_height, noisy_width;  /* the noisy input's grid */
+  int32_t tile_rows;                  /* rows per workgroup of the coefficient walk; 0 = planned */
+  const float* guides;                /* [Q][height][width] */
+  const float* guides_low;            /* joint frames: [Q][noisy_height][noisy_width]; else NULL */
+  const float* noisy;                 /* [C][noisy_height][noisy_width] */
+  float* out;                         /* [C][height][width] */
+} flr_frame;
+
+/* Launch plan of a batch, filled by flr_batch_plan and only read by
+ * flr_batch_run. It points into the plan's workspace, which must stay
+ * allocated and untouched while the plan is used. */
+typedef struct {
+  flr_params params;
+  int32_t num_frames, num_joint;
+  int32_t coeff_blocks, apply_blocks, up_blocks;
+  void* walk_table;                   /* device: per-frame launch arguments of the walk */
+  void* apply_table;                  /* device: ... of the averaging kernel (plain frames) */
+  void* up_table;                     /* device: ... of the upsampling kernel (joint frames) */
+  int* walk_starts;                   /* device: workgroup offsets of the three launches */
+  /* joint frames, fitted on the noisy grid in FP64 */
+  const float* joint_guides[FLR_BATCH_MAX]; /* the frame's guides_low */
+  const float* joint_noisy[FLR_BATCH_MAX];  /* the frame's noisy input */
+  double* joint_sums[FLR_BATCH_MAX];        /* device: window count and moment sums */
+  double* joint_models[FLR_BATCH_MAX];      /* device: the fitted models */
+  double* joint_mean[FLR_BATCH_MAX];        /* device: ... window-averaged */
+  int32_t joint_height[FLR_BATCH_MAX], joint_width[FLR_BATCH_MAX];
+} flr_batch;
+
+/* Workspace bytes of a batch (0 if invalid): the launch tables, the
+ * coefficient image (FP32) of every plain frame, and for every joint frame
+ * FP64 images on its noisy grid: the window count and moment sums, the
+ * models and their window means. */
+size_t flr_batch_workspace_bytes(const flr_params* p, const flr_frame* frames,
+                                 int32_t num_frames);
+
+/* Validates the batch (p: num_guides, num_channels, radius, eps, eps_mul,
+ * reg_mode; average_coeffs must be 1, flags 0; every frame as flr_denoise
+ * would check it; at most FLR_BATCH_MAX frames; the walk must fit one pass,
+ * Q + C + Q(Q+1)/2 + Q*C <= 78, else FLR_ERR_CHANNELS), plans every frame's
+ * tiles (tile_rows, or the planned segment length), orders the walk's
+ * frames largest first, and copies the launch tables into the workspace
+ * (a synchronous copy: not for graph capture). */
+flr_status flr_batch_plan(const flr_params* p, const flr_frame* frames, int32_t num_frames,
+                          void* workspace, size_t workspace_bytes, flr_batch* plan);
+
+/* Runs a planned batch on `stream`: the coefficient walk over the plain
+ * frames, their averaging and reconstruction; per joint frame the FP64
+ * window sums, solve and window mean of the models; the upsampling and
+ * reconstruction over the joint frames. Kernel launches only, so the call can be captured
+ * in a HIP graph and replayed. */
+flr_status flr_batch_run(const flr_batch* plan, void* stream);
+
 /* Static description of a status code. */
 const char* flr_status_str(flr_status s);
 

@@ -31,6 +31,7 @@ EXPORTED = ("flr_num_moment_planes", "flr_num_coeff_planes", "flr_denoise_worksp
             "flr_moments", "flr_solve", "flr_coefficients", "flr_apply", "flr_denoise",
             "flr_status_str", "flr_validate_params", "flr_denoise_backward_workspace_bytes",
             "flr_denoise_backward", "flr_lowres_workspace_bytes", "flr_denoise_lowres",
+            "flr_batch_workspace_bytes", "flr_batch_plan", "flr_batch_run",
             # include/flr_net.h
             "flr_net_num_params", "flr_net_packed_bytes", "flr_net_pack", "flr_net_workspace_bytes",
             "flr_net_forward", "flr_flnr_workspace_bytes", "flr_flnr_denoise")
@@ -50,6 +51,47 @@ class FlrParams(ctypes.Structure):
         ("fused", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
         ("tile_rows", ctypes.c_int32),
+    ]
+
+
+FLR_BATCH_MAX = 64
+
+
+class FlrFrame(ctypes.Structure):
+    """flr_frame: one frame of a batch."""
+    _fields_ = [
+        ("height", ctypes.c_int32),
+        ("width", ctypes.c_int32),
+        ("noisy_height", ctypes.c_int32),
+        ("noisy_width", ctypes.c_int32),
+        ("tile_rows", ctypes.c_int32),
+        ("guides", ctypes.c_void_p),
+        ("guides_low", ctypes.c_void_p),
+        ("noisy", ctypes.c_void_p),
+        ("out", ctypes.c_void_p),
+    ]
+
+
+class FlrBatch(ctypes.Structure):
+    """flr_batch: a planned batch (filled by flr_batch_plan)."""
+    _fields_ = [
+        ("params", FlrParams),
+        ("num_frames", ctypes.c_int32),
+        ("num_joint", ctypes.c_int32),
+        ("coeff_blocks", ctypes.c_int32),
+        ("apply_blocks", ctypes.c_int32),
+        ("up_blocks", ctypes.c_int32),
+        ("walk_table", ctypes.c_void_p),
+        ("apply_table", ctypes.c_void_p),
+        ("up_table", ctypes.c_void_p),
+        ("walk_starts", ctypes.c_void_p),
+        ("joint_guides", ctypes.c_void_p * FLR_BATCH_MAX),
+        ("joint_noisy", ctypes.c_void_p * FLR_BATCH_MAX),
+        ("joint_sums", ctypes.c_void_p * FLR_BATCH_MAX),
+        ("joint_models", ctypes.c_void_p * FLR_BATCH_MAX),
+        ("joint_mean", ctypes.c_void_p * FLR_BATCH_MAX),
+        ("joint_height", ctypes.c_int32 * FLR_BATCH_MAX),
+        ("joint_width", ctypes.c_int32 * FLR_BATCH_MAX),
     ]
 
 
@@ -102,6 +144,14 @@ def lib() -> ctypes.CDLL:
     L.flr_denoise_lowres.argtypes = [P, ctypes.c_int32, ctypes.c_float, ctypes.c_int32, vp, vp, vp,
                                      vp, ctypes.c_size_t, vp]
     L.flr_denoise_lowres.restype = ctypes.c_int
+    F = ctypes.POINTER(FlrFrame)
+    Bp = ctypes.POINTER(FlrBatch)
+    L.flr_batch_workspace_bytes.argtypes = [P, F, ctypes.c_int32]
+    L.flr_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.flr_batch_plan.argtypes = [P, F, ctypes.c_int32, vp, ctypes.c_size_t, Bp]
+    L.flr_batch_plan.restype = ctypes.c_int
+    L.flr_batch_run.argtypes = [Bp, vp]
+    L.flr_batch_run.restype = ctypes.c_int
     L.flr_net_num_params.restype = ctypes.c_size_t
     L.flr_net_packed_bytes.restype = ctypes.c_size_t
     L.flr_net_pack.argtypes = [vp, vp, vp]

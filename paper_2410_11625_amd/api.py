@@ -11,8 +11,8 @@ import ctypes
 
 import torch
 
-from ._lib import (FLR_FLAG_RAW_MOMENTS, FLR_REG_PAPER, FLR_REG_RIDGE, FLRError, FlrParams,
-                   check, lib)
+from ._lib import (FLR_BATCH_MAX, FLR_FLAG_RAW_MOMENTS, FLR_REG_PAPER, FLR_REG_RIDGE, FLRError,
+                   FlrBatch, FlrFrame, FlrParams, check, lib)
 
 _MODES = {"ridge": FLR_REG_RIDGE, "paper": FLR_REG_PAPER}
 # flr_denoise execution paths (flr_path in the C header)
@@ -211,6 +211,69 @@ def denoise_lowres(noisy: torch.Tensor, guides: torch.Tensor, block: int = 8,
                                    workspace.numel() * workspace.element_size(),
                                    _stream(guides)), "flr_denoise_lowres")
     return out
+
+
+# --------------------------------------------------------------------------
+# Batched serving (flr_batch_plan / flr_batch_run)
+
+
+class Batch:
+    """Frames of uneven size through the two-pass path, each stage one
+    launch over all frames. ``frames``: dicts with ``guides`` [Q,H,W] and
+    ``noisy`` [C,h,w] (h, w = H, W, or H/up, W/up for a joint frame, which
+    then also gives ``guides_low`` [Q,h,w]); optional ``out`` [C,H,W] and
+    ``tile_rows``. ``run()`` only launches kernels (graph-capturable); the
+    plan and its workspace stay with the object."""
+
+    def __init__(self, frames, radius: int = 8, eps: float = 1e-3, mode: str = "ridge",
+                 eps_mul: float = 0.0):
+        if not 1 <= len(frames) <= FLR_BATCH_MAX:
+            raise ValueError(f"1..{FLR_BATCH_MAX} frames")
+        Q = frames[0]["guides"].shape[0]
+        C = frames[0]["noisy"].shape[0]
+        dev = frames[0]["guides"].device
+        self._keep = []
+        arr = (FlrFrame * len(frames))()
+        self.outs = []
+        for i, f in enumerate(frames):
+            g, y = f["guides"], f["noisy"]
+            _need(g, "guides")
+            _need(y, "noisy")
+            low = f.get("guides_low")
+            if low is not None:
+                _need(low, "guides_low")
+            if g.shape[0] != Q or y.shape[0] != C:
+                raise ValueError("every frame needs the same guide and channel counts")
+            out = f.get("out")
+            if out is None:
+                out = torch.empty((C,) + tuple(g.shape[1:]), dtype=torch.float32, device=dev)
+            _need(out, "out")
+            self.outs.append(out)
+            self._keep += [g, y, out] + ([low] if low is not None else [])
+            arr[i] = FlrFrame(height=g.shape[1], width=g.shape[2], noisy_height=y.shape[1],
+                              noisy_width=y.shape[2], tile_rows=int(f.get("tile_rows", 0)),
+                              guides=g.data_ptr(),
+                              guides_low=low.data_ptr() if low is not None else None,
+                              noisy=y.data_ptr(), out=out.data_ptr())
+        self.params = make_params(1, 1, Q, C, radius, eps=eps, mode=mode, eps_mul=eps_mul,
+                                  average=True, fused="two_pass")
+        self._frames = arr
+        need = int(lib().flr_batch_workspace_bytes(ctypes.byref(self.params), arr, len(frames)))
+        if need == 0:
+            check(lib().flr_batch_plan(ctypes.byref(self.params), arr, len(frames), None, 0,
+                                       None), "flr_batch_plan")
+        self.workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+        self.plan = FlrBatch()
+        check(lib().flr_batch_plan(ctypes.byref(self.params), arr, len(frames),
+                                   self.workspace.data_ptr(), need, ctypes.byref(self.plan)),
+              "flr_batch_plan")
+        self.device = dev
+
+    def run(self):
+        check(lib().flr_batch_run(ctypes.byref(self.plan),
+                                  ctypes.c_void_p(torch.cuda.current_stream(self.device)
+                                                  .cuda_stream)), "flr_batch_run")
+        return self.outs
 
 
 # --------------------------------------------------------------------------

@@ -18,6 +18,8 @@ namespace flr {
 constexpr int kBoxSegRows = 64;
 
 struct AdjBoxArgs {
+  const float* srcf;   // BOX_MEAN32: FP32 planes, averaged into dstf
+  float* dstf;
   const double* src;   // FP64 planes, or NULL for the product channels below
   const float* guides; // product channels: guides [Q][H][W]
   const float* noisy;  // product channels: noisy [C][H][W]
@@ -25,6 +27,7 @@ struct AdjBoxArgs {
   int64_t plane;  // elements per plane
   int H, W, r, seg_rows, tiles_x;
   int Q, C;
+  int count_first;  // BOX_PRODUCTS: plane 0 is the window pixel count, channels follow
 };
 
 // Input plane v of the product channels: a guide (v < Q) or a noisy channel.
@@ -57,11 +60,15 @@ __device__ __forceinline__ void channel_factors(int ch, int Q, int C, int* u, in
   *v = Q + ch % C;
 }
 
-// Window sums of FP64 planes (a.src) or, with a.src NULL, of the anchored
-// products of the inputs: channel blockIdx.y is (x_u - c_u)(x_v - c_v) or
-// x_u - c_u, with c the plane's value at pixel (0, 0).
-template <bool PRODUCTS>
+// Window sums of FP64 planes (BOX_SUM64), of the anchored products of the
+// inputs (BOX_PRODUCTS: channel blockIdx.y is (x_u - c_u)(x_v - c_v) or
+// x_u - c_u, with c the plane's value at pixel (0, 0)), or window means of
+// FP32 planes (BOX_MEAN32: FP64 sums divided by the pixel count).
+enum BoxSource : int { BOX_SUM64 = 0, BOX_PRODUCTS = 1, BOX_MEAN32 = 2, BOX_MEAN64 = 3 };
+
+template <int SRC>
 __global__ void __launch_bounds__(256) adj_box_kernel(AdjBoxArgs a) {
+  constexpr bool PRODUCTS = SRC == BOX_PRODUCTS;
   extern __shared__ float lds[];
   double* rows = reinterpret_cast<double*>(lds);  // two rows of kThreads
   const int tid = threadIdx.x;
@@ -73,12 +80,16 @@ __global__ void __launch_bounds__(256) adj_box_kernel(AdjBoxArgs a) {
   const int y1 = y0 + a.seg_rows < H ? y0 + a.seg_rows : H;
   const int64_t col = inx ? x : 0;
   const double* src = nullptr;
+  const float* srcf = nullptr;
   const float *pu = nullptr, *pv = nullptr;
   double cu = 0.0, cv = 0.0;
   bool single = false;  // a first moment: the second factor is 1
+  bool ones = false;    // the pixel count: every factor is 1
   if constexpr (PRODUCTS) {
     int u, v;
-    channel_factors(blockIdx.y, a.Q, a.C, &u, &v);
+    const int ch = (int)blockIdx.y - a.count_first;
+    ones = ch < 0;
+    channel_factors(ones ? 0 : ch, a.Q, a.C, &u, &v);
     single = v < 0;
     pu = input_plane(a, u);
     pv = single ? pu : input_plane(a, v);  // read either way, used only for products
@@ -86,20 +97,24 @@ __global__ void __launch_bounds__(256) adj_box_kernel(AdjBoxArgs a) {
     cv = pv[0];
     pu += col;
     pv += col;
-  } else {
+  } else if constexpr (SRC == BOX_MEAN32) {
+    srcf = a.srcf + (int64_t)blockIdx.y * a.plane + col;
+  } else {  // BOX_SUM64, BOX_MEAN64
     src = a.src + (int64_t)blockIdx.y * a.plane + col;
   }
   auto value = [&](int yy) -> double {
     if constexpr (PRODUCTS) {
       const double t = (double)pu[(int64_t)yy * W] - cu;
       const double w = (double)pv[(int64_t)yy * W] - cv;
-      return single ? t : t * w;
-    } else {
+      return ones ? 1.0 : (single ? t : t * w);
+    } else if constexpr (SRC == BOX_MEAN32) {
+      return (double)srcf[(int64_t)yy * W];
+    } else {  // BOX_SUM64, BOX_MEAN64
       return src[(int64_t)yy * W];
     }
   };
   auto clamp_row = [&](int yy) { return yy < 0 ? 0 : (yy >= H ? H - 1 : yy); };
-  double* dst = a.dst + (int64_t)blockIdx.y * a.plane;
+  double* dst = SRC == BOX_MEAN32 ? nullptr : a.dst + (int64_t)blockIdx.y * a.plane;  // FP64 out
   const bool owner = inx && tid >= r && tid < kThreads - r;
   // Loads are unconditional from clamped rows and masked afterwards, in
   // batches of kRowBatch rows, so that a batch's loads are in flight
@@ -143,7 +158,17 @@ __global__ void __launch_bounds__(256) adj_box_kernel(AdjBoxArgs a) {
       if (owner) {
         double s = 0.0;
         for (int d = -r; d <= r; ++d) s += buf[tid + d];
-        dst[(int64_t)y * W + x] = s;
+        if constexpr (SRC == BOX_MEAN32 || SRC == BOX_MEAN64) {
+          const int ny = (y + r < H - 1 ? y + r : H - 1) - (y - r > 0 ? y - r : 0) + 1;
+          const int nx = (x + r < W - 1 ? x + r : W - 1) - (x - r > 0 ? x - r : 0) + 1;
+          const double m = s / (double)(ny * nx);
+          if constexpr (SRC == BOX_MEAN32)
+            a.dstf[(int64_t)blockIdx.y * a.plane + (int64_t)y * W + x] = (float)m;
+          else
+            dst[(int64_t)y * W + x] = m;
+        } else {
+          dst[(int64_t)y * W + x] = s;
+        }
       }
     }
   }
@@ -189,11 +214,27 @@ static hipError_t box_launch(AdjBoxArgs a, int planes, hipStream_t s) {
   const int n_seg = (a.H + a.seg_rows - 1) / a.seg_rows;
   const dim3 grid(a.tiles_x * n_seg, planes);
   const size_t lds = 2 * kThreads * sizeof(double);
-  if (a.src)
-    hipLaunchKernelGGL(adj_box_kernel<false>, grid, dim3(kThreads), lds, s, a);
+  if (a.srcf)
+    hipLaunchKernelGGL(adj_box_kernel<BOX_MEAN32>, grid, dim3(kThreads), lds, s, a);
+  else if (a.src && a.count_first)  // count_first marks a mean of FP64 planes here
+    hipLaunchKernelGGL(adj_box_kernel<BOX_MEAN64>, grid, dim3(kThreads), lds, s, a);
+  else if (a.src)
+    hipLaunchKernelGGL(adj_box_kernel<BOX_SUM64>, grid, dim3(kThreads), lds, s, a);
   else
-    hipLaunchKernelGGL(adj_box_kernel<true>, grid, dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL(adj_box_kernel<BOX_PRODUCTS>, grid, dim3(kThreads), lds, s, a);
   return hipGetLastError();
+}
+
+hipError_t launch_mean_planes(const float* src, float* dst, int planes, int H, int W, int r,
+                              hipStream_t s) {
+  if (!src || !dst) return hipErrorInvalidValue;
+  AdjBoxArgs a = {};
+  a.srcf = src;
+  a.dstf = dst;
+  a.H = H;
+  a.W = W;
+  a.r = r;
+  return box_launch(a, planes, s);
 }
 
 hipError_t launch_box(const double* src, double* dst, int planes, int H, int W, int r,
@@ -209,7 +250,7 @@ hipError_t launch_box(const double* src, double* dst, int planes, int H, int W, 
 }
 
 hipError_t launch_box_products(const float* guides, const float* noisy, int Q, int C, int H,
-                               int W, int r, double* dst, hipStream_t s) {
+                               int W, int r, double* dst, hipStream_t s, bool with_count) {
   AdjBoxArgs a = {};
   a.guides = guides;
   a.noisy = noisy;
@@ -219,7 +260,21 @@ hipError_t launch_box_products(const float* guides, const float* noisy, int Q, i
   a.r = r;
   a.Q = Q;
   a.C = C;
-  return box_launch(a, num_sums(Q, C), s);
+  a.count_first = with_count ? 1 : 0;
+  return box_launch(a, num_sums(Q, C) + a.count_first, s);
+}
+
+hipError_t launch_mean_planes64(const double* src, double* dst, int planes, int H, int W, int r,
+                                hipStream_t s) {
+  if (!src || !dst) return hipErrorInvalidValue;
+  AdjBoxArgs a = {};
+  a.src = src;
+  a.dst = dst;
+  a.count_first = 1;
+  a.H = H;
+  a.W = W;
+  a.r = r;
+  return box_launch(a, planes, s);
 }
 
 hipError_t launch_pair_sum(const double* src, int n, double* dst, hipStream_t s) {

@@ -156,6 +156,99 @@ flr_status validate_lowres(const flr_params* p, int block, float sigma, int radi
   return FLR_OK;
 }
 
+// Workspace of a batch: the launch tables, then per frame its coefficient
+// image on the noisy grid, then per joint frame its averaged coefficients.
+struct BatchLayout {
+  // coef: a plain frame's coefficient image, or a joint frame's FP64 sums
+  size_t walk, apply, up, starts, coef[FLR_BATCH_MAX], models[FLR_BATCH_MAX],
+      mean[FLR_BATCH_MAX], total;
+};
+
+bool frame_is_joint(const flr_frame& f) { return f.guides_low != nullptr; }
+
+int frame_up(const flr_frame& f) {
+  return f.noisy_height > 0 ? f.height / f.noisy_height : 0;
+}
+
+BatchLayout batch_layout(const flr_params* p, const flr_frame* frames, int n) {
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  BatchLayout L{};
+  const size_t fc = (size_t)(p->num_guides + 1) * p->num_channels;
+  size_t o = 0;
+  L.walk = o;
+  o += al(n * sizeof(LaunchArgs));
+  L.apply = o;
+  o += al(n * sizeof(LaunchArgs));
+  L.up = o;
+  o += al(n * sizeof(LaunchArgs));
+  L.starts = o;
+  o += al(3 * (n + 1) * sizeof(int));
+  const size_t ns1 = 1 + (size_t)flr::num_sums(p->num_guides, p->num_channels);
+  for (int i = 0; i < n; ++i) {
+    const size_t px = (size_t)frames[i].noisy_height * frames[i].noisy_width;
+    L.coef[i] = o;
+    if (!frame_is_joint(frames[i])) {
+      o += al(fc * px * sizeof(float));
+    } else {  // sums, models, means
+      o += al(ns1 * px * sizeof(double));
+      L.models[i] = o;
+      o += al(fc * px * sizeof(double));
+      L.mean[i] = o;
+      o += al(fc * px * sizeof(double));
+    }
+  }
+  L.total = o;
+  return L;
+}
+
+flr_status validate_batch(const flr_params* p, const flr_frame* frames, int n) {
+  if (!p || !frames) return FLR_ERR_NULL;
+  if (n < 1 || n > FLR_BATCH_MAX) return FLR_ERR_SHAPE;
+  flr_params q = *p;
+  q.height = q.width = 1;
+  flr_status st = flr_validate_params(&q);
+  if (st != FLR_OK) return st;
+  if (!p->average_coeffs || p->flags) return FLR_ERR_MODE;
+  if (flr::split_walk(p->num_guides, p->num_channels) ||
+      flr::num_sums(p->num_guides, p->num_channels) > flr::resident_channels())
+    return FLR_ERR_CHANNELS;
+  const int Q = p->num_guides, C = p->num_channels;
+  for (int i = 0; i < n; ++i) {
+    const flr_frame& f = frames[i];
+    q.height = f.height;
+    q.width = f.width;
+    if ((st = flr_validate_params(&q)) != FLR_OK) return st;
+    if (f.noisy_height < 1 || f.noisy_width < 1 || f.tile_rows < 0) return FLR_ERR_SHAPE;
+    if (frame_is_joint(f)) {
+      const int up = frame_up(f);
+      if ((up != 2 && up != 4 && up != 8) || f.height != up * f.noisy_height ||
+          f.width != up * f.noisy_width)
+        return FLR_ERR_SHAPE;
+    } else if (f.noisy_height != f.height || f.noisy_width != f.width) {
+      return FLR_ERR_SHAPE;
+    }
+    if ((st = check_ptrs({f.guides, f.noisy, f.out})) != FLR_OK) return st;
+    if (frame_is_joint(f) && !aligned16(f.guides_low)) return FLR_ERR_ALIGN;
+  }
+  // outputs against every input and every other output
+  for (int i = 0; i < n; ++i) {
+    const size_t ob = (size_t)C * frames[i].height * frames[i].width * sizeof(float);
+    for (int j = 0; j < n; ++j) {
+      const flr_frame& g = frames[j];
+      const size_t gb = (size_t)Q * g.height * g.width * sizeof(float);
+      const size_t nb = (size_t)C * g.noisy_height * g.noisy_width * sizeof(float);
+      const size_t lb = (size_t)Q * g.noisy_height * g.noisy_width * sizeof(float);
+      if (overlaps(frames[i].out, ob, g.guides, gb) || overlaps(frames[i].out, ob, g.noisy, nb) ||
+          (g.guides_low && overlaps(frames[i].out, ob, g.guides_low, lb)))
+        return FLR_ERR_ALIAS;
+      if (j != i && overlaps(frames[i].out, ob, g.out,
+                             (size_t)C * g.height * g.width * sizeof(float)))
+        return FLR_ERR_ALIAS;
+    }
+  }
+  return FLR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -447,6 +540,178 @@ flr_status flr_denoise_lowres(const flr_params* p, int32_t block, float sigma_lo
   a.out = out;
   a.lr_rows = flr::lr_apply_rows(Q, C, block);
   return dispatch(Q, C, flr::K_LR_APPLY, a, stream);
+}
+
+size_t flr_batch_workspace_bytes(const flr_params* p, const flr_frame* frames,
+                                 int32_t num_frames) {
+  if (validate_batch(p, frames, num_frames) != FLR_OK) return 0;
+  return batch_layout(p, frames, num_frames).total;
+}
+
+flr_status flr_batch_plan(const flr_params* p, const flr_frame* frames, int32_t n,
+                          void* workspace, size_t workspace_bytes, flr_batch* out_plan) {
+  flr_status st = validate_batch(p, frames, n);
+  if (st != FLR_OK) return st;
+  if (!out_plan || !workspace) return FLR_ERR_NULL;
+  if (!aligned16(workspace)) return FLR_ERR_ALIGN;
+  const BatchLayout L = batch_layout(p, frames, n);
+  if (workspace_bytes < L.total) return FLR_ERR_WORKSPACE;
+  const int Q = p->num_guides, C = p->num_channels;
+  for (int i = 0; i < n; ++i) {
+    const flr_frame& f = frames[i];
+    const size_t gb = (size_t)Q * f.height * f.width * sizeof(float);
+    const size_t nb = (size_t)C * f.noisy_height * f.noisy_width * sizeof(float);
+    if (overlaps(workspace, L.total, f.guides, gb) || overlaps(workspace, L.total, f.noisy, nb) ||
+        overlaps(workspace, L.total, f.out, (size_t)C * f.height * f.width * sizeof(float)) ||
+        (f.guides_low &&
+         overlaps(workspace, L.total, f.guides_low,
+                  (size_t)Q * f.noisy_height * f.noisy_width * sizeof(float))))
+      return FLR_ERR_ALIAS;
+  }
+  char* ws = static_cast<char*>(workspace);
+  LaunchArgs walk[FLR_BATCH_MAX], apply[FLR_BATCH_MAX], up[FLR_BATCH_MAX];
+  int ws_walk[FLR_BATCH_MAX + 1], ws_apply[FLR_BATCH_MAX + 1], ws_up[FLR_BATCH_MAX + 1];
+  int order[FLR_BATCH_MAX], blocks[FLR_BATCH_MAX];
+  flr_params q = *p;
+  // the coefficient walk of every plain frame
+  int nw = 0;
+  for (int i = 0; i < n; ++i) {
+    const flr_frame& f = frames[i];
+    if (frame_is_joint(f)) continue;
+    q.height = f.height;
+    q.width = f.width;
+    q.tile_rows = f.tile_rows;
+    LaunchArgs a = base_args(&q);
+    a.guides = f.guides;
+    a.noisy = f.noisy;
+    a.out = reinterpret_cast<float*>(ws + L.coef[i]);
+    plan(&q, flr::K_COEFFS, &a);
+    walk[nw] = a;
+    blocks[nw] = a.tiles_x * a.n_seg;
+    order[nw] = nw;
+    ++nw;
+  }
+  // largest frames first, so that the small ones fill the tail of the launch
+  for (int i = 1; i < nw; ++i)
+    for (int j = i; j > 0 && blocks[order[j]] > blocks[order[j - 1]]; --j) {
+      const int t = order[j];
+      order[j] = order[j - 1];
+      order[j - 1] = t;
+    }
+  LaunchArgs walk_sorted[FLR_BATCH_MAX];
+  ws_walk[0] = 0;
+  for (int k = 0; k < nw; ++k) {
+    walk_sorted[k] = walk[order[k]];
+    ws_walk[k + 1] = ws_walk[k] + blocks[order[k]];
+  }
+  int np = 0, nj = 0;
+  ws_apply[0] = ws_up[0] = 0;
+  for (int i = 0; i < n; ++i) {
+    const flr_frame& f = frames[i];
+    q.height = f.height;
+    q.width = f.width;
+    q.tile_rows = f.tile_rows;  // as flr_denoise: the segment length of both kernels
+    LaunchArgs a = base_args(&q);
+    a.guides = f.guides;
+    a.out = f.out;
+    if (!frame_is_joint(f)) {
+      a.planes = reinterpret_cast<const float*>(ws + L.coef[i]);
+      plan(&q, flr::K_APPLY_AVG, &a);
+      apply[np] = a;
+      ws_apply[np + 1] = ws_apply[np] + a.tiles_x * a.n_seg;
+      ++np;
+    } else {
+      a.fin = reinterpret_cast<const double*>(ws + L.mean[i]);
+      a.guides_low = f.guides_low;
+      a.noisy = f.noisy;
+      a.Hl = f.noisy_height;
+      a.Wl = f.noisy_width;
+      a.up = frame_up(f);
+      up[nj] = a;
+      ws_up[nj + 1] = ws_up[nj] + (int)(((size_t)f.height * f.width + 255) / 256);
+      out_plan->joint_guides[nj] = f.guides_low;
+      out_plan->joint_noisy[nj] = f.noisy;
+      out_plan->joint_sums[nj] = reinterpret_cast<double*>(ws + L.coef[i]);
+      out_plan->joint_models[nj] = reinterpret_cast<double*>(ws + L.models[i]);
+      out_plan->joint_mean[nj] = reinterpret_cast<double*>(ws + L.mean[i]);
+      out_plan->joint_height[nj] = f.noisy_height;
+      out_plan->joint_width[nj] = f.noisy_width;
+      ++nj;
+    }
+  }
+  // tables: launch arguments, then the three workgroup offset arrays
+  int starts[3 * (FLR_BATCH_MAX + 1)];
+  for (int k = 0; k <= n; ++k) {
+    starts[k] = k <= nw ? ws_walk[k] : 0;
+    starts[(n + 1) + k] = k <= np ? ws_apply[k] : 0;
+    starts[2 * (n + 1) + k] = k <= nj ? ws_up[k] : 0;
+  }
+  if ((nw && hipMemcpy(ws + L.walk, walk_sorted, nw * sizeof(LaunchArgs),
+                       hipMemcpyHostToDevice) != hipSuccess) ||
+      (np && hipMemcpy(ws + L.apply, apply, np * sizeof(LaunchArgs), hipMemcpyHostToDevice) !=
+                 hipSuccess) ||
+      (nj && hipMemcpy(ws + L.up, up, nj * sizeof(LaunchArgs), hipMemcpyHostToDevice) !=
+                 hipSuccess) ||
+      hipMemcpy(ws + L.starts, starts, 3 * (n + 1) * sizeof(int), hipMemcpyHostToDevice) !=
+          hipSuccess)
+    return FLR_ERR_HIP;
+  out_plan->params = *p;
+  out_plan->num_frames = n;
+  out_plan->num_joint = nj;
+  out_plan->coeff_blocks = ws_walk[nw];
+  out_plan->apply_blocks = ws_apply[np];
+  out_plan->up_blocks = ws_up[nj];
+  out_plan->walk_table = ws + L.walk;
+  out_plan->apply_table = ws + L.apply;
+  out_plan->up_table = ws + L.up;
+  out_plan->walk_starts = reinterpret_cast<int*>(ws + L.starts);
+  return FLR_OK;
+}
+
+flr_status flr_batch_run(const flr_batch* b, void* stream) {
+  if (!b || !b->walk_table) return FLR_ERR_NULL;
+  const flr_params* p = &b->params;
+  const int Q = p->num_guides, C = p->num_channels, n = b->num_frames;
+  const int np = n - b->num_joint, nj = b->num_joint;
+  const int* starts = b->walk_starts;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  flr_status st;
+  LaunchArgs a = base_args(p);
+  if (np > 0) {
+    a.frames = static_cast<const LaunchArgs*>(b->walk_table);
+    a.wg_start = starts;
+    a.nframes = np;
+    a.batch_blocks = b->coeff_blocks;
+    if ((st = dispatch(Q, C, flr::K_COEFFS_BATCH, a, stream)) != FLR_OK) return st;
+    a.frames = static_cast<const LaunchArgs*>(b->apply_table);
+    a.wg_start = starts + (n + 1);
+    a.batch_blocks = b->apply_blocks;
+    if ((st = dispatch(Q, C, flr::K_APPLY_AVG_BATCH, a, stream)) != FLR_OK) return st;
+  }
+  if (nj > 0) {
+    for (int k = 0; k < nj; ++k) {
+      const int h = b->joint_height[k], w = b->joint_width[k];
+      if (flr::launch_box_products(b->joint_guides[k], b->joint_noisy[k], Q, C, h, w, p->radius,
+                                   b->joint_sums[k], s, true) != hipSuccess)
+        return FLR_ERR_HIP;
+      LaunchArgs j = base_args(p);
+      j.H = j.Hl = h;
+      j.W = j.Wl = w;
+      j.guides = b->joint_guides[k];
+      j.fin = b->joint_sums[k];
+      j.fout = b->joint_models[k];
+      if ((st = dispatch(Q, C, flr::K_LR_SOLVE, j, stream)) != FLR_OK) return st;
+      if (flr::launch_mean_planes64(b->joint_models[k], b->joint_mean[k], (Q + 1) * C, h, w,
+                                    p->radius, s) != hipSuccess)
+        return FLR_ERR_HIP;
+    }
+    a.frames = static_cast<const LaunchArgs*>(b->up_table);
+    a.wg_start = starts + 2 * (n + 1);
+    a.nframes = nj;
+    a.batch_blocks = b->up_blocks;
+    if ((st = dispatch(Q, C, flr::K_UP_APPLY_BATCH, a, stream)) != FLR_OK) return st;
+  }
+  return FLR_OK;
 }
 
 const char* flr_status_str(flr_status s) {

@@ -611,8 +611,20 @@ enum WalkMode : int { W_MOMENTS = 0, W_FUSED0 = 1, W_FUSED1 = 2, W_COEFFS = 3 };
 // POFF, PCNT: the slice of product channels this walker carries (all by
 // default); W_MOMENTS over a slice writes that slice's planes (and, for the
 // first slice, n and the means).
-template <int Q, int C, int MODE, bool WIDE, int POFF = 0, int PCNT = -1>
-__global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
+// The frame and local workgroup index of a batched launch (frames are few:
+// a scan of the workgroup offsets, uniform across the workgroup).
+__device__ __forceinline__ const LaunchArgs& batch_frame(const LaunchArgs& ain, int* bid) {
+  const int b = blockIdx.x;
+  int f = 0;
+  while (f + 1 < ain.nframes && ain.wg_start[f + 1] <= b) ++f;
+  *bid = b - ain.wg_start[f];
+  return ain.frames[f];
+}
+
+template <int Q, int C, int MODE, bool WIDE, int POFF = 0, int PCNT = -1, bool BATCH = false>
+__global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs ain) {
+  int bid = blockIdx.x;
+  const LaunchArgs a = BATCH ? batch_frame(ain, &bid) : ain;
   using D = Dims<Q, C>;
   using T = solve_t;
   constexpr int NPQ = D::NP + D::NQC;              // product channels
@@ -643,8 +655,8 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
   const int hc = MODE == W_FUSED1 ? r : 0;
   const int ncoef = kThreads - 2 * r;
   const int tout = ncoef - 2 * hc;
-  const int sx = blockIdx.x % a.tiles_x;
-  const int sy = blockIdx.x / a.tiles_x;
+  const int sx = bid % a.tiles_x;
+  const int sy = bid / a.tiles_x;
   const int X0 = sx * tout;
   const int Y0 = sy * a.seg_rows;
   const int Y1 = min(Y0 + a.seg_rows, H);
@@ -732,7 +744,7 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs a) {
     for (int f = 0; f < FC; ++f) VAL[f * kLdsStride + tid] = T(0);
   }
   ring_t* ring =
-      reinterpret_cast<ring_t*>(a.ring) + (size_t)blockIdx.x * (size_t)(2 * r + 1) * FC * kThreads + tid;
+      reinterpret_cast<ring_t*>(a.ring) + (size_t)bid * (size_t)(2 * r + 1) * FC * kThreads + tid;
 
   // inputs of the rows entering (ym + r) and leaving (ym - r - 1) the window
   float fa[Q + C], fs[Q + C];
@@ -1044,8 +1056,10 @@ __host__ __device__ constexpr int avg_variant(int r, int C) {
   return (r == 8 && C <= 3) ? AV_BLOCK8 : (wide_segments(r) ? AV_STREAM64 : AV_STREAM16);
 }
 
-template <int Q, int C, int AV>
-__global__ void __launch_bounds__(kThreads, 2) apply_avg_kernel(LaunchArgs a) {
+template <int Q, int C, int AV, bool BATCH = false>
+__global__ void __launch_bounds__(kThreads, 2) apply_avg_kernel(LaunchArgs ain) {
+  int bid = blockIdx.x;
+  const LaunchArgs a = BATCH ? batch_frame(ain, &bid) : ain;
   using T = solve_t;
   constexpr bool WIDE = AV == AV_STREAM64;
   constexpr int TH = kAvgTileRows;
@@ -1058,8 +1072,8 @@ __global__ void __launch_bounds__(kThreads, 2) apply_avg_kernel(LaunchArgs a) {
   const int W = a.W;
   const int64_t pl = (int64_t)H * W;
   const int tout = kThreads - 2 * r;
-  const int sx = blockIdx.x % a.tiles_x;
-  const int sy = blockIdx.x / a.tiles_x;
+  const int sx = bid % a.tiles_x;
+  const int sy = bid / a.tiles_x;
   const int X0 = sx * tout;
   const int Y0 = sy * a.seg_rows;
   const int th = min(a.seg_rows, H - Y0);
@@ -1261,6 +1275,7 @@ hipError_t launch_qc(int kind, const LaunchArgs& a, hipStream_t s) {
   const int wblocks = a.tiles_x * a.n_seg;
   const bool wide = wide_segments(a.r);
   const size_t lds = walk_lds_bytes(kind, Q, C);
+  auto lds_of = [](int k) { return walk_lds_bytes(k, Q, C); };
   switch (kind) {
     case K_MOMENTS:
       return wide ? launch_with_lds(walk_kernel<Q, C, W_MOMENTS, true>, wblocks, lds, a, s)
@@ -1323,6 +1338,31 @@ hipError_t launch_qc(int kind, const LaunchArgs& a, hipStream_t s) {
       hipLaunchKernelGGL((lr_solve_kernel<Q, C>), dim3(lb), dim3(256), 0, s, a);
       return hipGetLastError();
     }
+    case K_COEFFS_BATCH:
+      if constexpr (!split_walk(Q, C)) {
+        return wide ? launch_with_lds(walk_kernel<Q, C, W_COEFFS, true, 0, -1, true>,
+                                      a.batch_blocks, lds_of(K_COEFFS), a, s)
+                    : launch_with_lds(walk_kernel<Q, C, W_COEFFS, false, 0, -1, true>,
+                                      a.batch_blocks, lds_of(K_COEFFS), a, s);
+      }
+      return hipErrorInvalidValue;
+    case K_APPLY_AVG_BATCH:
+      switch (avg_variant(a.r, C)) {
+        case AV_BLOCK8:
+          if constexpr (C <= 3)
+            return launch_with_lds(apply_avg_kernel<Q, C, AV_BLOCK8, true>, a.batch_blocks,
+                                   lds_of(K_APPLY_AVG), a, s);
+          return hipErrorInvalidValue;
+        case AV_STREAM64:
+          return launch_with_lds(apply_avg_kernel<Q, C, AV_STREAM64, true>, a.batch_blocks,
+                                 lds_of(K_APPLY_AVG), a, s);
+        default:
+          return launch_with_lds(apply_avg_kernel<Q, C, AV_STREAM16, true>, a.batch_blocks,
+                                 lds_of(K_APPLY_AVG), a, s);
+      }
+    case K_UP_APPLY_BATCH:
+      hipLaunchKernelGGL((up_apply_kernel<Q, C, true>), dim3(a.batch_blocks), dim3(256), 0, s, a);
+      return hipGetLastError();
     case K_LR_APPLY:
       if (a.lr_rows > 0) {
         const size_t l = lr_apply_lds_bytes(Q, C, a.block, a.lr_rows);

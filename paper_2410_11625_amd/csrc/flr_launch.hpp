@@ -79,6 +79,10 @@ enum Kind : int {
   K_LR_BLOCK = 12,    // block sums of the anchored products -> low-resolution planes
   K_LR_SOLVE = 13,    // Gaussian pass along columns + solve per low-resolution pixel
   K_LR_APPLY = 14,    // bilinear model interpolation + reconstruction
+  // batched serving
+  K_COEFFS_BATCH = 15,     // K_COEFFS over the tiles of several frames
+  K_APPLY_AVG_BATCH = 16,  // K_APPLY_AVG over the tiles of several frames
+  K_UP_APPLY_BATCH = 17,   // bilinear upsampling of coefficient planes + reconstruction
 };
 
 // Longest Gaussian of the downsampled-moment variant (taps -R..R).
@@ -109,6 +113,15 @@ struct LaunchArgs {
   // downsampled-moment variant only
   int block, Hl, Wl, lr_R;
   int lr_rows;  // K_LR_APPLY: full-resolution rows per workgroup (0: one lane per pixel)
+  // batched launches (K_COEFFS_BATCH, K_APPLY_AVG_BATCH, K_UP_APPLY_BATCH):
+  // workgroup b belongs to the frame f with wg_start[f] <= b < wg_start[f + 1]
+  // and runs as workgroup b - wg_start[f] of frames[f]
+  const struct LaunchArgs* frames;
+  const int* wg_start;
+  int nframes;
+  int batch_blocks;  // total workgroups of the launch
+  int up;            // K_UP_APPLY: upsampling factor (coefficient grid = H / up)
+  const float* guides_low;  // K_UP_APPLY: the guides the models were fitted on (anchors)
   double taps[2 * kMaxLowresRadius + 1];
 };
 
@@ -144,11 +157,20 @@ __host__ __device__ constexpr int num_avg_fields(int Q, int C) { return C + 2 * 
 // column sums, then a row pass through LDS). src and dst must not overlap.
 hipError_t launch_box(const double* src, double* dst, int planes, int H, int W, int r,
                       hipStream_t s);
+// FP32 window means (clipped window, FP64 sums) of `planes` planes of H x W.
+hipError_t launch_mean_planes(const float* src, float* dst, int planes, int H, int W, int r,
+                              hipStream_t s);
+// The same for FP64 planes, FP64 means.
+hipError_t launch_mean_planes64(const double* src, double* dst, int planes, int H, int W, int r,
+                                hipStream_t s);
 // FP64 clipped window sums of the num_sums(Q, C) anchored products of the
 // inputs, in the moment order g_q | y_c | g_p g_q (p <= q) | g_q y_c, each
 // input plane shifted by its value at pixel (0, 0).
+// With with_count, plane 0 is the window pixel count and the channels follow
+// (the plane order of the downsampled-moment variant's solve).
 hipError_t launch_box_products(const float* guides, const float* noisy, int Q, int C, int H,
-                               int W, int r, double* dst, hipStream_t s);
+                               int W, int r, double* dst, hipStream_t s,
+                               bool with_count = false);
 // dst[0..1] = sums over n entries of the interleaved pairs src[2i], src[2i+1]
 // (fixed order; one workgroup).
 hipError_t launch_pair_sum(const double* src, int n, double* dst, hipStream_t s);

@@ -299,4 +299,47 @@ __global__ void __launch_bounds__(256) lr_apply_staged_kernel(LaunchArgs a) {
   }
 }
 
+// Joint denoising and upsampling (Sec. 3.2): anchored FP64 models (b~ | a,
+// as lr_solve_kernel writes them, window-averaged) on a grid a.Hl x a.Wl,
+// a.up times coarser than the output, bilinearly interpolated at each output
+// pixel (half-pixel centres, clamped) and applied to the full-resolution
+// guides with the anchors of the fit (pixel (0, 0) of the low-resolution
+// guides and of the noisy input). Batched over frames.
+template <int Q, int C, bool BATCH>
+__global__ void __launch_bounds__(256) up_apply_kernel(LaunchArgs ain) {
+  using T = double;
+  constexpr int FC = (Q + 1) * C;
+  int bid = blockIdx.x;
+  const LaunchArgs a = BATCH ? batch_frame(ain, &bid) : ain;
+  const int64_t pl = (int64_t)a.H * a.W;
+  const int64_t pll = (int64_t)a.Hl * a.Wl;
+  const int64_t idx = (int64_t)bid * blockDim.x + threadIdx.x;
+  if (idx >= pl) return;
+  const int i = (int)(idx / a.W), j = (int)(idx - (int64_t)i * a.W);
+  int r0, r1, c0, c1;
+  double tr, tc;
+  lr_axis(i, a.up, a.Hl, &r0, &r1, &tr);
+  lr_axis(j, a.up, a.Wl, &c0, &c1, &tc);
+  const int64_t o00 = (int64_t)r0 * a.Wl + c0, o01 = (int64_t)r0 * a.Wl + c1;
+  const int64_t o10 = (int64_t)r1 * a.Wl + c0, o11 = (int64_t)r1 * a.Wl + c1;
+  T m[FC];
+#pragma unroll
+  for (int k = 0; k < FC; ++k) {
+    const double* p = a.fin + k * pll;
+    const T top = p[o00] * (T(1) - tc) + p[o01] * tc;
+    const T bot = p[o10] * (T(1) - tc) + p[o11] * tc;
+    m[k] = top * (T(1) - tr) + bot * tr;
+  }
+  T g[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) g[q] = (T)a.guides[q * pl + idx] - (T)a.guides_low[q * pll];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    T s = m[c] + (T)a.noisy[c * pll];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) s = fma(m[C + q * C + c], g[q], s);
+    a.out[c * pl + idx] = (float)s;
+  }
+}
+
 }  // namespace flr

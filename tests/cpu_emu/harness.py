@@ -169,6 +169,39 @@ class Emu:
                                         need, None), "flr_denoise_lowres")
         return out.copy()
 
+    def batch(self, frames, p: FlrParams):
+        """flr_batch_plan + flr_batch_run over frames (dicts of guides, noisy,
+        optional guides_low) -> list of outputs."""
+        from paper_2410_11625_amd._lib import FlrBatch, FlrFrame
+        L = self.L
+        F = ctypes.POINTER(FlrFrame)
+        Bp = ctypes.POINTER(FlrBatch)
+        P = ctypes.POINTER(FlrParams)
+        L.flr_batch_workspace_bytes.argtypes = [P, F, ctypes.c_int32]
+        L.flr_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.flr_batch_plan.argtypes = [P, F, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t, Bp]
+        L.flr_batch_run.argtypes = [Bp, ctypes.c_void_p]
+        arr = (FlrFrame * len(frames))()
+        outs = []
+        for i, f in enumerate(frames):
+            gp, _ = self.buf(f["guides"])
+            yp, _ = self.buf(f["noisy"])
+            lp = self.buf(f["guides_low"])[0] if f.get("guides_low") is not None else None
+            C = f["noisy"].shape[0]
+            H, W = f["guides"].shape[1:]
+            op, out = self.buf(shape=(C, H, W))
+            outs.append(out)
+            arr[i] = FlrFrame(height=H, width=W, noisy_height=f["noisy"].shape[1],
+                              noisy_width=f["noisy"].shape[2], tile_rows=f.get("tile_rows", 0),
+                              guides=gp, guides_low=lp, noisy=yp, out=op)
+        need = int(L.flr_batch_workspace_bytes(ctypes.byref(p), arr, len(frames)))
+        wp, _ = self.buf(shape=(need // 4,))
+        plan = FlrBatch()
+        self.check(L.flr_batch_plan(ctypes.byref(p), arr, len(frames), wp, need,
+                                    ctypes.byref(plan)), "flr_batch_plan")
+        self.check(L.flr_batch_run(ctypes.byref(plan), None), "flr_batch_run")
+        return [o.copy() for o in outs]
+
     def moments(self, noisy, guides, p: FlrParams):
         Q, H, W = guides.shape
         C = noisy.shape[0]
@@ -239,6 +272,40 @@ def run_case(spec: dict) -> dict:
             d = np.abs(got - want)
             return {"maxabs": float(d.max()), "median": float(np.median(d)),
                     "within": float(np.mean(d <= 2e-3)), "shape": list(got.shape)}
+        if kind == "batch":
+            from oracle import flr_lowres
+            # plain frames of uneven sizes and one joint frame (noisy input and
+            # low-resolution guides at 1/up of the output grid)
+            sizes = spec["sizes"]
+            up = spec.get("up", 2)
+            frames, refs = [], []
+            for k, (h, w) in enumerate(sizes):
+                fr = make_config(1, seed=10 + k, h=h, w=w)
+                frames.append(dict(guides=fr["guides"], noisy=fr["noisy"],
+                                   tile_rows=spec.get("tile_rows", 0)))
+            jh, jw = spec["joint"]
+            hi = make_config(1, seed=40, h=jh, w=jw)
+            lo = make_config(1, seed=40, h=jh // up, w=jw // up)
+            frames.append(dict(guides=hi["guides"], guides_low=lo["guides"], noisy=lo["noisy"]))
+            p = params(1, 1, 8, 3, r, 1e-3, 0, 0.0, 1, 2)
+            got = emu.batch(frames, p)
+            res = {}
+            # plain frames: the same kernels and plans as flr_denoise (two-pass)
+            for k, f in enumerate(frames[:-1]):
+                h, w = f["guides"].shape[1:]
+                one = emu.denoise(f["noisy"], f["guides"],
+                                  params(h, w, 8, 3, r, 1e-3, 0, 0.0, 1, 2,
+                                         tile_rows=spec.get("tile_rows", 0)))
+                res[f"plain{k}_equal"] = bool(np.array_equal(got[k], one))
+            # joint frame: low-resolution fit, window-averaged, bilinearly upsampled
+            _, A = ref.flr_reference(lo["noisy"].astype(np.float32),
+                                     lo["guides"].astype(np.float32), r,
+                                     float(np.float32(1e-3)), return_coeffs=True)
+            Abar = ref.average_coefficients(A, r)
+            want = ref.apply_model(flr_lowres.bilinear_upsample(Abar, jh, jw, up),
+                                   hi["guides"].astype(np.float32))
+            res["joint_rel"] = _rel_err(got[-1], want)
+            return res
         if kind == "lowres":
             from oracle import flr_lowres
             if spec.get("frame") == "config":

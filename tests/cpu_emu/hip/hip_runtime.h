@@ -102,6 +102,11 @@ typedef void* hipStream_t;
 enum hipFuncAttribute { hipFuncAttributeMaxDynamicSharedMemorySize = 0 };
 inline hipError_t hipFuncSetAttribute(const void*, hipFuncAttribute, int) { return hipSuccess; }
 hipError_t hipGetLastError();
+enum hipMemcpyKind { hipMemcpyHostToDevice = 1 };
+inline hipError_t hipMemcpy(void* dst, const void* src, size_t n, hipMemcpyKind) {
+  std::memcpy(dst, src, n);
+  return hipSuccess;
+}
 
 // Runs a kernel over the grid on host threads (defined by the emulator):
 // `tramp(kernel, arg)` executes one lane.

@@ -206,3 +206,63 @@ def test_lowres_validates_before_launch(L):
     assert lw(pp, 8, 1.25, 4, g, y, g, ws, need, None) == 6
     assert lw(pp, 8, 1.25, 4, g, y, o, y, need, None) == 6
     assert lw(ctypes.byref(_params(flags=1)), 8, 1.25, 4, g, y, o, ws, need, None) == 9
+
+
+def test_batch_structs_match_the_header(tmp_path):
+    """sizeof and field offsets of flr_frame and flr_batch, compiled from the
+    header with the host C compiler, against the ctypes mirrors."""
+    import shutil
+    import subprocess
+    from paper_2410_11625_amd._lib import FlrBatch, FlrFrame
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = {"flr_frame": [f[0] for f in FlrFrame._fields_],
+              "flr_batch": [f[0] for f in FlrBatch._fields_]}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "flr.h"', "int main(void) {"]
+    for t, names in fields.items():
+        lines.append(f'printf("{t} %zu\\n", sizeof({t}));')
+        for n in names:
+            lines.append(f'printf("{t}.{n} %zu\\n", offsetof({t}, {n}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, f"-I{os.path.join(ROOT, 'include')}", str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                 check=True).stdout.splitlines())
+    for cls, t in ((FlrFrame, "flr_frame"), (FlrBatch, "flr_batch")):
+        assert int(got[t]) == ctypes.sizeof(cls)
+        for n, _ in cls._fields_:
+            assert int(got[f"{t}.{n}"]) == getattr(cls, n).offset, (t, n)
+
+
+def test_batch_validates_before_launch(L):
+    from paper_2410_11625_amd._lib import FlrBatch, FlrFrame
+    p = _params(num_guides=8, num_channels=3, fused=2)
+    fr = (FlrFrame * 2)()
+    fr[0] = FlrFrame(height=64, width=80, noisy_height=64, noisy_width=80, tile_rows=0,
+                     guides=0x10000000, guides_low=None, noisy=0x20000000, out=0x30000000)
+    fr[1] = FlrFrame(height=64, width=80, noisy_height=32, noisy_width=40, tile_rows=0,
+                     guides=0x40000000, guides_low=0x50000000, noisy=0x60000000,
+                     out=0x70000000)
+    need = L.flr_batch_workspace_bytes(ctypes.byref(p), fr, 2)
+    assert need > 0
+    plan = FlrBatch()
+    ws = 0x80000000
+    bp = L.flr_batch_plan
+    assert bp(ctypes.byref(p), fr, 0, ws, need, ctypes.byref(plan)) == 2
+    assert bp(ctypes.byref(p), fr, 2, ws, need - 256, ctypes.byref(plan)) == 8
+    assert bp(ctypes.byref(_params(num_guides=8, num_channels=3, average_coeffs=0)), fr, 2, ws,
+              need, ctypes.byref(plan)) == 9
+    # Q = 8, C = 4 needs a split walk: not batched
+    assert L.flr_batch_workspace_bytes(ctypes.byref(_params(num_guides=8, num_channels=4)),
+                                       fr, 2) == 0
+    # a joint frame whose grids are not an integer factor apart
+    fr[1].noisy_height = 30
+    assert bp(ctypes.byref(p), fr, 2, ws, need, ctypes.byref(plan)) == 2
+    fr[1].noisy_height = 32
+    # an output on top of another frame's input
+    fr[0].out = 0x60000000
+    assert bp(ctypes.byref(p), fr, 2, ws, need, ctypes.byref(plan)) == 6

@@ -118,3 +118,22 @@ def test_emulated_adjoint_radius_zero():
 def test_emulated_lowres_matches_oracle(spec):
     res = run_in_subprocess(spec)
     assert res["rel"] <= 1e-6, res
+
+
+# Batched serving: plain frames of uneven size in one launch per stage must
+# equal flr_denoise (two-pass) frame by frame, bit for bit (same kernels,
+# same tiles); a joint frame (noisy input and guides on a grid `up` times
+# coarser) against the oracle's low-resolution fit, window-averaged and
+# bilinearly upsampled, with the FP32 eps the ABI carries.
+@pytest.mark.parametrize("spec", [
+    dict(kind="batch", H=0, W=0, Q=8, C=3, r=8, sizes=[[40, 300], [25, 70], [1, 260]],
+         joint=[48, 520]),
+    dict(kind="batch", H=0, W=0, Q=8, C=3, r=8, sizes=[[33, 270]], joint=[64, 600], up=4,
+         tile_rows=7),
+], ids=["three-plain-one-joint", "tile7-joint-up4"])
+def test_emulated_batch(spec):
+    res = run_in_subprocess(spec)
+    for k, v in res.items():
+        if k.endswith("_equal"):
+            assert v, (k, res)
+    assert res["joint_rel"] <= 1e-6, res
