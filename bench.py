@@ -20,7 +20,6 @@ plain device copy of known size, the reference for the HBM byte counters.
 from __future__ import annotations
 
 import argparse
-import glob
 import hashlib
 import json
 import os
@@ -65,10 +64,12 @@ def algo_flops_per_px(Q: int, C: int, part: str = "all") -> int:
 
 
 def kernel_source_digest() -> str:
+    """Digest of the sources that define the two-pass kernels and their
+    launch (the counters are void once any of them changes)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2410_11625_amd", "csrc")
-    for f in sorted(glob.glob(os.path.join(csrc, "*.hpp")) + [os.path.join(csrc, "flr_q08.hip")]):
-        h.update(open(f, "rb").read())
+    for f in ("flr_device.hpp", "flr_launch.hpp", "flr_q08.hip"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
