@@ -164,6 +164,20 @@ __device__ __forceinline__ void epilogue(const ConvArgs& a, int y, int px, bool 
   }
 }
 
+// DPP lane move of an 8-byte fragment within 16-lane rows (two 32-bit moves).
+constexpr int kDppRowShl1 = 0x101, kDppRowShr1 = 0x111, kDppRowRor1 = 0x121,
+              kDppRowRor15 = 0x12F;
+template <int CTRL>
+__device__ __forceinline__ bf16x4_t dpp_frag(bf16x4_t v) {
+  int w[2];
+  __builtin_memcpy(w, &v, sizeof w);
+  w[0] = __builtin_amdgcn_update_dpp(0, w[0], CTRL, 0xf, 0xf, true);
+  w[1] = __builtin_amdgcn_update_dpp(0, w[1], CTRL, 0xf, 0xf, true);
+  bf16x4_t r;
+  __builtin_memcpy(&r, w, sizeof w);
+  return r;
+}
+
 // Four tiles of 16 output pixels per wave: the input fragments of the four
 // tiles for one kernel row are in flight together and each weight fragment
 // is reused across them.
@@ -199,14 +213,83 @@ __global__ void __launch_bounds__(256) conv_kernel(ConvArgs a) {
     const int yc = min(max(yi, 0), a.Hi - 1);
     // this kernel row's input fragments of every tile, then their products
     bf16x4_t bv[TPW][KS][NCB];
+    if constexpr (ST == 1 && KS == 3) {
+      // Only the centre column (kx = 1) of each tile and one pixel beyond
+      // each end of the four tiles are loaded. In the B layout a 16-lane DPP
+      // row holds 16 consecutive pixels of one channel group, so kx = 0 is
+      // the centre shifted right by one lane (row_shr) with lane 0 taking
+      // lane 15 of the tile before (row_ror:1), and kx = 2 the centre shifted
+      // left (row_shl) with lane 15 taking lane 0 of the next tile
+      // (row_ror:15). Out-of-image pixels are zero in the centre and halo
+      // loads, hence in every shifted copy.
+      bf16x4_t hl[NCB], hr[NCB];
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) {
+      for (int t = 0; t < TPW; ++t) {
+        const int xc = min(max(px[t], 0), a.Wi - 1);
+        load_blocks<CIN, CUP, IN, NCB>(a, yc, xc, 4 * kq, pin[t] && oky, bv[t][1]);
+      }
+      {
+        const int xl = px[0] - 1, xr = px[TPW - 1] + 1;
+        load_blocks<CIN, CUP, IN, NCB>(a, yc, min(max(xl, 0), a.Wi - 1), 4 * kq,
+                                       oky && xl >= 0 && xl < a.Wi, hl);
+        load_blocks<CIN, CUP, IN, NCB>(a, yc, min(max(xr, 0), a.Wi - 1), 4 * kq,
+                                       oky && xr >= 0 && xr < a.Wi, hr);
+      }
+      const bool first = (lane & 15) == 0, last = (lane & 15) == 15;
 #pragma unroll
-      for (int kx = 0; kx < KS; ++kx) {
-        const int xi = px[t] * ST + kx - P;
-        const bool ok = pin[t] && oky && xi >= 0 && xi < a.Wi;
-        const int xc = min(max(xi, 0), a.Wi - 1);
-        load_blocks<CIN, CUP, IN, NCB>(a, yc, xc, 4 * kq, ok, bv[t][kx]);
+      for (int t = 0; t < TPW; ++t) {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          const bf16x4_t left = t == 0 ? hl[cb] : dpp_frag<kDppRowRor1>(bv[t - 1][1][cb]);
+          const bf16x4_t shr = dpp_frag<kDppRowShr1>(bv[t][1][cb]);
+          bv[t][0][cb] = first ? left : shr;
+          const bf16x4_t right = t == TPW - 1 ? hr[cb] : dpp_frag<kDppRowRor15>(bv[t + 1][1][cb]);
+          const bf16x4_t shl = dpp_frag<kDppRowShl1>(bv[t][1][cb]);
+          bv[t][2][cb] = last ? right : shl;
+        }
+      }
+    } else if constexpr (ST == 2 && KS == 3 && CIN <= 32) {
+      // Stride 2: kx = 1 and kx = 2 read input pixels 2p and 2p + 1; kx = 0
+      // reads 2p - 1, the kx = 2 pixel of the lane before (row_shr), lane 0
+      // taking lane 15 of the tile before (row_ror:1) or, for the first
+      // tile, one loaded halo pixel. (Measured: faster at 32 input channels,
+      // slower at 64, where the three loads per tile are kept.)
+      bf16x4_t hl[NCB];
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+#pragma unroll
+        for (int kx = 1; kx < 3; ++kx) {
+          const int xi = px[t] * 2 + kx - 1;
+          const int xc = min(max(xi, 0), a.Wi - 1);
+          load_blocks<CIN, CUP, IN, NCB>(a, yc, xc, 4 * kq, pin[t] && oky && xi < a.Wi,
+                                         bv[t][kx]);
+        }
+      }
+      {
+        const int xl = px[0] * 2 - 1;
+        load_blocks<CIN, CUP, IN, NCB>(a, yc, min(max(xl, 0), a.Wi - 1), 4 * kq,
+                                       oky && xl >= 0 && xl < a.Wi, hl);
+      }
+      const bool first = (lane & 15) == 0;
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          const bf16x4_t left = t == 0 ? hl[cb] : dpp_frag<kDppRowRor1>(bv[t - 1][2][cb]);
+          const bf16x4_t shr = dpp_frag<kDppRowShr1>(bv[t][2][cb]);
+          bv[t][0][cb] = first ? left : shr;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+#pragma unroll
+        for (int kx = 0; kx < KS; ++kx) {
+          const int xi = px[t] * ST + kx - P;
+          const bool ok = pin[t] && oky && xi >= 0 && xi < a.Wi;
+          const int xc = min(max(xi, 0), a.Wi - 1);
+          load_blocks<CIN, CUP, IN, NCB>(a, yc, xc, 4 * kq, ok, bv[t][kx]);
+        }
       }
     }
 #pragma unroll

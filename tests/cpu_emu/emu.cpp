@@ -181,6 +181,12 @@ int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask, int ba
     s = row * 16 + (15 - rl);
   } else if (ctrl == 0x141) {  // row_half_mirror
     s = row * 16 + (rl & 8) + (7 - (rl & 7));
+  } else if (ctrl > 0x100 && ctrl <= 0x10f) {  // row_shl:k
+    const int k = ctrl - 0x100;
+    s = rl + k <= 15 ? (int)l + k : -1;
+  } else if (ctrl > 0x120 && ctrl <= 0x12f) {  // row_ror:k
+    const int k = ctrl - 0x120;
+    s = row * 16 + ((rl - k + 16) & 15);
   } else if (ctrl > 0x110 && ctrl <= 0x11f) {
     const int k = ctrl - 0x110;
     s = rl >= k ? (int)l - k : -1;

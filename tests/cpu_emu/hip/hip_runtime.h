@@ -89,7 +89,8 @@ emu_f32x4 __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(emu_bf16x4 a, emu_bf16x4 b, 
                                                     int, int);
 
 // DPP lane move of a 64-lane wavefront (quad_perm, row_mirror,
-// row_half_mirror, row_shr:1..15, wave_shr:1, row_bcast:15, row_bcast:31);
+// row_half_mirror, row_shl:1..15, row_shr:1..15, row_ror:1..15, wave_shr:1,
+// row_bcast:15, row_bcast:31);
 // every lane of the wavefront must call it at the same point.
 int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask,
                                 bool bound_ctrl);
