@@ -21,6 +21,11 @@
 #include "flr.h"
 #include "flr_net.h"
 
+// The workgroup's dynamic LDS (one array shared by every kernel of the library).
+namespace flr {
+extern __shared__ float lds[];
+}
+
 namespace flrnet {
 
 typedef short bf16x4_t __attribute__((vector_size(8)));
@@ -322,6 +327,115 @@ __global__ void __launch_bounds__(256) conv_kernel(ConvArgs a) {
   for (int t = 0; t < TPW; ++t) epilogue<COUT, FUSE, COUT2>(a, y, px[t], pin[t], kq, lane, sum[t]);
 }
 
+// Stride-1 3x3 layers, input tile in LDS. A workgroup computes kTileRows
+// output rows (one per wave) of kTilePx pixels (four tiles of 16) for all
+// output channels. It first stages the (kTileRows + 2) x (kTilePx + 2) input
+// pixels of the tile with all their channels in LDS (HWC, 8-byte chunks,
+// zero outside the image; the decoder's upsampling and concatenation happen
+// here), so each input row is fetched by 1.5 output rows instead of 3, and
+// the MFMA B fragments are then read from LDS. The MFMA sequence is that of
+// conv_kernel, so the two give identical results.
+constexpr int kTileRows = 4, kTilePx = 64;
+constexpr int kStRows = kTileRows + 2, kStPx = kTilePx + 2;
+__host__ __device__ constexpr size_t conv_tile_lds_bytes(int cin) {
+  return (size_t)kStRows * kStPx * cin * sizeof(uint16_t);
+}
+
+template <int CIN, int COUT, int IN, int CUP, int FUSE, int COUT2>
+__global__ void __launch_bounds__(256) conv_tile_kernel(ConvArgs a) {
+  constexpr int NCB = CIN / 16, NB = COUT / 16, TPW = 4, KS = 3;
+  constexpr int CQ = CIN / 4;                   // 8-byte chunks per pixel
+  constexpr int NCH = kStRows * kStPx * CQ;     // chunks to stage
+  bf16x4_t* st = reinterpret_cast<bf16x4_t*>(flr::lds);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, kq = lane >> 4;
+  const int x0 = blockIdx.x * kTilePx, y0 = blockIdx.y * kTileRows;
+  for (int b0 = 0; b0 < NCH; b0 += 8 * 256) {
+    bf16x4_t v[8];
+    bool ok[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = b0 + u * 256 + tid;
+      const int ic = i < NCH ? i : NCH - 1;
+      const int pix = ic / CQ, c = 4 * (ic - pix * CQ);
+      const int sr = pix / kStPx, sx = pix - sr * kStPx;
+      const int yi = y0 - 1 + sr, xi = x0 - 1 + sx;
+      ok[u] = i < NCH && yi >= 0 && yi < a.Hi && xi >= 0 && xi < a.Wi;
+      const int yc = min(max(yi, 0), a.Hi - 1), xc = min(max(xi, 0), a.Wi - 1);
+      const uint16_t* src;
+      if constexpr (IN == IN_UPCAT) {
+        // one load from a selected address: the upsampled coarse half or the skip
+        // (both addresses in range: the unused one's channel is clamped)
+        const int cl = c < CUP ? c : CUP - 4, ch = c < CUP ? 0 : c - CUP;
+        const uint16_t* lo = a.in0 + ((size_t)(yc >> 1) * a.Wl + (xc >> 1)) * CUP + cl;
+        const uint16_t* hi = a.in1 + ((size_t)yc * a.Wi + xc) * (CIN - CUP) + ch;
+        src = c < CUP ? lo : hi;
+      } else {
+        src = a.in0 + ((size_t)yc * a.Wi + xc) * CIN + c;
+      }
+      v[u] = *reinterpret_cast<const bf16x4_t*>(src);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = b0 + u * 256 + tid;
+      if (i < NCH) st[i] = ok[u] ? v[u] : pack4(0, 0, 0, 0);
+    }
+  }
+  __syncthreads();
+  const int y = y0 + wv;
+  if (y >= a.Ho) return;  // uniform across the wave; no barrier follows
+  int px[TPW];
+  bool pin[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    px[t] = x0 + t * 16 + (lane & 15);
+    pin[t] = px[t] < a.Wo;
+  }
+  constexpr int KSPL = (TPW * NB >= 8) ? 1 : 8 / (TPW * NB);
+  f32x4_t acc[TPW][NB][KSPL];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int k = 0; k < KSPL; ++k) acc[t][nb][k] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ky = 0; ky < KS; ++ky) {
+#pragma unroll
+    for (int kx = 0; kx < KS; ++kx) {
+      bf16x4_t bv[TPW][NCB];
+#pragma unroll
+      for (int t = 0; t < TPW; ++t)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+          bv[t][cb] = st[((wv + ky) * kStPx + t * 16 + (lane & 15) + kx) * CQ + cb * 4 + kq];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const int tap = ky * KS + kx;
+        const int ks = (tap * NCB + cb) % KSPL;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const bf16x4_t av = a.w[((tap * NCB + cb) * NB + nb) * 64 + lane];
+#pragma unroll
+          for (int t = 0; t < TPW; ++t)
+            acc[t][nb][ks] =
+                __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv[t][cb], acc[t][nb][ks], 0, 0, 0);
+        }
+      }
+    }
+  }
+  f32x4_t sum[TPW][NB];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      sum[t][nb] = acc[t][nb][0];
+#pragma unroll
+      for (int k = 1; k < KSPL; ++k) sum[t][nb] += acc[t][nb][k];
+    }
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) epilogue<COUT, FUSE, COUT2>(a, y, px[t], pin[t], kq, lane, sum[t]);
+}
+
 // Packing: FP32 weight [cout][cin][k][k] -> fragments (tap, cin block,
 // cout block, lane) of 4 BF16, lane l holding output channel 16*nb + l%16
 // and input channels 16*cb + 4*(l/16) .. +3; zero in the padding.
@@ -439,6 +553,18 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 
 template <int CIN, int COUT, int KS, int ST, int IN, int CUP, int FUSE, int COUT2>
 hipError_t launch(const ConvArgs& a, hipStream_t s) {
+  // (measured: the LDS tile is faster up to 48 input channels; at 96 its
+  // 76 KB tile allows two workgroups per CU and the direct kernel wins)
+  if constexpr (KS == 3 && ST == 1 && CIN <= 48) {
+    auto k = conv_tile_kernel<CIN, COUT, IN, CUP, FUSE, COUT2>;
+    const size_t lds = conv_tile_lds_bytes(CIN);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3((a.Wo + kTilePx - 1) / kTilePx, (a.Ho + kTileRows - 1) / kTileRows),
+                       dim3(256), lds, s, a);
+    return hipGetLastError();
+  }
   constexpr int px_per_block = 4 * tiles_per_wave(CIN) * 16;
   hipLaunchKernelGGL((conv_kernel<CIN, COUT, KS, ST, IN, CUP, FUSE, COUT2>),
                      dim3((a.Wo + px_per_block - 1) / px_per_block, a.Ho), dim3(256), 0, s, a);
