@@ -118,3 +118,27 @@ def test_flnr_equals_network_then_regression(packed):
     ref = flr.denoise(y, g12, radius=8, eps=1e-3, fused="two_pass")
     assert torch.equal(out, ref)
     assert torch.isfinite(out).all()
+
+
+def test_flnr_regression_1080p_sampled():
+    """The 12-guide regression FLNR runs (flr_denoise two-pass: split moment
+    walks, solve, averaging) at 1080p, in the launch configuration the
+    benchmark times, on sampled blocks against the FLR oracle. The four
+    extra guides are seeded smooth fields in (0, 1) standing in for the
+    network's sigmoid outputs (the regression's parity does not depend on
+    where its guides come from)."""
+    fr = make_config(1)
+    H, W = 1080, 1920
+    rng = np.random.default_rng(12)
+    yy, xx = np.mgrid[0:H, 0:W] / np.array([H, W])[:, None, None]
+    extra = np.stack([1 / (1 + np.exp(-(np.sin(6.3 * (a * xx + b * yy) + c) * 2.0)))
+                      for a, b, c in rng.uniform(0.5, 3.0, size=(4, 3))]).astype(np.float32)
+    g12 = np.concatenate([fr["guides"], extra]).astype(np.float32)
+    got = flr.denoise(_t(fr["noisy"]), _t(g12), radius=8, eps=1e-3,
+                      fused="two_pass").cpu().numpy()
+    for (y0, y1, x0, x1) in [(0, 16, 0, 32), (530, 546, 950, 982), (H - 16, H, W - 32, W)]:
+        want = flr_ref.flr_reference_block(fr["noisy"].astype(np.float64),
+                                           g12.astype(np.float64), 8, 1e-3, y0, y1, x0, x1)
+        rms = np.sqrt(np.mean(want ** 2))
+        rel = np.abs(got[:, y0:y1, x0:x1] - want) / np.maximum(np.abs(want), 1e-3 * rms)
+        assert rel.max() <= 1e-4, (y0, x0, rel.max())
