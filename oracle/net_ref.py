@@ -96,15 +96,20 @@ def upsample2(x: np.ndarray, H: int, W: int) -> np.ndarray:
 
 
 def net_forward(guides: np.ndarray, noisy: np.ndarray, weights: dict,
-                logits: bool = False, compress: bool = True) -> np.ndarray:
+                logits: bool = False, compress: bool = True, bf16: bool = True,
+                cache: dict | None = None) -> np.ndarray:
     """The 4 extra guide planes [4][H][W] for guides [8][H][W] and noisy
     [3][H][W] (float64 out). ``logits`` returns the out1 pre-activation;
-    ``compress=False`` skips the input compression (for tests of the layers)."""
-    wq = {n: (bf16_round(w), bf16_round(b)) for n, (w, b) in weights.items()}
+    ``compress=False`` skips the input compression (for tests of the layers);
+    ``bf16=False`` drops every BF16 rounding (an FP64 network, for finite-
+    difference checks of gradients); ``cache``, a dict, receives each
+    layer's input and pre-activation under its name (for the backward)."""
+    rnd = bf16_round if bf16 else (lambda v: np.asarray(v, dtype=np.float64))
+    wq = {n: (rnd(w), rnd(b)) for n, (w, b) in weights.items()}
     x = np.concatenate([guides, noisy]).astype(np.float64)
     if compress:
         x = np.sign(x) * np.log1p(np.abs(x))
-    x = bf16_round(x)
+    x = rnd(x)
     assert x.shape[0] == 11
     H, W = x.shape[1:]
 
@@ -114,8 +119,10 @@ def net_forward(guides: np.ndarray, noisy: np.ndarray, weights: dict,
         w, b = wq[name]
         assert w.shape == (cout, cin, k, k) and inp.shape[0] == cin, name
         z = conv2d(inp, w, b, stride)
+        if cache is not None:
+            cache[name] = (inp, z, w)
         if act == "relu":
-            return bf16_round(np.maximum(z, 0.0))
+            return rnd(np.maximum(z, 0.0))
         return z
 
     a = layer("in3", x)
