@@ -78,6 +78,36 @@ flr_status flr_net_forward(int32_t height, int32_t width, const float* guides,
                            const float* noisy, const void* packed, float* out,
                            void* workspace, size_t workspace_bytes, void* stream);
 
+/* Workspace bytes of flr_net_backward for a height x width frame: the
+ * forward's activations plus FP32 gradient tensors (about 1.3 KB per pixel).
+ * 0 for invalid sizes. */
+size_t flr_net_backward_workspace_bytes(int32_t height, int32_t width);
+
+/* Gradient of a loss with respect to every network parameter, given the
+ * loss's gradient grad_out [4][H][W] (planar FP32) with respect to the four
+ * sigmoid outputs of flr_net_forward on the same guides and noisy input
+ * (Sec. 3.3: the network is trained by backpropagating the denoising loss
+ * through the regression into it; the regression's part is
+ * flr_denoise_backward, whose guide gradient planes 8..11 are grad_out).
+ *
+ * The call reruns the forward (it keeps no state between calls), then
+ * reverses the layers. BF16 rounding in the forward is treated as the
+ * identity (straight-through): the result is the gradient of the exact
+ * network at the BF16 weights and activations, accumulated in FP32.
+ *
+ * params: the FP32 parameters packed has been made from (flr_net_pack), in
+ * the layout of flr_net_num_params(). grad_params [flr_net_num_params()]
+ * receives the gradients in the same layout, overwritten when accumulate is
+ * 0 and added to when 1 (to sum a batch frame by frame); the weight
+ * gradients are sums over all pixels, added in a fixed order (repeatable
+ * bit for bit). Errors as flr_net_forward, FLR_ERR_MODE for accumulate not
+ * 0 or 1, FLR_ERR_ALIAS when grad_params or the workspace overlaps an input
+ * or each other. */
+flr_status flr_net_backward(int32_t height, int32_t width, const float* guides,
+                            const float* noisy, const float* params, const void* packed,
+                            const float* grad_out, float* grad_params, int32_t accumulate,
+                            void* workspace, size_t workspace_bytes, void* stream);
+
 /* Workspace bytes of flr_flnr_denoise for params p (p->num_guides must be
  * FLR_NET_IN_GUIDES + FLR_NET_OUT = 12 and p->num_channels 3). */
 size_t flr_flnr_workspace_bytes(const flr_params* p);

@@ -8,11 +8,11 @@ hand-written HIP kernels behind the C ABI in ``include/flr.h`` and
 """
 from .api import (PATHS, Batch, FLRError, apply, backward_workspace_bytes, coefficients, denoise,
                   denoise_backward, denoise_lowres, flnr_denoise, flnr_workspace_bytes, flr,
-                  lowres_workspace_bytes, make_params, moments, net_forward, net_num_params,
-                  net_pack, num_coeff_planes, num_moment_planes, solve, workspace_bytes)
+                  lowres_workspace_bytes, make_params, moments, net_backward, net_forward,
+                  net_num_params, net_pack, num_coeff_planes, num_moment_planes, solve, workspace_bytes)
 
 __all__ = ["PATHS", "Batch", "FLRError", "apply", "backward_workspace_bytes", "coefficients", "denoise",
            "denoise_backward", "denoise_lowres", "flnr_denoise", "flnr_workspace_bytes", "flr",
            "lowres_workspace_bytes", "make_params",
-           "moments", "net_forward", "net_num_params", "net_pack", "num_coeff_planes",
+           "moments", "net_backward", "net_forward", "net_num_params", "net_pack", "num_coeff_planes",
            "num_moment_planes", "solve", "workspace_bytes"]

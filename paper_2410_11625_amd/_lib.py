@@ -34,7 +34,8 @@ EXPORTED = ("flr_num_moment_planes", "flr_num_coeff_planes", "flr_denoise_worksp
             "flr_batch_workspace_bytes", "flr_batch_plan", "flr_batch_run",
             # include/flr_net.h
             "flr_net_num_params", "flr_net_packed_bytes", "flr_net_pack", "flr_net_workspace_bytes",
-            "flr_net_forward", "flr_flnr_workspace_bytes", "flr_flnr_denoise")
+            "flr_net_forward", "flr_net_backward_workspace_bytes", "flr_net_backward",
+            "flr_flnr_workspace_bytes", "flr_flnr_denoise")
 
 
 class FlrParams(ctypes.Structure):
@@ -161,6 +162,11 @@ def lib() -> ctypes.CDLL:
     L.flr_net_forward.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp,
                                   ctypes.c_size_t, vp]
     L.flr_net_forward.restype = ctypes.c_int
+    L.flr_net_backward_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    L.flr_net_backward_workspace_bytes.restype = ctypes.c_size_t
+    L.flr_net_backward.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp, vp,
+                                   ctypes.c_int32, vp, ctypes.c_size_t, vp]
+    L.flr_net_backward.restype = ctypes.c_int
     L.flr_flnr_workspace_bytes.argtypes = [P]
     L.flr_flnr_workspace_bytes.restype = ctypes.c_size_t
     L.flr_flnr_denoise.argtypes = [P, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]

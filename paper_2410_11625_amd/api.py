@@ -410,6 +410,37 @@ def net_forward(guides: torch.Tensor, noisy: torch.Tensor, packed: torch.Tensor,
     return out
 
 
+def net_backward(guides: torch.Tensor, noisy: torch.Tensor, params: torch.Tensor,
+                 packed: torch.Tensor, grad_out: torch.Tensor,
+                 grad_params: torch.Tensor | None = None, accumulate: bool = False,
+                 workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Gradient of a loss with respect to the FP32 parameters ``params``
+    (packed = net_pack(params)) given its gradient ``grad_out`` [4,H,W] with
+    respect to net_forward's output. accumulate=True adds into grad_params."""
+    _need(guides, "guides")
+    _need(noisy, "noisy")
+    _need(grad_out, "grad_out")
+    _need(params, "params", ndim=1)
+    if guides.shape[0] != NET_IN_GUIDES or noisy.shape[0] != NET_IN_NOISY or \
+            grad_out.shape[0] != NET_OUT:
+        raise ValueError("the network reads 8 guide and 3 noisy planes and writes 4")
+    _, H, W = guides.shape
+    need = int(lib().flr_net_backward_workspace_bytes(H, W))
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=guides.device)
+    if grad_params is None:
+        if accumulate:
+            raise ValueError("accumulate needs grad_params")
+        grad_params = torch.empty_like(params)
+    _need(grad_params, "grad_params", ndim=1)
+    check(lib().flr_net_backward(H, W, guides.data_ptr(), noisy.data_ptr(), params.data_ptr(),
+                                 packed.data_ptr(), grad_out.data_ptr(), grad_params.data_ptr(),
+                                 int(bool(accumulate)), workspace.data_ptr(),
+                                 workspace.numel() * workspace.element_size(), _stream(guides)),
+          "flr_net_backward")
+    return grad_params
+
+
 def flnr_workspace_bytes(p: FlrParams) -> int:
     return int(lib().flr_flnr_workspace_bytes(ctypes.byref(p)))
 
@@ -444,4 +475,5 @@ def flnr_denoise(noisy: torch.Tensor, guides12: torch.Tensor, packed: torch.Tens
 
 __all__ = ["FLRError", "PATHS", "make_params", "num_moment_planes", "num_coeff_planes",
            "workspace_bytes", "moments", "solve", "coefficients", "apply", "denoise",
-           "net_num_params", "net_pack", "net_forward", "flnr_workspace_bytes", "flnr_denoise"]
+           "net_num_params", "net_pack", "net_forward", "net_backward", "flnr_workspace_bytes",
+           "flnr_denoise"]

@@ -571,69 +571,15 @@ hipError_t launch(const ConvArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-}  // namespace flrnet
-
-using namespace flrnet;
-
-extern "C" {
-
-size_t flr_net_num_params(void) { return param_offset(12); }
-
-size_t flr_net_packed_bytes(void) { return packed_offset(12); }
-
-flr_status flr_net_pack(const float* params, void* packed, void* stream) {
-  if (!params || !packed) return FLR_ERR_NULL;
-  if (!aligned16(params) || !aligned16(packed)) return FLR_ERR_ALIGN;
-  if (overlaps(params, flr_net_num_params() * sizeof(float), packed, flr_net_packed_bytes()))
-    return FLR_ERR_ALIAS;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  for (int i = 0; i < 12; ++i) {
-    const Layer& L = kLayers[i];
-    const float* w = params + param_offset(i);
-    const float* b = w + (size_t)L.cout * L.cin * L.k * L.k;
-    const int n = (int)frag_count(L);
-    const PackArgs pa = {w, b, L.cin, L.cout, L.k, pad16(L.cin) / 16, pad16(L.cout) / 16,
-                         const_cast<bf16x4_t*>(layer_w(packed, i)),
-                         const_cast<float*>(layer_b(packed, i))};
-    hipLaunchKernelGGL(pack_kernel, dim3((n + 255) / 256), dim3(256), 0, s, pa);
-    if (hipGetLastError() != hipSuccess) return FLR_ERR_HIP;
-  }
-  return FLR_OK;
-}
-
-size_t flr_net_workspace_bytes(int32_t height, int32_t width) {
-  if (!valid_dims(height, width)) return 0;
-  size_t off[kActBufs + 1];
-  act_layout(grids(height, width), off);
-  return off[kActBufs];
-}
-
-flr_status flr_net_forward(int32_t height, int32_t width, const float* guides, const float* noisy,
-                           const void* packed, float* out, void* workspace, size_t workspace_bytes,
-                           void* stream) {
-  if (!valid_dims(height, width)) return FLR_ERR_SHAPE;
-  if (!guides || !noisy || !packed || !out) return FLR_ERR_NULL;
-  if (!aligned16(guides) || !aligned16(noisy) || !aligned16(packed) || !aligned16(out))
-    return FLR_ERR_ALIGN;
-  const size_t need = flr_net_workspace_bytes(height, width);
-  if (!workspace || workspace_bytes < need) return FLR_ERR_WORKSPACE;
-  if (!aligned16(workspace)) return FLR_ERR_ALIGN;
-  const size_t pb = (size_t)height * width * sizeof(float);
-  const size_t gb = FLR_NET_IN_GUIDES * pb, nb = FLR_NET_IN_NOISY * pb, ob = FLR_NET_OUT * pb;
-  const size_t kb = flr_net_packed_bytes();
-  if (overlaps(out, ob, guides, gb) || overlaps(out, ob, noisy, nb) || overlaps(out, ob, packed, kb) ||
-      overlaps(workspace, need, guides, gb) || overlaps(workspace, need, noisy, nb) ||
-      overlaps(workspace, need, packed, kb) || overlaps(workspace, need, out, ob))
-    return FLR_ERR_ALIAS;
-
-  const Grids g = grids(height, width);
+// The forward pass into the activation buffers at the start of ws (the
+// act_layout offsets), the sigmoid output planar FP32 into out.
+flr_status run_forward(const Grids& g, const float* guides, const float* noisy, const void* packed,
+                       float* out, char* ws, hipStream_t s) {
   size_t off[kActBufs + 1];
   act_layout(g, off);
-  char* ws = static_cast<char*>(workspace);
   auto buf = [&](int i) { return reinterpret_cast<uint16_t*>(ws + off[i]); };
   uint16_t *x0 = buf(0), *e0 = buf(1), *t1 = buf(2), *e1 = buf(3), *t2 = buf(4), *e2 = buf(5),
            *t3 = buf(6), *d1 = buf(7), *t4 = buf(8), *t5 = buf(9);
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   auto args = [&](int layer, int Hi, int Wi, int Ho, int Wo) {
     ConvArgs a = {};
     a.w = layer_w(packed, layer);
@@ -723,6 +669,290 @@ flr_status flr_net_forward(int32_t height, int32_t width, const float* guides, c
       return FLR_ERR_HIP;
   }
   return FLR_OK;
+}
+
+
+}  // namespace flrnet
+
+#include "flr_net_bwd.hpp"
+
+namespace flrnet {
+
+// Backward workspace: the forward's activation buffers (act_layout), then
+// in3's and out3's activations (fused away in the forward), the sigmoid
+// output, the BF16-rounded weights, the FP32 gradient tensors and the
+// weight-gradient partials.
+enum BwdBuf : int {
+  B_A, B_T6, B_SIG, B_WR, B_DZ1, B_GT6, B_GT5, B_GT4, B_G48, B_GD1, B_GT3, B_G96, B_GE2, B_GT2,
+  B_GE1, B_GT1, B_GE0, B_GA, B_PART, B_COUNT
+};
+// Output grid of each layer: 0 full, 1 half, 2 quarter.
+constexpr int kOutGrid[12] = {0, 0, 0, 1, 1, 2, 1, 1, 0, 0, 0, 0};
+
+inline size_t grid_px(const Grids& g, int which) {
+  return which == 0 ? (size_t)g.H * g.W : which == 1 ? (size_t)g.Hh * g.Wh : (size_t)g.Hq * g.Wq;
+}
+
+inline void bwd_layout(const Grids& g, size_t off[B_COUNT + 1]) {
+  size_t act[kActBufs + 1];
+  act_layout(g, act);
+  const size_t F = grid_px(g, 0), Hf = grid_px(g, 1), Q = grid_px(g, 2);
+  size_t part = 0;
+  for (int li = 0; li < 12; ++li) {
+    const WgradPlan wp = wgrad_plan(kLayers[li], stored_cin_blocks(li), grid_px(g, kOutGrid[li]));
+    const size_t n = (size_t)wp.nchunk * ((size_t)wp.ne * kWgAcc + kLayers[li].cout);
+    if (n > part) part = n;
+  }
+  const size_t sz[B_COUNT] = {16 * F * 2,  16 * F * 2,  4 * F * 4,   param_offset(12) * 4,
+                              4 * F * 4,   16 * F * 4,  16 * F * 4,  16 * F * 4,
+                              48 * F * 4,  32 * Hf * 4, 32 * Hf * 4, 96 * Hf * 4,
+                              64 * Q * 4,  64 * Hf * 4, 32 * Hf * 4, 32 * F * 4,
+                              16 * F * 4,  16 * F * 4,  part * 4};
+  off[0] = act[kActBufs];
+  for (int i = 0; i < B_COUNT; ++i) off[i + 1] = off[i] + align256(sz[i]);
+}
+
+// Weight and bias gradients of layer li: chunked partials, then the
+// fixed-order sum into grad (+= when accumulate).
+hipError_t layer_wgrad(int li, const Grids& g, const float* gout, const uint16_t* act,
+                       const BwdSrc& src, int Hi, int Wi, float* part, float* grad, int accumulate,
+                       hipStream_t s) {
+  const Layer& L = kLayers[li];
+  const int ncb = stored_cin_blocks(li);
+  const int og = kOutGrid[li];
+  const int Ho = og == 0 ? g.H : og == 1 ? g.Hh : g.Hq, Wo = og == 0 ? g.W : og == 1 ? g.Wh : g.Wq;
+  const WgradPlan wp = wgrad_plan(L, ncb, (size_t)Ho * Wo);
+  WgradArgs a = {};
+  a.g = gout;
+  a.act = act;
+  a.src = src;
+  a.Hi = Hi;
+  a.Wi = Wi;
+  a.Ho = Ho;
+  a.Wo = Wo;
+  a.cout = L.cout;
+  a.ncb = ncb;
+  a.k = L.k;
+  a.stride = L.stride;
+  a.ne = wp.ne;
+  a.chunk_px = wp.chunk_px;
+  a.part = part;
+  a.bpart = part + (size_t)wp.nchunk * wp.ne * kWgAcc;
+  hipLaunchKernelGGL(wgrad_kernel, dim3(wp.nchunk, wp.wg_y), dim3(256), wgrad_lds_bytes(), s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const WreduceArgs r = {part, a.bpart, wp.nchunk, wp.ne, ncb, L.cin, L.cout, L.k,
+                         grad + param_offset(li), accumulate};
+  const int n = L.cout * L.cin * L.k * L.k + L.cout;
+  hipLaunchKernelGGL(wreduce_kernel, dim3((n + 255) / 256), dim3(256), 0, s, r);
+  return hipGetLastError();
+}
+
+// Gradient of layer li's input (channels 0..cin-1, HWC FP32 into dx), plus
+// an optional addend tensor's channels.
+hipError_t layer_dgrad(int li, const Grids& g, const float* gout, const uint16_t* act,
+                       const float* wr, int Hi, int Wi, float* dx, const float* add, int add_cs,
+                       int add_off, hipStream_t s) {
+  const Layer& L = kLayers[li];
+  const int og = kOutGrid[li];
+  DgradArgs a = {};
+  a.g = gout;
+  a.act = act;
+  a.w = wr + param_offset(li);
+  a.cin = L.cin;
+  a.cout = L.cout;
+  a.k = L.k;
+  a.stride = L.stride;
+  a.Hi = Hi;
+  a.Wi = Wi;
+  a.Ho = og == 0 ? g.H : og == 1 ? g.Hh : g.Hq;
+  a.Wo = og == 0 ? g.W : og == 1 ? g.Wh : g.Wq;
+  a.dx = dx;
+  a.add = add;
+  a.add_cs = add_cs;
+  a.add_off = add_off;
+  const size_t n = (size_t)Hi * Wi;
+  hipLaunchKernelGGL(dgrad_kernel, dim3((unsigned)((n + 255) / 256), L.cin / 8), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t up2_bwd(const float* fine, int H, int W, int cs, float* low, int Hl, int Wl, int nc,
+                   hipStream_t s) {
+  const size_t n = (size_t)Hl * Wl * nc;
+  const Up2BwdArgs a = {fine, H, W, cs, low, Hl, Wl, nc};
+  hipLaunchKernelGGL(up2_bwd_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+flr_status run_backward(const Grids& g, const float* guides, const float* noisy,
+                        const float* params, const void* packed, const float* dout, float* grad,
+                        int accumulate, char* ws, hipStream_t s) {
+  size_t act[kActBufs + 1], off[B_COUNT + 1];
+  act_layout(g, act);
+  bwd_layout(g, off);
+  auto abuf = [&](int i) { return reinterpret_cast<uint16_t*>(ws + act[i]); };
+  auto fbuf = [&](int i) { return reinterpret_cast<float*>(ws + off[i]); };
+  uint16_t *x0 = abuf(0), *e0 = abuf(1), *t1 = abuf(2), *e1 = abuf(3), *t2 = abuf(4),
+           *e2 = abuf(5), *t3 = abuf(6), *d1 = abuf(7), *t4 = abuf(8), *t5 = abuf(9);
+  uint16_t* a16 = reinterpret_cast<uint16_t*>(ws + off[B_A]);
+  uint16_t* t6 = reinterpret_cast<uint16_t*>(ws + off[B_T6]);
+  float *sig = fbuf(B_SIG), *wr = fbuf(B_WR), *part = fbuf(B_PART);
+  const int F = (int)grid_px(g, 0);
+  const int np = (int)param_offset(12);
+
+  const RoundArgs ra = {params, wr, np};
+  hipLaunchKernelGGL(round_params_kernel, dim3((np + 255) / 256), dim3(256), 0, s, ra);
+  if (hipGetLastError() != hipSuccess) return FLR_ERR_HIP;
+  flr_status st = run_forward(g, guides, noisy, packed, sig, ws, s);
+  if (st != FLR_OK) return st;
+  {  // in3 and out3 outputs, which the forward keeps in registers
+    ConvArgs a = {};
+    a.Hi = a.Ho = g.H;
+    a.Wi = a.Wo = g.W;
+    a.w = layer_w(packed, 0);
+    a.b = layer_b(packed, 0);
+    a.in0 = x0;
+    a.out = a16;
+    if (launch<16, 16, 3, 1, IN_HWC, 0, FUSE_NONE, 0>(a, s) != hipSuccess) return FLR_ERR_HIP;
+    a.w = layer_w(packed, 10);
+    a.b = layer_b(packed, 10);
+    a.in0 = t5;
+    a.out = t6;
+    if (launch<16, 16, 3, 1, IN_HWC, 0, FUSE_NONE, 0>(a, s) != hipSuccess) return FLR_ERR_HIP;
+  }
+  const SigmoidBwdArgs sa = {dout, sig, fbuf(B_DZ1), F, FLR_NET_OUT};
+  hipLaunchKernelGGL(sigmoid_bwd_kernel, dim3((F + 255) / 256), dim3(256), 0, s, sa);
+  if (hipGetLastError() != hipSuccess) return FLR_ERR_HIP;
+
+  auto plain = [](const uint16_t* in, int cs) { return BwdSrc{in, nullptr, cs, cs, 0, 0}; };
+  const BwdSrc cat48 = {d1, e0, 32, 32, 16, g.Wh};
+  const BwdSrc cat96 = {e2, e1, 64, 64, 32, g.Wq};
+  bool ok = true;
+  auto W = [&](int li, const float* go, const uint16_t* ac, const BwdSrc& src, int Hi, int Wi) {
+    ok = ok && layer_wgrad(li, g, go, ac, src, Hi, Wi, part, grad, accumulate, s) == hipSuccess;
+  };
+  auto D = [&](int li, const float* go, const uint16_t* ac, int Hi, int Wi, float* dx,
+               const float* add = nullptr, int add_cs = 0, int add_off = 0) {
+    ok = ok && layer_dgrad(li, g, go, ac, wr, Hi, Wi, dx, add, add_cs, add_off, s) == hipSuccess;
+  };
+  // out1 (sigmoid head, no mask) and the layers back to in3, as in the forward reversed
+  W(11, fbuf(B_DZ1), nullptr, plain(t6, 16), g.H, g.W);
+  D(11, fbuf(B_DZ1), nullptr, g.H, g.W, fbuf(B_GT6));
+  W(10, fbuf(B_GT6), t6, plain(t5, 16), g.H, g.W);
+  D(10, fbuf(B_GT6), t6, g.H, g.W, fbuf(B_GT5));
+  W(9, fbuf(B_GT5), t5, plain(t4, 16), g.H, g.W);
+  D(9, fbuf(B_GT5), t5, g.H, g.W, fbuf(B_GT4));
+  W(8, fbuf(B_GT4), t4, cat48, g.H, g.W);
+  D(8, fbuf(B_GT4), t4, g.H, g.W, fbuf(B_G48));
+  ok = ok && up2_bwd(fbuf(B_G48), g.H, g.W, 48, fbuf(B_GD1), g.Hh, g.Wh, 32, s) == hipSuccess;
+  W(7, fbuf(B_GD1), d1, plain(t3, 32), g.Hh, g.Wh);
+  D(7, fbuf(B_GD1), d1, g.Hh, g.Wh, fbuf(B_GT3));
+  W(6, fbuf(B_GT3), t3, cat96, g.Hh, g.Wh);
+  D(6, fbuf(B_GT3), t3, g.Hh, g.Wh, fbuf(B_G96));
+  ok = ok && up2_bwd(fbuf(B_G96), g.Hh, g.Wh, 96, fbuf(B_GE2), g.Hq, g.Wq, 64, s) == hipSuccess;
+  W(5, fbuf(B_GE2), e2, plain(t2, 64), g.Hh, g.Wh);
+  D(5, fbuf(B_GE2), e2, g.Hh, g.Wh, fbuf(B_GT2));
+  W(4, fbuf(B_GT2), t2, plain(e1, 32), g.Hh, g.Wh);
+  D(4, fbuf(B_GT2), t2, g.Hh, g.Wh, fbuf(B_GE1), fbuf(B_G96), 96, 64);
+  W(3, fbuf(B_GE1), e1, plain(t1, 32), g.H, g.W);
+  D(3, fbuf(B_GE1), e1, g.H, g.W, fbuf(B_GT1));
+  W(2, fbuf(B_GT1), t1, plain(e0, 16), g.H, g.W);
+  D(2, fbuf(B_GT1), t1, g.H, g.W, fbuf(B_GE0), fbuf(B_G48), 48, 32);
+  W(1, fbuf(B_GE0), e0, plain(a16, 16), g.H, g.W);
+  D(1, fbuf(B_GE0), e0, g.H, g.W, fbuf(B_GA));
+  W(0, fbuf(B_GA), a16, plain(x0, 16), g.H, g.W);
+  return ok ? FLR_OK : FLR_ERR_HIP;
+}
+}  // namespace flrnet
+
+using namespace flrnet;
+
+extern "C" {
+
+size_t flr_net_num_params(void) { return param_offset(12); }
+
+size_t flr_net_packed_bytes(void) { return packed_offset(12); }
+
+flr_status flr_net_pack(const float* params, void* packed, void* stream) {
+  if (!params || !packed) return FLR_ERR_NULL;
+  if (!aligned16(params) || !aligned16(packed)) return FLR_ERR_ALIGN;
+  if (overlaps(params, flr_net_num_params() * sizeof(float), packed, flr_net_packed_bytes()))
+    return FLR_ERR_ALIAS;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  for (int i = 0; i < 12; ++i) {
+    const Layer& L = kLayers[i];
+    const float* w = params + param_offset(i);
+    const float* b = w + (size_t)L.cout * L.cin * L.k * L.k;
+    const int n = (int)frag_count(L);
+    const PackArgs pa = {w, b, L.cin, L.cout, L.k, pad16(L.cin) / 16, pad16(L.cout) / 16,
+                         const_cast<bf16x4_t*>(layer_w(packed, i)),
+                         const_cast<float*>(layer_b(packed, i))};
+    hipLaunchKernelGGL(pack_kernel, dim3((n + 255) / 256), dim3(256), 0, s, pa);
+    if (hipGetLastError() != hipSuccess) return FLR_ERR_HIP;
+  }
+  return FLR_OK;
+}
+
+size_t flr_net_workspace_bytes(int32_t height, int32_t width) {
+  if (!valid_dims(height, width)) return 0;
+  size_t off[kActBufs + 1];
+  act_layout(grids(height, width), off);
+  return off[kActBufs];
+}
+
+flr_status flr_net_forward(int32_t height, int32_t width, const float* guides, const float* noisy,
+                           const void* packed, float* out, void* workspace, size_t workspace_bytes,
+                           void* stream) {
+  if (!valid_dims(height, width)) return FLR_ERR_SHAPE;
+  if (!guides || !noisy || !packed || !out) return FLR_ERR_NULL;
+  if (!aligned16(guides) || !aligned16(noisy) || !aligned16(packed) || !aligned16(out))
+    return FLR_ERR_ALIGN;
+  const size_t need = flr_net_workspace_bytes(height, width);
+  if (!workspace || workspace_bytes < need) return FLR_ERR_WORKSPACE;
+  if (!aligned16(workspace)) return FLR_ERR_ALIGN;
+  const size_t pb = (size_t)height * width * sizeof(float);
+  const size_t gb = FLR_NET_IN_GUIDES * pb, nb = FLR_NET_IN_NOISY * pb, ob = FLR_NET_OUT * pb;
+  const size_t kb = flr_net_packed_bytes();
+  if (overlaps(out, ob, guides, gb) || overlaps(out, ob, noisy, nb) || overlaps(out, ob, packed, kb) ||
+      overlaps(workspace, need, guides, gb) || overlaps(workspace, need, noisy, nb) ||
+      overlaps(workspace, need, packed, kb) || overlaps(workspace, need, out, ob))
+    return FLR_ERR_ALIAS;
+  return run_forward(grids(height, width), guides, noisy, packed, out,
+                     static_cast<char*>(workspace), reinterpret_cast<hipStream_t>(stream));
+}
+
+size_t flr_net_backward_workspace_bytes(int32_t height, int32_t width) {
+  if (!valid_dims(height, width)) return 0;
+  size_t off[B_COUNT + 1];
+  bwd_layout(grids(height, width), off);
+  return off[B_COUNT];
+}
+
+flr_status flr_net_backward(int32_t height, int32_t width, const float* guides, const float* noisy,
+                            const float* params, const void* packed, const float* grad_out,
+                            float* grad_params, int32_t accumulate, void* workspace,
+                            size_t workspace_bytes, void* stream) {
+  if (!valid_dims(height, width)) return FLR_ERR_SHAPE;
+  if (!guides || !noisy || !params || !packed || !grad_out || !grad_params) return FLR_ERR_NULL;
+  if (!aligned16(guides) || !aligned16(noisy) || !aligned16(params) || !aligned16(packed) ||
+      !aligned16(grad_out) || !aligned16(grad_params))
+    return FLR_ERR_ALIGN;
+  if (accumulate != 0 && accumulate != 1) return FLR_ERR_MODE;
+  const size_t need = flr_net_backward_workspace_bytes(height, width);
+  if (!workspace || workspace_bytes < need) return FLR_ERR_WORKSPACE;
+  if (!aligned16(workspace)) return FLR_ERR_ALIGN;
+  const size_t pb = (size_t)height * width * sizeof(float);
+  const size_t gb = FLR_NET_IN_GUIDES * pb, nb = FLR_NET_IN_NOISY * pb, ob = FLR_NET_OUT * pb;
+  const size_t kb = flr_net_packed_bytes(), wb = flr_net_num_params() * sizeof(float);
+  const void* ins[5] = {guides, noisy, params, packed, grad_out};
+  const size_t inb[5] = {gb, nb, wb, kb, ob};
+  for (int i = 0; i < 5; ++i)
+    if (overlaps(workspace, need, ins[i], inb[i]) || overlaps(grad_params, wb, ins[i], inb[i]))
+      return FLR_ERR_ALIAS;
+  if (overlaps(workspace, need, grad_params, wb)) return FLR_ERR_ALIAS;
+  return run_backward(grids(height, width), guides, noisy, params, packed, grad_out, grad_params,
+                      accumulate, static_cast<char*>(workspace),
+                      reinterpret_cast<hipStream_t>(stream));
 }
 
 size_t flr_flnr_workspace_bytes(const flr_params* p) {

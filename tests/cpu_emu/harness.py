@@ -39,6 +39,7 @@ def build(force: bool = False) -> str:
     deps = srcs + [net_src, adj_src, lr_src, os.path.join(HERE, "hip", "hip_runtime.h"),
                    os.path.join(CSRC, "flr_device.hpp"), os.path.join(CSRC, "flr_launch.hpp"),
                    os.path.join(CSRC, "flr_adjoint.hpp"), os.path.join(CSRC, "flr_lowres.hpp"),
+                   os.path.join(CSRC, "flr_net_bwd.hpp"),
                    os.path.join(INCLUDE, "flr.h"), os.path.join(INCLUDE, "flr_net.h")]
     if not force and os.path.exists(SO) and \
             os.path.getmtime(SO) >= max(os.path.getmtime(d) for d in deps):
@@ -129,6 +130,31 @@ class Emu:
         need = int(L.flr_net_workspace_bytes(H, W))
         wp, _ = self.buf(shape=(need // 4,))
         self.check(L.flr_net_forward(H, W, gp, yp, kp, op, wp, need, None), "flr_net_forward")
+        return out.copy()
+
+    def net_backward(self, guides, noisy, params, grad_out):
+        """flr_net_backward -> FP32 parameter gradients (layout of params)."""
+        L = self.L
+        vp = ctypes.c_void_p
+        L.flr_net_packed_bytes.restype = ctypes.c_size_t
+        L.flr_net_pack.argtypes = [vp, vp, vp]
+        L.flr_net_backward_workspace_bytes.restype = ctypes.c_size_t
+        L.flr_net_backward_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        L.flr_net_backward.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp, vp,
+                                       ctypes.c_int32, vp, ctypes.c_size_t, vp]
+        _, H, W = guides.shape
+        pp, _ = self.buf(params)
+        kb = int(L.flr_net_packed_bytes())
+        kp, _ = self.buf(shape=(kb // 4,))
+        self.check(L.flr_net_pack(pp, kp, None), "flr_net_pack")
+        gp, _ = self.buf(guides)
+        yp, _ = self.buf(noisy)
+        dp, _ = self.buf(grad_out)
+        op, out = self.buf(shape=params.shape)
+        need = int(L.flr_net_backward_workspace_bytes(H, W))
+        wp, _ = self.buf(shape=(need // 4,))
+        self.check(L.flr_net_backward(H, W, gp, yp, pp, kp, dp, op, 0, wp, need, None),
+                   "flr_net_backward")
         return out.copy()
 
     def backward(self, noisy, guides, grad_out, p: FlrParams):
@@ -241,6 +267,23 @@ def _rel_err(got, want) -> float:
     return float(np.max(np.abs(got - want) / den))
 
 
+def net_grad_errors(got, want64: dict, weights: dict) -> dict:
+    """Per layer, max |got - want| over the layer's weights (and its biases)
+    relative to the largest |want| of the same; got is the flat FP32 gradient
+    vector in parameter order, want64 the oracle's {layer: (dW, db)}."""
+    from synth.net_weights import LAYERS
+    out, o = {}, 0
+    for name, _, _, _ in LAYERS:
+        w, b = weights[name]
+        for tag, ref in (("w", want64[name][0]), ("b", want64[name][1])):
+            n = ref.size
+            g = np.asarray(got[o:o + n], np.float64).reshape(ref.shape)
+            out[f"{name}.{tag}"] = float(np.max(np.abs(g - ref)) / max(np.max(np.abs(ref)), 1e-30))
+            o += n
+    assert o == len(got)
+    return out
+
+
 def run_case(spec: dict) -> dict:
     """Execute one case described by ``spec`` and return error figures."""
     from oracle import flr_ref as ref
@@ -272,6 +315,18 @@ def run_case(spec: dict) -> dict:
             d = np.abs(got - want)
             return {"maxabs": float(d.max()), "median": float(np.median(d)),
                     "within": float(np.mean(d <= 2e-3)), "shape": list(got.shape)}
+        if kind == "net_bwd":
+            from oracle import net_adjoint, net_ref
+            from synth.net_weights import flatten_net_weights, make_net_weights
+            fr = make_config(1, h=H, w=W)
+            wts = make_net_weights(spec.get("seed", 2))
+            G = np.random.default_rng(spec.get("seed", 2) + 1).standard_normal((4, H, W))
+            got = emu.net_backward(fr["guides"], fr["noisy"], flatten_net_weights(wts),
+                                   G.astype(np.float32))
+            cache = {}
+            net_ref.net_forward(fr["guides"], fr["noisy"], wts, cache=cache)
+            grads = net_adjoint.net_backward(cache, G.astype(np.float32).astype(np.float64))
+            return net_grad_errors(got, grads, wts)
         if kind == "batch":
             from oracle import flr_lowres
             # plain frames of uneven sizes and one joint frame (noisy input and

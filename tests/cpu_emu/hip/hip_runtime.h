@@ -24,6 +24,16 @@ struct dim3 {
   constexpr dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
 };
 
+struct alignas(8) uint2 {
+  unsigned x, y;
+};
+struct alignas(16) uint4 {
+  unsigned x, y, z, w;
+};
+struct alignas(16) float4 {
+  float x, y, z, w;
+};
+
 extern thread_local dim3 threadIdx;
 extern thread_local dim3 blockIdx;
 extern dim3 blockDim;

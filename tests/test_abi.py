@@ -43,6 +43,10 @@ def test_net_parameter_count_and_sizes(L):
     assert L.flr_net_workspace_bytes(0, 5) == 0 and L.flr_net_workspace_bytes(5, 40000) == 0
     # 9 BF16 activation buffers: 124 channel-bytes/2 per full-resolution pixel (rounded up)
     assert L.flr_net_workspace_bytes(64, 64) >= 64 * 64 * 2 * 124
+    # the forward's activations, then the backward's FP32 gradient tensors
+    assert L.flr_net_backward_workspace_bytes(64, 64) > L.flr_net_workspace_bytes(64, 64) + \
+        64 * 64 * 4 * 200
+    assert L.flr_net_backward_workspace_bytes(0, 5) == 0
     p = FlrParams(height=32, width=32, num_guides=12, num_channels=3, radius=8, eps=1e-3,
                   eps_mul=0.0, reg_mode=0, average_coeffs=1, fused=2, flags=0, tile_rows=0)
     assert L.flr_flnr_workspace_bytes(ctypes.byref(p)) >= L.flr_net_workspace_bytes(32, 32)
@@ -60,6 +64,14 @@ def test_net_entry_points_validate_before_launch(L):
     p = FlrParams(height=8, width=8, num_guides=8, num_channels=3, radius=2, eps=1e-3,
                   eps_mul=0.0, reg_mode=0, average_coeffs=1, fused=2, flags=0, tile_rows=0)
     assert L.flr_flnr_denoise(ctypes.byref(p), a16, a16, a16, a16, a16, 64, None) == 5  # CHANNELS
+    nb = L.flr_net_backward
+    assert nb(0, 8, a16, a16, a16, a16, a16, a16, 0, a16, 64, None) == 2     # FLR_ERR_SHAPE
+    assert nb(8, 8, a16, None, a16, a16, a16, a16, 0, a16, 64, None) == 1    # FLR_ERR_NULL
+    assert nb(8, 8, a16, a16, a16 + 4, a16, a16, a16, 0, a16, 64, None) == 7  # FLR_ERR_ALIGN
+    assert nb(8, 8, a16, a16, a16, a16, a16, a16, 2, a16, 64, None) == 9     # FLR_ERR_MODE
+    assert nb(8, 8, a16, a16, a16, a16, a16, a16, 0, a16, 64, None) == 8     # FLR_ERR_WORKSPACE
+    need = L.flr_net_backward_workspace_bytes(8, 8)
+    assert nb(8, 8, a16, a16, a16, a16, a16, a16, 0, a16, need, None) == 6   # FLR_ERR_ALIAS
 
 
 def test_params_struct_layout_matches_header():

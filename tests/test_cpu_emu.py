@@ -67,6 +67,14 @@ def test_emulated_net_matches_oracle(H, W):
     assert res["median"] <= 1e-5 and res["within"] >= 0.99 and res["maxabs"] <= 2e-2, res
 
 
+# The network's backward (flr_net_backward) against the FP64 backward oracle
+# on a frame where the emulated BF16 forward rounds every activation as the
+# oracle does: FP32-level agreement (criteria: tests/test_gpu_net_backward.py).
+def test_emulated_net_backward_matches_oracle():
+    res = run_in_subprocess(dict(kind="net_bwd", H=9, W=13, Q=8, C=3, r=0))
+    assert max(res.values()) <= 1e-4, res
+
+
 # The adjoint (flr_denoise_backward) against the FP64 adjoint oracle given
 # the same FP32 eps and eps_mul. Its arithmetic is FP64 throughout (moments
 # from FP64 window sums of anchored products, FP64 fields and sums), so the
