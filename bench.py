@@ -255,6 +255,41 @@ def time_adjoint(flr, torch, np, sets, nsets, dev, stream, args):
             "workspace_bytes": int(ws.numel()), "steps": args.adjoint_steps}
 
 
+def time_train(flr, torch, np, dev, stream, args):
+    """One FLNR training step per timed step: 8 crops of 256 x 256 (the
+    training workload, inputs resident in HBM), each through the network,
+    FLR over 12 guides, the L1 loss, the FLR adjoint and the network
+    backward, then the AdamW update of the FP32 master weights."""
+    from synth import make_training_batch
+    from synth.net_weights import flatten_net_weights, make_net_weights
+    crops = []
+    for c in make_training_batch():
+        g12 = torch.zeros((12,) + c["guides"].shape[1:], dtype=torch.float32, device=dev)
+        g12[:8].copy_(torch.from_numpy(c["guides"]))
+        crops.append({"guides12": g12, "noisy": torch.from_numpy(c["noisy"]).to(dev),
+                      "target": torch.from_numpy(c["target"]).to(dev)})
+    params = torch.from_numpy(flatten_net_weights(make_net_weights(2))).to(dev)
+    tr = flr.FLNRTrainer(params, lr=1e-3)
+    first = tr.step(crops).sum().item()
+    tr.step(crops)
+    torch.cuda.synchronize()
+    ev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(2))
+          for _ in range(args.train_steps)]
+    for k in range(args.train_steps):
+        ev[k][0].record(stream)
+        losses = tr.step(crops)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    px = sum(c["noisy"].shape[1] * c["noisy"].shape[2] for c in crops)
+    return {"ms_per_step": round(ms, 4), "value": round(px / (ms / 1e3) / 1e6, 2),
+            "unit": "Mpixel/s", "batch": len(crops), "crop": list(crops[0]["noisy"].shape[1:]),
+            "config": "FLNR training step: network, FLR over 12 guides, L1, FLR adjoint, "
+                      "network backward per crop, AdamW on FP32 master weights",
+            "loss_first": round(first, 6), "loss_after": round(losses.sum().item(), 6),
+            "steps": args.train_steps}
+
+
 def time_lowres(flr, torch, np, sets, nsets, dev, stream, args):
     """The paper's fast variant on the FLR workload's frames: 8x8 block
     moments, Gaussian sigma 1.25 (taps -4..4) at the low resolution, solve,
@@ -394,6 +429,8 @@ def main(argv=None):
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--lowres-steps", type=int, default=50)
     ap.add_argument("--adjoint-steps", type=int, default=10)
+    ap.add_argument("--no-train", action="store_true", help="skip the training-step timing")
+    ap.add_argument("--train-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter reference)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -519,6 +556,10 @@ def main(argv=None):
     if not args.no_adjoint:
         adjoint = time_adjoint(flr, torch, np, sets, nsets, dev, stream, args)
 
+    train = None
+    if not args.no_train:
+        train = time_train(flr, torch, np, dev, stream, args)
+
     if args.copy_calibration:
         src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -578,6 +619,7 @@ def main(argv=None):
         "adjoint": adjoint,
         "lowres": lowres,
         "batch": batch,
+        "train": train,
     }
     print(json.dumps(line))
     return 0

@@ -1,0 +1,60 @@
+/*
+ * flr_train.h - C ABI of the element-wise stages of an FLNR training step.
+ *
+ * Sec. 3.3 trains the guide network end to end: the denoised output's loss
+ * is backpropagated through the regression (flr_denoise_backward, flr.h) and
+ * the network (flr_net_backward, flr_net.h) into the weights. A step on a
+ * batch of crops is, per crop, flr_net_forward -> flr_denoise over the 12
+ * guides -> flr_l1_loss_grad -> flr_denoise_backward -> flr_net_backward
+ * (accumulating), and then one flr_adamw_step on the FP32 master weights.
+ *
+ * Ownership and errors as in flr.h: caller-owned device memory, 16-byte
+ * aligned; nothing is allocated; arguments are checked on the host before
+ * any launch; FLR_ERR_HIP on launch failure. Kernels run on `stream`.
+ */
+#ifndef FLR_TRAIN_H
+#define FLR_TRAIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "flr.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Workspace bytes of flr_l1_loss_grad for n values (0 when n is outside
+ * 1..2^34). */
+size_t flr_l1_workspace_bytes(int64_t n);
+
+/* L1 loss and its gradient over n FP32 values: *loss = scale * sum |out[i] -
+ * target[i]| (FP64, summed in a fixed order), grad[i] = scale * sign(out[i] -
+ * target[i]) with sign(0) = 0 (the difference taken in FP32). scale = 1 /
+ * (number of values in the batch) gives the mean absolute error. loss is one
+ * device double (8-byte alignment suffices, so a batch's losses can sit side
+ * by side in one array). FLR_ERR_SHAPE for n outside 1..2^34, FLR_ERR_EPS for a scale
+ * that is not finite, FLR_ERR_ALIAS when an output overlaps an input or
+ * another output. */
+flr_status flr_l1_loss_grad(int64_t n, const float* out, const float* target, float scale,
+                            float* grad, double* loss, void* workspace, size_t workspace_bytes,
+                            void* stream);
+
+/* One AdamW step (Adam with decoupled weight decay) on n FP32 parameters, in
+ * place: with t = step (1 for the first update),
+ *   p <- p - lr * weight_decay * p
+ *   m <- beta1 m + (1 - beta1) g,   v <- beta2 v + (1 - beta2) g^2
+ *   p <- p - lr / (1 - beta1^t) * m / (sqrt(v) / sqrt(1 - beta2^t) + eps)
+ * m and v (zero before the first step) are updated in place. FP32
+ * arithmetic; the bias corrections are formed in FP64 on the host.
+ * FLR_ERR_MODE for step < 1, FLR_ERR_EPS for a negative or non-finite
+ * hyperparameter or beta >= 1, FLR_ERR_ALIAS when two of the arrays overlap. */
+flr_status flr_adamw_step(int64_t n, float* params, const float* grads, float* m, float* v,
+                          int32_t step, float lr, float beta1, float beta2, float eps,
+                          float weight_decay, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLR_TRAIN_H */

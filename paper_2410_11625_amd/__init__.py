@@ -6,12 +6,12 @@ Regression for Low-Cost, Path Traced Lambertian Global Illumination"
 hand-written HIP kernels behind the C ABI in ``include/flr.h`` and
 ``include/flr_net.h``. This package is the thin Python binding.
 """
-from .api import (PATHS, Batch, FLRError, apply, backward_workspace_bytes, coefficients, denoise,
+from .api import (PATHS, Batch, FLNRTrainer, FLRError, adamw_step, apply, backward_workspace_bytes, coefficients, denoise,
                   denoise_backward, denoise_lowres, flnr_denoise, flnr_workspace_bytes, flr,
-                  lowres_workspace_bytes, make_params, moments, net_backward, net_forward,
+                  l1_loss_grad, lowres_workspace_bytes, make_params, moments, net_backward, net_forward,
                   net_num_params, net_pack, num_coeff_planes, num_moment_planes, solve, workspace_bytes)
 
-__all__ = ["PATHS", "Batch", "FLRError", "apply", "backward_workspace_bytes", "coefficients", "denoise",
+__all__ = ["PATHS", "Batch", "FLNRTrainer", "FLRError", "adamw_step", "l1_loss_grad", "apply", "backward_workspace_bytes", "coefficients", "denoise",
            "denoise_backward", "denoise_lowres", "flnr_denoise", "flnr_workspace_bytes", "flr",
            "lowres_workspace_bytes", "make_params",
            "moments", "net_backward", "net_forward", "net_num_params", "net_pack", "num_coeff_planes",

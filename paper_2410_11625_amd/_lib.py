@@ -35,7 +35,9 @@ EXPORTED = ("flr_num_moment_planes", "flr_num_coeff_planes", "flr_denoise_worksp
             # include/flr_net.h
             "flr_net_num_params", "flr_net_packed_bytes", "flr_net_pack", "flr_net_workspace_bytes",
             "flr_net_forward", "flr_net_backward_workspace_bytes", "flr_net_backward",
-            "flr_flnr_workspace_bytes", "flr_flnr_denoise")
+            "flr_flnr_workspace_bytes", "flr_flnr_denoise",
+            # include/flr_train.h
+            "flr_l1_workspace_bytes", "flr_l1_loss_grad", "flr_adamw_step")
 
 
 class FlrParams(ctypes.Structure):
@@ -171,6 +173,14 @@ def lib() -> ctypes.CDLL:
     L.flr_flnr_workspace_bytes.restype = ctypes.c_size_t
     L.flr_flnr_denoise.argtypes = [P, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     L.flr_flnr_denoise.restype = ctypes.c_int
+    L.flr_l1_workspace_bytes.argtypes = [ctypes.c_int64]
+    L.flr_l1_workspace_bytes.restype = ctypes.c_size_t
+    L.flr_l1_loss_grad.argtypes = [ctypes.c_int64, vp, vp, ctypes.c_float, vp, vp, vp,
+                                   ctypes.c_size_t, vp]
+    L.flr_l1_loss_grad.restype = ctypes.c_int
+    f = ctypes.c_float
+    L.flr_adamw_step.argtypes = [ctypes.c_int64, vp, vp, vp, vp, ctypes.c_int32, f, f, f, f, f, vp]
+    L.flr_adamw_step.restype = ctypes.c_int
     L.flr_status_str.argtypes = [ctypes.c_int]
     L.flr_status_str.restype = ctypes.c_char_p
     _lib = L

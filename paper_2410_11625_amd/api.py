@@ -473,7 +473,130 @@ def flnr_denoise(noisy: torch.Tensor, guides12: torch.Tensor, packed: torch.Tens
     return out
 
 
+# Training step (include/flr_train.h)
+
+def l1_loss_grad(out: torch.Tensor, target: torch.Tensor, scale: float,
+                 grad: torch.Tensor | None = None, loss: torch.Tensor | None = None,
+                 workspace: torch.Tensor | None = None):
+    """(grad, loss): grad = scale sign(out - target) (shape of out), loss a
+    float64 device tensor of one element, scale * sum |out - target|."""
+    for t, name in ((out, "out"), (target, "target")):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or \
+                t.device.type != "cuda" or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float32 device tensor")
+    if out.shape != target.shape:
+        raise ValueError("out and target must have the same shape")
+    n = out.numel()
+    if grad is None:
+        grad = torch.empty_like(out)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float64, device=out.device)
+    need = int(lib().flr_l1_workspace_bytes(n))
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=out.device)
+    check(lib().flr_l1_loss_grad(n, out.data_ptr(), target.data_ptr(), float(scale),
+                                 grad.data_ptr(), loss.data_ptr(), workspace.data_ptr(),
+                                 workspace.numel(), _stream(out)), "flr_l1_loss_grad")
+    return grad, loss
+
+
+def adamw_step(params: torch.Tensor, grads: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
+               step: int, lr: float, betas=(0.9, 0.999), eps: float = 1e-8,
+               weight_decay: float = 0.0) -> None:
+    """AdamW update of params (in place) with moments m, v (in place)."""
+    for t, name in ((params, "params"), (grads, "grads"), (m, "m"), (v, "v")):
+        _need(t, name, ndim=1)
+        if t.numel() != params.numel():
+            raise ValueError(f"{name} must have {params.numel()} elements")
+    check(lib().flr_adamw_step(params.numel(), params.data_ptr(), grads.data_ptr(), m.data_ptr(),
+                               v.data_ptr(), int(step), float(lr), float(betas[0]),
+                               float(betas[1]), float(eps), float(weight_decay),
+                               _stream(params)), "flr_adamw_step")
+
+
+class FLNRTrainer:
+    """Training of the guide network through FLR (Sec. 3.3): per crop the
+    network writes guide planes 8..11, FLR (two-pass path) denoises over the
+    12 guides, the L1 loss against the target gives dL/d(out), the FLR adjoint
+    gives dL/d(guides) and the network backward accumulates dL/d(weights);
+    then one AdamW step updates the FP32 master weights. ``params`` (FP32
+    device vector) is updated in place. Buffers are allocated once per crop
+    size and reused."""
+
+    def __init__(self, params: torch.Tensor, lr: float = 1e-3, betas=(0.9, 0.999),
+                 eps: float = 1e-8, weight_decay: float = 0.0, radius: int = 8,
+                 flr_eps: float = 1e-3):
+        _need(params, "params", ndim=1)
+        if params.numel() != net_num_params():
+            raise ValueError(f"expected {net_num_params()} parameters")
+        self.params = params
+        self.grad = torch.zeros_like(params)
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.t = 0
+        self.lr, self.betas, self.eps, self.wd = lr, betas, eps, weight_decay
+        self.radius, self.flr_eps = radius, flr_eps
+        self._bufs = {}
+
+    def _buffers(self, H, W, dev):
+        key = (H, W)
+        if key not in self._bufs:
+            p = make_params(H, W, 12, 3, self.radius, eps=self.flr_eps, fused="two_pass")
+            b = dict(
+                g12=torch.empty((12, H, W), dtype=torch.float32, device=dev),
+                out=torch.empty((3, H, W), dtype=torch.float32, device=dev),
+                G=torch.empty((3, H, W), dtype=torch.float32, device=dev),
+                dy=torch.empty((3, H, W), dtype=torch.float32, device=dev),
+                dg=torch.empty((12, H, W), dtype=torch.float32, device=dev),
+                dreg=torch.empty(2, dtype=torch.float64, device=dev),
+                ws_fwd=torch.empty(max(workspace_bytes(p), 1), dtype=torch.uint8, device=dev),
+                ws_bwd=torch.empty(max(backward_workspace_bytes(p), 1), dtype=torch.uint8,
+                                   device=dev),
+                ws_net=torch.empty(max(int(lib().flr_net_backward_workspace_bytes(H, W)), 1),
+                                   dtype=torch.uint8, device=dev),
+                ws_l1=torch.empty(max(int(lib().flr_l1_workspace_bytes(3 * H * W)), 1),
+                                  dtype=torch.uint8, device=dev))
+            self._bufs[key] = b
+        return self._bufs[key]
+
+    def step(self, crops) -> torch.Tensor:
+        """One step on a batch: crops is a list of dicts with device tensors
+        ``guides`` [8,H,W] (or ``guides12`` [12,H,W] with the 8 guides in
+        planes 0..7; the network overwrites 8..11), ``noisy`` and ``target``
+        [3,H,W]. Returns the
+        per-crop losses (float64 device tensor; their sum is the batch mean
+        absolute error)."""
+        dev = self.params.device
+        packed = net_pack(self.params)
+        losses = torch.empty(len(crops), dtype=torch.float64, device=dev)
+        total = sum(c["noisy"].numel() for c in crops)
+        for k, c in enumerate(crops):
+            _, H, W = c["noisy"].shape
+            b = self._buffers(H, W, dev)
+            if "guides12" in c:  # the caller's 12-plane buffer, planes 0..7 filled
+                g12 = c["guides12"]
+            else:
+                g12 = b["g12"]
+                g12[:NET_IN_GUIDES].copy_(c["guides"])
+            net_forward(g12[:NET_IN_GUIDES], c["noisy"], packed, out=g12[NET_IN_GUIDES:],
+                        workspace=b["ws_net"])
+            denoise(c["noisy"], g12, self.radius, self.flr_eps, fused="two_pass", out=b["out"],
+                    workspace=b["ws_fwd"])
+            l1_loss_grad(b["out"], c["target"], 1.0 / total, grad=b["G"], loss=losses[k:k + 1],
+                         workspace=b["ws_l1"])
+            denoise_backward(c["noisy"], g12, b["G"], self.radius, self.flr_eps,
+                             workspace=b["ws_bwd"], grad_noisy=b["dy"], grad_guides=b["dg"],
+                             grad_reg=b["dreg"])
+            net_backward(g12[:NET_IN_GUIDES], c["noisy"], self.params, packed,
+                         b["dg"][NET_IN_GUIDES:], grad_params=self.grad, accumulate=k > 0,
+                         workspace=b["ws_net"])
+        self.t += 1
+        adamw_step(self.params, self.grad, self.m, self.v, self.t, self.lr, self.betas, self.eps,
+                   self.wd)
+        return losses
+
+
 __all__ = ["FLRError", "PATHS", "make_params", "num_moment_planes", "num_coeff_planes",
            "workspace_bytes", "moments", "solve", "coefficients", "apply", "denoise",
            "net_num_params", "net_pack", "net_forward", "net_backward", "flnr_workspace_bytes",
-           "flnr_denoise"]
+           "flnr_denoise", "l1_loss_grad", "adamw_step", "FLNRTrainer"]

@@ -700,7 +700,8 @@ inline void bwd_layout(const Grids& g, size_t off[B_COUNT + 1]) {
   size_t part = 0;
   for (int li = 0; li < 12; ++li) {
     const WgradPlan wp = wgrad_plan(kLayers[li], stored_cin_blocks(li), grid_px(g, kOutGrid[li]));
-    const size_t n = (size_t)wp.nchunk * ((size_t)wp.ne * kWgAcc + kLayers[li].cout);
+    const size_t S = (size_t)wp.ne * kWgAcc + kLayers[li].cout;
+    const size_t n = ((size_t)wp.nchunk + (wp.nchunk + kChunkGroup - 1) / kChunkGroup) * S;
     if (n > part) part = n;
   }
   const size_t sz[B_COUNT] = {16 * F * 2,  16 * F * 2,  4 * F * 4,   param_offset(12) * 4,
@@ -737,14 +738,20 @@ hipError_t layer_wgrad(int li, const Grids& g, const float* gout, const uint16_t
   a.ne = wp.ne;
   a.chunk_px = wp.chunk_px;
   a.part = part;
-  a.bpart = part + (size_t)wp.nchunk * wp.ne * kWgAcc;
   hipLaunchKernelGGL(wgrad_kernel, dim3(wp.nchunk, wp.wg_y), dim3(256), wgrad_lds_bytes(), s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const WreduceArgs r = {part, a.bpart, wp.nchunk, wp.ne, ncb, L.cin, L.cout, L.k,
-                         grad + param_offset(li), accumulate};
-  const int n = L.cout * L.cin * L.k * L.k + L.cout;
-  hipLaunchKernelGGL(wreduce_kernel, dim3((n + 255) / 256), dim3(256), 0, s, r);
+  // two-level fixed-order sum over the chunks: groups of kChunkGroup, then the groups
+  const int S = wp.ne * kWgAcc + L.cout;
+  const int ng = (wp.nchunk + kChunkGroup - 1) / kChunkGroup;
+  float* groups = part + (size_t)wp.nchunk * S;
+  const ChunkSumArgs c = {part, groups, S, wp.nchunk};
+  const size_t nc = (size_t)ng * S;
+  hipLaunchKernelGGL(chunk_sum_kernel, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, c);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const WreduceArgs r = {groups, ng, wp.ne, ncb, L.cin, L.cout, L.k, grad + param_offset(li),
+                         accumulate};
+  hipLaunchKernelGGL(wreduce_kernel, dim3((S + 255) / 256), dim3(256), 0, s, r);
   return hipGetLastError();
 }
 
@@ -772,7 +779,8 @@ hipError_t layer_dgrad(int li, const Grids& g, const float* gout, const uint16_t
   a.add_cs = add_cs;
   a.add_off = add_off;
   const size_t n = (size_t)Hi * Wi;
-  hipLaunchKernelGGL(dgrad_kernel, dim3((unsigned)((n + 255) / 256), L.cin / 8), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(dgrad_kernel, dim3((unsigned)((n + 255) / 256), L.cin / 8), dim3(256),
+                     dgrad_lds_bytes(L), s, a);
   return hipGetLastError();
 }
 

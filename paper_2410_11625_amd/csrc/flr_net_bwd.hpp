@@ -107,8 +107,7 @@ struct WgradArgs {
   int cout, ncb, k, stride;  // ncb: 8-channel blocks of the stored input
   int ne;                    // entries: (cout / 4) * ncb * k * k
   int chunk_px;              // output pixels per chunk (blockIdx.x)
-  float* part;               // [nchunk][ne][32]
-  float* bpart;              // [nchunk][cout]
+  float* part;               // [nchunk][ne * 32 + cout]: entries' sums, then the bias sums
 };
 
 // One wave per entry (4 output channels x 8 input channels x one tap), its 64
@@ -164,39 +163,63 @@ __global__ void __launch_bounds__(256) wgrad_kernel(WgradArgs a) {
   if (live && lane < kWgAcc + kWgOB) {
     float s = 0.f;
     for (int l = 0; l < 64; ++l) s += red[l * kRow + lane];
+    float* row = a.part + (size_t)blockIdx.x * (a.ne * kWgAcc + a.cout);
     if (lane < kWgAcc)
-      a.part[((size_t)blockIdx.x * a.ne + e) * kWgAcc + lane] = s;
+      row[e * kWgAcc + lane] = s;
     else if (with_bias)
-      a.bpart[(size_t)blockIdx.x * a.cout + ob * kWgOB + (lane - kWgAcc)] = s;
+      row[a.ne * kWgAcc + ob * kWgOB + (lane - kWgAcc)] = s;
   }
 }
 constexpr size_t wgrad_lds_bytes() { return 4 * 64 * (kWgAcc + kWgOB + 1) * sizeof(float); }
 
+// First level of the chunk sum: out[g][slot] = sum of in[ch][slot] over
+// the chunks ch of group g (kChunkGroup consecutive chunks), in order.
+constexpr int kChunkGroup = 32;
+struct ChunkSumArgs {
+  const float* in;
+  float* out;
+  int S, nchunk;
+};
+__global__ void __launch_bounds__(256) chunk_sum_kernel(ChunkSumArgs a) {
+  const int ng = (a.nchunk + kChunkGroup - 1) / kChunkGroup;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)ng * a.S) return;
+  const int g = (int)(idx / a.S), slot = (int)(idx % a.S);
+  const int c0 = g * kChunkGroup;
+  const int c1 = c0 + kChunkGroup < a.nchunk ? c0 + kChunkGroup : a.nchunk;
+  float s = 0.f;
+  for (int ch = c0; ch < c1; ++ch) s += a.in[(size_t)ch * a.S + slot];
+  a.out[idx] = s;
+}
+
 struct WreduceArgs {
-  const float* part;
-  const float* bpart;
+  const float* part;  // [nchunk][ne * 32 + cout]
   int nchunk, ne, ncb, cin, cout, k;
   float* grad;  // the layer's weights [cout][cin][k][k] then bias [cout]
   int accumulate;
 };
 
 // grad = (accumulate ? grad : 0) + the chunk partials, added in chunk order.
+// One thread per partial slot (entry e, slot j), so the chunk loop reads
+// consecutive addresses across the wave; the result goes to its weight.
 __global__ void __launch_bounds__(256) wreduce_kernel(WreduceArgs a) {
   const int kk = a.k * a.k;
-  const int nw = a.cout * a.cin * kk;
+  const int np = a.ne * kWgAcc, S = np + a.cout;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nw + a.cout) return;
-  float s = 0.f;
-  if (idx < nw) {
-    const int o = idx / (a.cin * kk), c = (idx / kk) % a.cin, tap = idx % kk;
-    const int e = ((o / kWgOB) * a.ncb + c / kWgCB) * kk + tap;
-    const int j = (o % kWgOB) * kWgCB + c % kWgCB;
-    for (int ch = 0; ch < a.nchunk; ++ch) s += a.part[((size_t)ch * a.ne + e) * kWgAcc + j];
+  if (idx >= S) return;
+  int dst;
+  if (idx < np) {
+    const int e = idx / kWgAcc, j = idx % kWgAcc;
+    const int tap = e % kk, cb = (e / kk) % a.ncb, ob = e / kk / a.ncb;
+    const int o = ob * kWgOB + j / kWgCB, c = cb * kWgCB + j % kWgCB;
+    if (c >= a.cin) return;  // padding channels of the stored input
+    dst = (o * a.cin + c) * kk + tap;
   } else {
-    const int o = idx - nw;
-    for (int ch = 0; ch < a.nchunk; ++ch) s += a.bpart[(size_t)ch * a.cout + o];
+    dst = a.cout * a.cin * kk + (idx - np);
   }
-  a.grad[idx] = a.accumulate ? a.grad[idx] + s : s;
+  float s = 0.f;
+  for (int ch = 0; ch < a.nchunk; ++ch) s += a.part[(size_t)ch * S + idx];
+  a.grad[dst] = a.accumulate ? a.grad[dst] + s : s;
 }
 
 struct DgradArgs {
@@ -210,15 +233,22 @@ struct DgradArgs {
   int add_cs, add_off;
 };
 
-// One thread per input pixel and 8 input channels (blockIdx.y picks the 8,
-// so the weight reads are uniform across the workgroup).
+// One thread per input pixel and 8 input channels (blockIdx.y picks the 8);
+// the workgroup first stages those channels' weights in LDS as [tap][o][8].
 __global__ void __launch_bounds__(256) dgrad_kernel(DgradArgs a) {
+  float* wl = flr::lds;
+  const int c0 = blockIdx.y * 8;
+  const int pd = a.k / 2, kk = a.k * a.k;
+  const int nw = kk * a.cout * 8;
+  for (int t = threadIdx.x; t < nw; t += blockDim.x) {
+    const int c = t % 8, o = (t / 8) % a.cout, tap = t / (8 * a.cout);
+    wl[t] = a.w[((size_t)o * a.cin + c0 + c) * kk + tap];
+  }
+  __syncthreads();
   const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t npx = (size_t)a.Hi * a.Wi;
   if (p >= npx) return;
-  const int c0 = blockIdx.y * 8;
   const int y = (int)(p / a.Wi), x = (int)(p % a.Wi);
-  const int pd = a.k / 2, kk = a.k * a.k;
   float acc[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) acc[c] = 0.f;
@@ -233,15 +263,22 @@ __global__ void __launch_bounds__(256) dgrad_kernel(DgradArgs a) {
       const int j = nx / a.stride;
       if (j >= a.Wo) continue;
       const size_t q = (size_t)i * a.Wo + j;
-      const int tap = u * a.k + v;
+      const float* wt = wl + (size_t)(u * a.k + v) * a.cout * 8;
       for (int o = 0; o < a.cout; o += 4) {
         const float4 d4 = load_dz4(a.g, a.act, q, a.cout, o);
         const float d[4] = {d4.x, d4.y, d4.z, d4.w};
 #pragma unroll
         for (int oo = 0; oo < 4; ++oo) {
-          const float* wo = a.w + ((size_t)(o + oo) * a.cin + c0) * kk + tap;
-#pragma unroll
-          for (int c = 0; c < 8; ++c) acc[c] += wo[(size_t)c * kk] * d[oo];
+          const float4 w0 = *reinterpret_cast<const float4*>(wt + (o + oo) * 8);
+          const float4 w1 = *reinterpret_cast<const float4*>(wt + (o + oo) * 8 + 4);
+          acc[0] += w0.x * d[oo];
+          acc[1] += w0.y * d[oo];
+          acc[2] += w0.z * d[oo];
+          acc[3] += w0.w * d[oo];
+          acc[4] += w1.x * d[oo];
+          acc[5] += w1.y * d[oo];
+          acc[6] += w1.z * d[oo];
+          acc[7] += w1.w * d[oo];
         }
       }
     }
@@ -256,6 +293,7 @@ __global__ void __launch_bounds__(256) dgrad_kernel(DgradArgs a) {
     for (int c = 0; c < 8; ++c) dst[c] = acc[c];
   }
 }
+inline size_t dgrad_lds_bytes(const Layer& L) { return (size_t)L.k * L.k * L.cout * 8 * sizeof(float); }
 
 // low[(i,j)][c] = sum of fine[(2i+di, 2j+dj)][c] over the fine pixels in the
 // H x W grid, channels c < nc of a fine tensor with channel stride cs.
@@ -280,8 +318,11 @@ __global__ void __launch_bounds__(256) up2_bwd_kernel(Up2BwdArgs a) {
   a.low[idx] = s;
 }
 
-// Chunking of a weight-gradient launch: enough workgroups to fill the chip,
-// chunks of whole waves of pixels.
+// Chunking of a weight-gradient launch: about kWgTarget workgroups (4 per
+// CU), chunks of whole waves of pixels and at least kWgMinIters pixels per
+// lane, so that the pixel loop outweighs the wave's closing LDS reduction.
+constexpr int kWgTarget = 1024;
+constexpr int kWgMinIters = 16;
 struct WgradPlan {
   int ne, wg_y, chunk_px, nchunk;
 };
@@ -290,8 +331,8 @@ inline WgradPlan wgrad_plan(const Layer& L, int ncb, size_t npx) {
   p.ne = (L.cout / kWgOB) * ncb * L.k * L.k;
   p.wg_y = (p.ne + 3) / 4;
   const size_t waves = (npx + 63) / 64;
-  size_t want = (4096 + p.wg_y - 1) / p.wg_y;
-  if (want > waves) want = waves;
+  size_t want = (kWgTarget + p.wg_y - 1) / p.wg_y;
+  if (want > (waves + kWgMinIters - 1) / kWgMinIters) want = (waves + kWgMinIters - 1) / kWgMinIters;
   if (want < 1) want = 1;
   const size_t per = (waves + want - 1) / want;
   p.chunk_px = (int)(per * 64);

@@ -157,3 +157,27 @@ def random_frame(h: int, w: int, q: int, c: int, seed: int, *, smooth: float = 0
     g = g + offset
     y = rng.exponential(1.0, size=(c, h, w)) * (1.0 + 0.5 * np.abs(g[:1]))
     return {"noisy": y.astype(np.float32), "guides": g.astype(np.float32)}
+
+
+def make_training_batch(n: int = 8, crop: int = 256, seed: int = 3, frame_h: int = 512,
+                        frame_w: int = 512, samples: int = 256):
+    """The FLNR training workload: ``n`` random crop x crop windows, one from
+    each of ``n`` frames in the style of configuration 1 (frame seeds 100,
+    101, ..., generated at frame_h x frame_w), each with a target that is the
+    mean of ``samples`` independent Exponential(1) noise draws times the clean
+    shading. That mean is drawn directly from its distribution,
+    Gamma(samples, 1 / samples). Returns a list of dicts with ``guides``
+    [8,crop,crop], ``noisy`` and ``target`` [3,crop,crop] (float32)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        fr = make_frame(frame_h, frame_w, 100 + k, rgb=True, fireflies=True)
+        y0 = int(rng.integers(0, frame_h - crop + 1))
+        x0 = int(rng.integers(0, frame_w - crop + 1))
+        sl = (slice(None), slice(y0, y0 + crop), slice(x0, x0 + crop))
+        clean = fr["clean"][sl]
+        target = clean * rng.gamma(samples, 1.0 / samples, size=clean.shape)
+        out.append({"guides": np.ascontiguousarray(fr["guides"][sl]),
+                    "noisy": np.ascontiguousarray(fr["noisy"][sl]),
+                    "target": np.ascontiguousarray(target, dtype=np.float32)})
+    return out

@@ -74,6 +74,25 @@ def test_net_entry_points_validate_before_launch(L):
     assert nb(8, 8, a16, a16, a16, a16, a16, a16, 0, a16, need, None) == 6   # FLR_ERR_ALIAS
 
 
+def test_train_entry_points_validate_before_launch(L):
+    buf = ctypes.create_string_buffer(64)
+    a16 = ctypes.addressof(buf) + (-ctypes.addressof(buf)) % 16
+    assert L.flr_l1_workspace_bytes(0) == 0 and L.flr_l1_workspace_bytes(1 << 35) == 0
+    assert L.flr_l1_workspace_bytes(1000) >= 8
+    l1 = L.flr_l1_loss_grad
+    assert l1(0, a16, a16, 1.0, a16, a16, a16, 64, None) == 2                 # FLR_ERR_SHAPE
+    assert l1(4, None, a16, 1.0, a16, a16, a16, 64, None) == 1                # FLR_ERR_NULL
+    assert l1(4, a16, a16, float("nan"), a16, a16, a16, 64, None) == 4        # FLR_ERR_EPS
+    assert l1(4, a16, a16, 1.0, a16, a16, a16, 0, None) == 8                  # FLR_ERR_WORKSPACE
+    assert l1(4, a16, a16, 1.0, a16, a16, a16, 64, None) == 6                 # FLR_ERR_ALIAS
+    ad = L.flr_adamw_step
+    assert ad(4, a16, a16, a16, a16, 0, 1e-3, 0.9, 0.999, 1e-8, 0.0, None) == 9    # MODE (step)
+    assert ad(4, a16, a16, a16, a16, 1, -1e-3, 0.9, 0.999, 1e-8, 0.0, None) == 4   # EPS (lr)
+    assert ad(4, a16, a16, a16, a16, 1, 1e-3, 1.0, 0.999, 1e-8, 0.0, None) == 4    # EPS (beta)
+    assert ad(4, a16 + 4, a16, a16, a16, 1, 1e-3, 0.9, 0.999, 1e-8, 0.0, None) == 7  # ALIGN
+    assert ad(4, a16, a16, a16, a16, 1, 1e-3, 0.9, 0.999, 1e-8, 0.0, None) == 6    # ALIAS
+
+
 def test_params_struct_layout_matches_header():
     # 12 four-byte fields, no padding
     assert ctypes.sizeof(FlrParams) == 48

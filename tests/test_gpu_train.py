@@ -1,0 +1,109 @@
+"""GPU tests of the FLNR training step (include/flr_train.h, FLNRTrainer).
+
+* flr_l1_loss_grad against the oracle on the same FP32 values: the gradient
+  bit for bit (scale times the sign of the same FP32 difference), the FP64
+  loss within 1e-12 (summation order).
+* flr_adamw_step against the FP64 AdamW oracle (pinned to the library
+  optimizer) over three steps on the same FP32 gradients: FP32 arithmetic,
+  so within 1e-6 of the largest parameter.
+* A trainer step equals its parts (network, FLR, L1, FLR adjoint, network
+  backward, AdamW) called one by one through the binding, bit for bit.
+* Training works: on a fixed batch of the training workload the loss falls.
+The parts' own parity is tested in test_gpu_net.py, test_gpu_adjoint.py and
+test_gpu_net_backward.py. The full step is not compared end to end with the
+oracle: the L1 gradient takes a sign of out - target, a decision that a
+rounding-level difference of the 12-guide regression flips.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2410_11625_amd as flr  # noqa: E402
+from oracle import train_ref  # noqa: E402
+from synth import make_training_batch  # noqa: E402
+from synth.net_weights import flatten_net_weights, make_net_weights  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(_dev())
+
+
+@pytest.mark.parametrize("n", [1, 7, 3 * 97 * 131, 3 * 256 * 256])
+def test_l1_loss_grad_matches_oracle(n):
+    rng = np.random.default_rng(n)
+    out = rng.standard_normal(n).astype(np.float32)
+    target = out.copy()
+    target[::3] = rng.standard_normal(target[::3].shape).astype(np.float32)  # ties elsewhere
+    scale = 1.0 / n
+    g, loss = flr.l1_loss_grad(_t(out), _t(target), scale)
+    want_loss, want_g = train_ref.l1_loss_grad(out, target, float(np.float32(scale)))
+    assert np.array_equal(g.cpu().numpy(), want_g.astype(np.float32))
+    assert abs(loss.item() - want_loss) <= 1e-12 * max(abs(want_loss), 1e-300)
+
+
+def test_adamw_matches_oracle():
+    n = 5003
+    rng = np.random.default_rng(0)
+    p0 = rng.standard_normal(n).astype(np.float32)
+    p, m, v = _t(p0), _t(np.zeros(n)), _t(np.zeros(n))
+    rp, rm, rv = p0.astype(np.float64), np.zeros(n), np.zeros(n)
+    lr, wd, betas, eps = 1e-2, 0.05, (0.9, 0.999), 1e-8
+    f32 = lambda x: float(np.float32(x))  # noqa: E731  (the ABI carries FP32)
+    for t in range(1, 4):
+        g = (rng.standard_normal(n) * t).astype(np.float32)
+        flr.adamw_step(p, _t(g), m, v, t, lr, betas, eps, wd)
+        rp, rm, rv = train_ref.adamw_step(rp, g, rm, rv, t, f32(lr), f32(betas[0]),
+                                          f32(betas[1]), f32(eps), f32(wd))
+    got = p.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(got - rp)) <= 1e-6 * np.max(np.abs(rp))
+
+
+def _crops(n=2, crop=48):
+    return [{k: _t(v) for k, v in c.items()}
+            for c in make_training_batch(n=n, crop=crop, frame_h=96, frame_w=128)]
+
+
+def test_trainer_step_equals_its_parts():
+    crops = _crops()
+    p0 = _t(flatten_net_weights(make_net_weights(2)))
+    tr = flr.FLNRTrainer(p0.clone(), lr=1e-3, weight_decay=0.01)
+    losses = tr.step(crops)
+    # the same step, part by part
+    p = p0.clone()
+    packed = flr.net_pack(p)
+    grad = torch.zeros_like(p)
+    total = sum(c["noisy"].numel() for c in crops)
+    want_losses = []
+    for k, c in enumerate(crops):
+        g12 = torch.empty((12,) + tuple(c["noisy"].shape[1:]), device=p.device)
+        g12[:8].copy_(c["guides"])
+        flr.net_forward(g12[:8], c["noisy"], packed, out=g12[8:])
+        out = flr.denoise(c["noisy"], g12, 8, 1e-3, fused="two_pass")
+        G, loss = flr.l1_loss_grad(out, c["target"], 1.0 / total)
+        want_losses.append(loss)
+        _, dg, _ = flr.denoise_backward(c["noisy"], g12, G, 8, 1e-3)
+        flr.net_backward(g12[:8], c["noisy"], p, packed, dg[8:].contiguous(), grad_params=grad,
+                         accumulate=k > 0)
+    flr.adamw_step(p, grad, torch.zeros_like(p), torch.zeros_like(p), 1, 1e-3,
+                   weight_decay=0.01)
+    assert torch.equal(losses, torch.cat(want_losses))
+    assert torch.equal(tr.grad, grad)
+    assert torch.equal(tr.params, p)
+
+
+def test_training_reduces_the_loss():
+    crops = _crops(n=2, crop=64)
+    tr = flr.FLNRTrainer(_t(flatten_net_weights(make_net_weights(2))), lr=2e-3)
+    first = tr.step(crops).sum().item()
+    for _ in range(14):
+        last = tr.step(crops).sum().item()
+    assert np.isfinite(last) and last < first, (first, last)
