@@ -738,7 +738,12 @@ hipError_t layer_wgrad(int li, const Grids& g, const float* gout, const uint16_t
   a.ne = wp.ne;
   a.chunk_px = wp.chunk_px;
   a.part = part;
-  hipLaunchKernelGGL(wgrad_kernel, dim3(wp.nchunk, wp.wg_y), dim3(256), wgrad_lds_bytes(), s, a);
+  if (L.k == 3)
+    hipLaunchKernelGGL(wgrad_kernel<3>, dim3(wp.nchunk, wp.wg_y), dim3(256), wgrad_lds_bytes(), s,
+                       a);
+  else
+    hipLaunchKernelGGL(wgrad_kernel<1>, dim3(wp.nchunk, wp.wg_y), dim3(256), wgrad_lds_bytes(), s,
+                       a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // two-level fixed-order sum over the chunks: groups of kChunkGroup, then the groups

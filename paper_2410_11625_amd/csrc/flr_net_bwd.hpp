@@ -110,23 +110,30 @@ struct WgradArgs {
   float* part;               // [nchunk][ne * 32 + cout]: entries' sums, then the bias sums
 };
 
-// One wave per entry (4 output channels x 8 input channels x one tap), its 64
-// lanes striding over the chunk's output pixels; the lanes' sums are added in
-// LDS in lane order.
+// One wave per row of KW taps (kernel row u) of 4 output channels x 8 input
+// channels: entries e0 .. e0 + KW - 1 with e0 = ((ob ncb + cb) k + u) k.
+// The 64 lanes stride over a chunk of output pixels, loading dz once for the
+// row's taps; the lanes' sums are added in LDS in lane order, one tap at a
+// time.
+template <int KW>
 __global__ void __launch_bounds__(256) wgrad_kernel(WgradArgs a) {
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int e = blockIdx.y * 4 + wave;
-  const bool live = e < a.ne;
-  const int kk = a.k * a.k;
-  const int tap = live ? e % kk : 0;
-  const int cb = live ? (e / kk) % a.ncb : 0;
-  const int ob = live ? e / kk / a.ncb : 0;
-  const int u = tap / a.k, v = tap % a.k, pd = a.k / 2;
-  const bool with_bias = live && cb == 0 && tap == 0;
-  float acc[kWgAcc];
+  const int kk = KW * KW;
+  const int nrow = a.ne / KW;
+  const int w = blockIdx.y * 4 + wave;
+  const bool live = w < nrow;
+  const int u = live ? w % KW : 0;
+  const int cb = live ? (w / KW) % a.ncb : 0;
+  const int ob = live ? w / KW / a.ncb : 0;
+  const int e0 = ((ob * a.ncb + cb) * KW + u) * KW;
+  const int pd = KW / 2;
+  const bool with_bias = live && cb == 0 && u == 0;
+  float acc[KW][kWgAcc];
   float bacc[kWgOB];
 #pragma unroll
-  for (int i = 0; i < kWgAcc; ++i) acc[i] = 0.f;
+  for (int v = 0; v < KW; ++v)
+#pragma unroll
+    for (int i = 0; i < kWgAcc; ++i) acc[v][i] = 0.f;
 #pragma unroll
   for (int i = 0; i < kWgOB; ++i) bacc[i] = 0.f;
   const size_t npx = (size_t)a.Ho * a.Wo;
@@ -135,39 +142,50 @@ __global__ void __launch_bounds__(256) wgrad_kernel(WgradArgs a) {
   if (live) {
     for (size_t q = q0 + lane; q < q1; q += 64) {
       const int i = (int)(q / a.Wo), j = (int)(q % a.Wo);
-      const int yi = a.stride * i + u - pd, xi = a.stride * j + v - pd;
-      const bool ok = yi >= 0 && yi < a.Hi && xi >= 0 && xi < a.Wi;
+      const int yi = a.stride * i + u - pd;
+      const bool oky = yi >= 0 && yi < a.Hi;
       const int yc = yi < 0 ? 0 : (yi >= a.Hi ? a.Hi - 1 : yi);
-      const int xc = xi < 0 ? 0 : (xi >= a.Wi ? a.Wi - 1 : xi);
-      float x[kWgCB];
-      load_x8(a.src, a.Wi, yc, xc, cb * kWgCB, x);
+      float x[KW][kWgCB];
+#pragma unroll
+      for (int v = 0; v < KW; ++v) {
+        const int xi = a.stride * j + v - pd;
+        const bool ok = oky && xi >= 0 && xi < a.Wi;
+        const int xc = xi < 0 ? 0 : (xi >= a.Wi ? a.Wi - 1 : xi);
+        load_x8(a.src, a.Wi, yc, xc, cb * kWgCB, x[v]);
+#pragma unroll
+        for (int c = 0; c < kWgCB; ++c) x[v][c] = ok ? x[v][c] : 0.f;
+      }
       const float4 d4 = load_dz4(a.g, a.act, q, a.cout, ob * kWgOB);
       const float d[kWgOB] = {d4.x, d4.y, d4.z, d4.w};
-#pragma unroll
-      for (int c = 0; c < kWgCB; ++c) x[c] = ok ? x[c] : 0.f;
 #pragma unroll
       for (int o = 0; o < kWgOB; ++o) {
         bacc[o] += d[o];
 #pragma unroll
-        for (int c = 0; c < kWgCB; ++c) acc[o * kWgCB + c] += d[o] * x[c];
+        for (int v = 0; v < KW; ++v)
+#pragma unroll
+          for (int c = 0; c < kWgCB; ++c) acc[v][o * kWgCB + c] += d[o] * x[v][c];
       }
     }
   }
   constexpr int kRow = kWgAcc + kWgOB + 1;  // + 1: staggers the LDS banks
   float* red = flr::lds + wave * 64 * kRow;
+  float* row = a.part + (size_t)blockIdx.x * (a.ne * kWgAcc + a.cout);
 #pragma unroll
-  for (int i = 0; i < kWgAcc; ++i) red[lane * kRow + i] = acc[i];
+  for (int v = 0; v < KW; ++v) {
+    if (v > 0) __syncthreads();  // the previous tap's sums have been read
 #pragma unroll
-  for (int i = 0; i < kWgOB; ++i) red[lane * kRow + kWgAcc + i] = bacc[i];
-  __syncthreads();
-  if (live && lane < kWgAcc + kWgOB) {
-    float s = 0.f;
-    for (int l = 0; l < 64; ++l) s += red[l * kRow + lane];
-    float* row = a.part + (size_t)blockIdx.x * (a.ne * kWgAcc + a.cout);
-    if (lane < kWgAcc)
-      row[e * kWgAcc + lane] = s;
-    else if (with_bias)
-      row[a.ne * kWgAcc + ob * kWgOB + (lane - kWgAcc)] = s;
+    for (int i = 0; i < kWgAcc; ++i) red[lane * kRow + i] = acc[v][i];
+#pragma unroll
+    for (int i = 0; i < kWgOB; ++i) red[lane * kRow + kWgAcc + i] = bacc[i];
+    __syncthreads();
+    if (live && lane < kWgAcc + kWgOB) {
+      float s = 0.f;
+      for (int l = 0; l < 64; ++l) s += red[l * kRow + lane];
+      if (lane < kWgAcc)
+        row[(e0 + v) * kWgAcc + lane] = s;
+      else if (with_bias && v == 0)
+        row[a.ne * kWgAcc + ob * kWgOB + (lane - kWgAcc)] = s;
+    }
   }
 }
 constexpr size_t wgrad_lds_bytes() { return 4 * 64 * (kWgAcc + kWgOB + 1) * sizeof(float); }
@@ -321,7 +339,7 @@ __global__ void __launch_bounds__(256) up2_bwd_kernel(Up2BwdArgs a) {
 // Chunking of a weight-gradient launch: about kWgTarget workgroups (4 per
 // CU), chunks of whole waves of pixels and at least kWgMinIters pixels per
 // lane, so that the pixel loop outweighs the wave's closing LDS reduction.
-constexpr int kWgTarget = 1024;
+constexpr int kWgTarget = 2048;
 constexpr int kWgMinIters = 16;
 struct WgradPlan {
   int ne, wg_y, chunk_px, nchunk;
@@ -329,7 +347,7 @@ struct WgradPlan {
 inline WgradPlan wgrad_plan(const Layer& L, int ncb, size_t npx) {
   WgradPlan p;
   p.ne = (L.cout / kWgOB) * ncb * L.k * L.k;
-  p.wg_y = (p.ne + 3) / 4;
+  p.wg_y = (p.ne / L.k + 3) / 4;  // one wave per row of L.k taps
   const size_t waves = (npx + 63) / 64;
   size_t want = (kWgTarget + p.wg_y - 1) / p.wg_y;
   if (want > (waves + kWgMinIters - 1) / kWgMinIters) want = (waves + kWgMinIters - 1) / kWgMinIters;
