@@ -766,6 +766,9 @@ hipError_t layer_dgrad(int li, const Grids& g, const float* gout, const uint16_t
                        const float* wr, int Hi, int Wi, float* dx, const float* add, int add_cs,
                        int add_off, hipStream_t s) {
   const Layer& L = kLayers[li];
+  const size_t n = (size_t)Hi * Wi;
+  const int cpt = n >= kDgWidePx ? 16 : 8;
+  if (L.cin % cpt) return hipErrorInvalidValue;  // whole channel groups per thread
   const int og = kOutGrid[li];
   DgradArgs a = {};
   a.g = gout;
@@ -783,9 +786,12 @@ hipError_t layer_dgrad(int li, const Grids& g, const float* gout, const uint16_t
   a.add = add;
   a.add_cs = add_cs;
   a.add_off = add_off;
-  const size_t n = (size_t)Hi * Wi;
-  hipLaunchKernelGGL(dgrad_kernel, dim3((unsigned)((n + 255) / 256), L.cin / 8), dim3(256),
-                     dgrad_lds_bytes(L), s, a);
+  if (cpt == 16)
+    hipLaunchKernelGGL(dgrad_kernel<16>, dim3((unsigned)((n + 255) / 256), L.cin / 16), dim3(256),
+                       dgrad_lds_bytes(L, 16), s, a);
+  else
+    hipLaunchKernelGGL(dgrad_kernel<8>, dim3((unsigned)((n + 255) / 256), L.cin / 8), dim3(256),
+                       dgrad_lds_bytes(L, 8), s, a);
   return hipGetLastError();
 }
 

@@ -251,15 +251,18 @@ struct DgradArgs {
   int add_cs, add_off;
 };
 
-// One thread per input pixel and 8 input channels (blockIdx.y picks the 8);
-// the workgroup first stages those channels' weights in LDS as [tap][o][8].
+// One thread per input pixel and kDgC input channels (blockIdx.y picks
+// them); the workgroup first stages those channels' weights in LDS as
+// [tap][o][kDgC]. 16 channels halve the dz loads per multiply-add; 8 give
+// twice the workgroups, which small frames need to fill the chip.
+template <int kDgC>
 __global__ void __launch_bounds__(256) dgrad_kernel(DgradArgs a) {
   float* wl = flr::lds;
-  const int c0 = blockIdx.y * 8;
+  const int c0 = blockIdx.y * kDgC;
   const int pd = a.k / 2, kk = a.k * a.k;
-  const int nw = kk * a.cout * 8;
+  const int nw = kk * a.cout * kDgC;
   for (int t = threadIdx.x; t < nw; t += blockDim.x) {
-    const int c = t % 8, o = (t / 8) % a.cout, tap = t / (8 * a.cout);
+    const int c = t % kDgC, o = (t / kDgC) % a.cout, tap = t / (kDgC * a.cout);
     wl[t] = a.w[((size_t)o * a.cin + c0 + c) * kk + tap];
   }
   __syncthreads();
@@ -267,9 +270,9 @@ __global__ void __launch_bounds__(256) dgrad_kernel(DgradArgs a) {
   const size_t npx = (size_t)a.Hi * a.Wi;
   if (p >= npx) return;
   const int y = (int)(p / a.Wi), x = (int)(p % a.Wi);
-  float acc[8];
+  float acc[kDgC];
 #pragma unroll
-  for (int c = 0; c < 8; ++c) acc[c] = 0.f;
+  for (int c = 0; c < kDgC; ++c) acc[c] = 0.f;
   for (int u = 0; u < a.k; ++u) {
     const int ny = y + pd - u;
     if (ny < 0 || ny % a.stride) continue;
@@ -281,22 +284,20 @@ __global__ void __launch_bounds__(256) dgrad_kernel(DgradArgs a) {
       const int j = nx / a.stride;
       if (j >= a.Wo) continue;
       const size_t q = (size_t)i * a.Wo + j;
-      const float* wt = wl + (size_t)(u * a.k + v) * a.cout * 8;
+      const float* wt = wl + (size_t)(u * a.k + v) * a.cout * kDgC;
       for (int o = 0; o < a.cout; o += 4) {
         const float4 d4 = load_dz4(a.g, a.act, q, a.cout, o);
         const float d[4] = {d4.x, d4.y, d4.z, d4.w};
 #pragma unroll
         for (int oo = 0; oo < 4; ++oo) {
-          const float4 w0 = *reinterpret_cast<const float4*>(wt + (o + oo) * 8);
-          const float4 w1 = *reinterpret_cast<const float4*>(wt + (o + oo) * 8 + 4);
-          acc[0] += w0.x * d[oo];
-          acc[1] += w0.y * d[oo];
-          acc[2] += w0.z * d[oo];
-          acc[3] += w0.w * d[oo];
-          acc[4] += w1.x * d[oo];
-          acc[5] += w1.y * d[oo];
-          acc[6] += w1.z * d[oo];
-          acc[7] += w1.w * d[oo];
+#pragma unroll
+          for (int c4 = 0; c4 < kDgC; c4 += 4) {
+            const float4 w4 = *reinterpret_cast<const float4*>(wt + (o + oo) * kDgC + c4);
+            acc[c4 + 0] += w4.x * d[oo];
+            acc[c4 + 1] += w4.y * d[oo];
+            acc[c4 + 2] += w4.z * d[oo];
+            acc[c4 + 3] += w4.w * d[oo];
+          }
         }
       }
     }
@@ -305,13 +306,16 @@ __global__ void __launch_bounds__(256) dgrad_kernel(DgradArgs a) {
   if (a.add) {
     const float* ad = a.add + p * a.add_cs + a.add_off + c0;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) dst[c] = acc[c] + ad[c];
+    for (int c = 0; c < kDgC; ++c) dst[c] = acc[c] + ad[c];
   } else {
 #pragma unroll
-    for (int c = 0; c < 8; ++c) dst[c] = acc[c];
+    for (int c = 0; c < kDgC; ++c) dst[c] = acc[c];
   }
 }
-inline size_t dgrad_lds_bytes(const Layer& L) { return (size_t)L.k * L.k * L.cout * 8 * sizeof(float); }
+inline size_t dgrad_lds_bytes(const Layer& L, int cpt) {
+  return (size_t)L.k * L.k * L.cout * cpt * sizeof(float);
+}
+constexpr size_t kDgWidePx = (size_t)1 << 18;  // grids from 2^18 pixels take 16 channels
 
 // low[(i,j)][c] = sum of fine[(2i+di, 2j+dj)][c] over the fine pixels in the
 // H x W grid, channels c < nc of a fine tensor with channel stride cs.
