@@ -538,6 +538,29 @@ class FLNRTrainer:
         self.radius, self.flr_eps = radius, flr_eps
         self._bufs = {}
 
+    def state_dict(self) -> dict:
+        """Checkpoint: the FP32 master weights, the AdamW moments and step
+        count, and the hyperparameters (tensors copied to the host)."""
+        return {"params": self.params.detach().cpu().clone(), "m": self.m.cpu().clone(),
+                "v": self.v.cpu().clone(), "step": int(self.t), "lr": self.lr,
+                "betas": tuple(self.betas), "eps": self.eps, "weight_decay": self.wd,
+                "radius": self.radius, "flr_eps": self.flr_eps}
+
+    def load_state_dict(self, state: dict) -> None:
+        """Resume from state_dict(): the next step equals the one the saved
+        trainer would have taken."""
+        for k in ("params", "m", "v"):
+            if state[k].numel() != self.params.numel():
+                raise ValueError(f"checkpoint {k} has {state[k].numel()} elements, "
+                                 f"expected {self.params.numel()}")
+        self.params.copy_(state["params"])
+        self.m.copy_(state["m"])
+        self.v.copy_(state["v"])
+        self.t = int(state["step"])
+        self.lr, self.betas, self.eps, self.wd = (state["lr"], tuple(state["betas"]),
+                                                  state["eps"], state["weight_decay"])
+        self.radius, self.flr_eps = state["radius"], state["flr_eps"]
+
     def _buffers(self, H, W, dev):
         key = (H, W)
         if key not in self._bufs:

@@ -9,6 +9,8 @@
 * A trainer step equals its parts (network, FLR, L1, FLR adjoint, network
   backward, AdamW) called one by one through the binding, bit for bit.
 * Training works: on a fixed batch of the training workload the loss falls.
+* A checkpoint (state_dict through a safetensors file) resumes the run: the
+  resumed trainer's next step equals the uninterrupted one, bit for bit.
 The parts' own parity is tested in test_gpu_net.py, test_gpu_adjoint.py and
 test_gpu_net_backward.py. The full step is not compared end to end with the
 oracle: the L1 gradient takes a sign of out - target, a decision that a
@@ -107,3 +109,21 @@ def test_training_reduces_the_loss():
     for _ in range(14):
         last = tr.step(crops).sum().item()
     assert np.isfinite(last) and last < first, (first, last)
+
+
+def test_checkpoint_resume(tmp_path):
+    from safetensors.torch import load_file, save_file
+    crops = _crops(n=2, crop=48)
+    p0 = _t(flatten_net_weights(make_net_weights(2)))
+    a = flr.FLNRTrainer(p0.clone(), lr=1e-3)
+    a.step(crops)
+    a.step(crops)
+    st = a.state_dict()
+    f = tmp_path / "ckpt.safetensors"
+    save_file({k: st[k] for k in ("params", "m", "v")}, str(f))
+    meta = {k: v for k, v in st.items() if k not in ("params", "m", "v")}
+    b = flr.FLNRTrainer(torch.zeros_like(p0), lr=0.5)
+    b.load_state_dict({**load_file(str(f)), **meta})
+    la = a.step(crops)
+    lb = b.step(crops)
+    assert torch.equal(la, lb) and torch.equal(a.params, b.params) and b.t == a.t == 3
