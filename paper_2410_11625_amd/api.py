@@ -8,6 +8,7 @@ Shapes: ``guides`` [Q,H,W] (without the implied constant guide), ``noisy``
 from __future__ import annotations
 
 import ctypes
+import math
 
 import torch
 
@@ -525,7 +526,7 @@ class FLNRTrainer:
 
     def __init__(self, params: torch.Tensor, lr: float = 1e-3, betas=(0.9, 0.999),
                  eps: float = 1e-8, weight_decay: float = 0.0, radius: int = 8,
-                 flr_eps: float = 1e-3):
+                 flr_eps: float = 1e-3, learn_eps: bool = False, eps_lr: float = 1e-2):
         _need(params, "params", ndim=1)
         if params.numel() != net_num_params():
             raise ValueError(f"expected {net_num_params()} parameters")
@@ -536,6 +537,13 @@ class FLNRTrainer:
         self.t = 0
         self.lr, self.betas, self.eps, self.wd = lr, betas, eps, weight_decay
         self.radius, self.flr_eps = radius, flr_eps
+        # learn_eps: FLR's regulariser learned with the network (the paper
+        # learns its regularisers by backpropagation), by Adam on log(eps)
+        # from the adjoint's dL/d(eps) summed over the batch; one host read
+        # per step
+        self.learn_eps, self.eps_lr = learn_eps, eps_lr
+        self.eps_m = self.eps_v = 0.0
+        self.last_deps = None
         self._bufs = {}
 
     def state_dict(self) -> dict:
@@ -544,7 +552,8 @@ class FLNRTrainer:
         return {"params": self.params.detach().cpu().clone(), "m": self.m.cpu().clone(),
                 "v": self.v.cpu().clone(), "step": int(self.t), "lr": self.lr,
                 "betas": tuple(self.betas), "eps": self.eps, "weight_decay": self.wd,
-                "radius": self.radius, "flr_eps": self.flr_eps}
+                "radius": self.radius, "flr_eps": self.flr_eps, "learn_eps": self.learn_eps,
+                "eps_lr": self.eps_lr, "eps_m": self.eps_m, "eps_v": self.eps_v}
 
     def load_state_dict(self, state: dict) -> None:
         """Resume from state_dict(): the next step equals the one the saved
@@ -560,6 +569,9 @@ class FLNRTrainer:
         self.lr, self.betas, self.eps, self.wd = (state["lr"], tuple(state["betas"]),
                                                   state["eps"], state["weight_decay"])
         self.radius, self.flr_eps = state["radius"], state["flr_eps"]
+        self.learn_eps = state.get("learn_eps", False)
+        self.eps_lr = state.get("eps_lr", self.eps_lr)
+        self.eps_m, self.eps_v = state.get("eps_m", 0.0), state.get("eps_v", 0.0)
 
     def _buffers(self, H, W, dev):
         key = (H, W)
@@ -571,7 +583,6 @@ class FLNRTrainer:
                 G=torch.empty((3, H, W), dtype=torch.float32, device=dev),
                 dy=torch.empty((3, H, W), dtype=torch.float32, device=dev),
                 dg=torch.empty((12, H, W), dtype=torch.float32, device=dev),
-                dreg=torch.empty(2, dtype=torch.float64, device=dev),
                 ws_fwd=torch.empty(max(workspace_bytes(p), 1), dtype=torch.uint8, device=dev),
                 ws_bwd=torch.empty(max(backward_workspace_bytes(p), 1), dtype=torch.uint8,
                                    device=dev),
@@ -592,6 +603,7 @@ class FLNRTrainer:
         dev = self.params.device
         packed = net_pack(self.params)
         losses = torch.empty(len(crops), dtype=torch.float64, device=dev)
+        dregs = torch.empty((len(crops), 2), dtype=torch.float64, device=dev)
         total = sum(c["noisy"].numel() for c in crops)
         for k, c in enumerate(crops):
             _, H, W = c["noisy"].shape
@@ -609,13 +621,23 @@ class FLNRTrainer:
                          workspace=b["ws_l1"])
             denoise_backward(c["noisy"], g12, b["G"], self.radius, self.flr_eps,
                              workspace=b["ws_bwd"], grad_noisy=b["dy"], grad_guides=b["dg"],
-                             grad_reg=b["dreg"])
+                             grad_reg=dregs[k])
             net_backward(g12[:NET_IN_GUIDES], c["noisy"], self.params, packed,
                          b["dg"][NET_IN_GUIDES:], grad_params=self.grad, accumulate=k > 0,
                          workspace=b["ws_net"])
         self.t += 1
         adamw_step(self.params, self.grad, self.m, self.v, self.t, self.lr, self.betas, self.eps,
                    self.wd)
+        if self.learn_eps:
+            deps = float(dregs[:, 0].sum().item())
+            self.last_deps = deps
+            g = deps * self.flr_eps  # d loss / d log(eps)
+            b1, b2 = self.betas
+            self.eps_m = b1 * self.eps_m + (1 - b1) * g
+            self.eps_v = b2 * self.eps_v + (1 - b2) * g * g
+            mh = self.eps_m / (1 - b1 ** self.t)
+            vh = self.eps_v / (1 - b2 ** self.t)
+            self.flr_eps = float(self.flr_eps * math.exp(-self.eps_lr * mh / (math.sqrt(vh) + 1e-12)))
         return losses
 
 

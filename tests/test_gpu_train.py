@@ -74,32 +74,51 @@ def _crops(n=2, crop=48):
             for c in make_training_batch(n=n, crop=crop, frame_h=96, frame_w=128)]
 
 
-def test_trainer_step_equals_its_parts():
-    crops = _crops()
-    p0 = _t(flatten_net_weights(make_net_weights(2)))
-    tr = flr.FLNRTrainer(p0.clone(), lr=1e-3, weight_decay=0.01)
-    losses = tr.step(crops)
-    # the same step, part by part
-    p = p0.clone()
+def _parts(crops, p):
+    """One step's losses, gradient and summed dL/d(eps), part by part."""
     packed = flr.net_pack(p)
     grad = torch.zeros_like(p)
     total = sum(c["noisy"].numel() for c in crops)
-    want_losses = []
+    losses, deps = [], 0.0
     for k, c in enumerate(crops):
         g12 = torch.empty((12,) + tuple(c["noisy"].shape[1:]), device=p.device)
         g12[:8].copy_(c["guides"])
         flr.net_forward(g12[:8], c["noisy"], packed, out=g12[8:])
         out = flr.denoise(c["noisy"], g12, 8, 1e-3, fused="two_pass")
         G, loss = flr.l1_loss_grad(out, c["target"], 1.0 / total)
-        want_losses.append(loss)
-        _, dg, _ = flr.denoise_backward(c["noisy"], g12, G, 8, 1e-3)
+        losses.append(loss)
+        _, dg, dreg = flr.denoise_backward(c["noisy"], g12, G, 8, 1e-3)
+        deps += float(dreg[0].item())
         flr.net_backward(g12[:8], c["noisy"], p, packed, dg[8:].contiguous(), grad_params=grad,
                          accumulate=k > 0)
+    return torch.cat(losses), grad, deps
+
+
+def test_trainer_step_equals_its_parts():
+    crops = _crops()
+    p0 = _t(flatten_net_weights(make_net_weights(2)))
+    tr = flr.FLNRTrainer(p0.clone(), lr=1e-3, weight_decay=0.01)
+    losses = tr.step(crops)
+    p = p0.clone()
+    want_losses, grad, _ = _parts(crops, p)
     flr.adamw_step(p, grad, torch.zeros_like(p), torch.zeros_like(p), 1, 1e-3,
                    weight_decay=0.01)
-    assert torch.equal(losses, torch.cat(want_losses))
+    assert torch.equal(losses, want_losses)
     assert torch.equal(tr.grad, grad)
     assert torch.equal(tr.params, p)
+
+
+def test_trainer_learns_eps():
+    """learn_eps: the step's dL/d(eps) is the crops' adjoint sums, and Adam's
+    first step on log(eps) moves it by eps_lr against that gradient's sign."""
+    crops = _crops()
+    p0 = _t(flatten_net_weights(make_net_weights(2)))
+    tr = flr.FLNRTrainer(p0.clone(), learn_eps=True, eps_lr=0.1)
+    tr.step(crops)
+    _, _, deps = _parts(crops, p0.clone())
+    assert deps != 0.0
+    assert abs(tr.last_deps - deps) <= 1e-12 * abs(deps)
+    assert abs(np.log(tr.flr_eps / 1e-3) + 0.1 * np.sign(deps)) <= 1e-6
 
 
 def test_training_reduces_the_loss():
