@@ -37,30 +37,40 @@ COPY_BYTES = 1 << 30         # calibration copy: 1 GiB read + 1 GiB written
 
 
 def flops_terms(Q: int, C: int) -> dict:
-    """Algorithmic flops per output pixel (FMA = 2) of each step, excluding
-    halo recomputation. Mirrors the derivation in the design notes."""
+    """Algorithmic flops per output pixel (FMA = 2) of each step, the
+    hot-path scope's count: products Q(Q+1)/2 + QC; sliding box 4 per summed
+    channel (M - 1 of them, M the moment planes with the count); centring
+    3 per product channel; Cholesky Q^3/3; the two triangular solves 2 Q^2 C;
+    the intercepts 2QC; the coefficient average 5 per coefficient plane (FC);
+    the reconstruction 2QC. Halo recomputation is not counted."""
     NP = Q * (Q + 1) // 2
-    NS = Q + C + NP + Q * C
+    NS = Q + C + NP + Q * C          # M - 1
     FC = (Q + 1) * C
     return {
-        "moments": 4 * (NP + Q * C) + 2 * (Q + C) + 2 * NS,   # vertical and horizontal slides
-        "centre": (Q + C) + 3 * (NP + Q * C),
-        "regularise": Q,
-        "cholesky": 2 * sum(j * (Q - j) for j in range(Q)) + Q * (Q - 1) // 2 + Q,
-        "substitution": 2 * (2 * (Q * (Q - 1) // 2) * C) + 2 * Q * C,
+        "products": NP + Q * C,
+        "box": 4 * NS,
+        "centre": 3 * (NP + Q * C),
+        "cholesky": Q ** 3 / 3,
+        "substitution": 2 * Q * Q * C,
         "intercept": 2 * Q * C,
-        "average": 4 * FC + C,
-        "reconstruct": 2 * Q * C + C,
+        "average": 5 * FC,
+        "reconstruct": 2 * Q * C,
     }
 
 
-def algo_flops_per_px(Q: int, C: int, part: str = "all") -> int:
+def algo_flops_per_px(Q: int, C: int, part: str = "all") -> float:
     t = flops_terms(Q, C)
     if part == "coefficients":
         return sum(v for k, v in t.items() if k not in ("average", "reconstruct"))
     if part == "apply":
         return t["average"] + t["reconstruct"]
     return sum(t.values())
+
+
+def algo_hbm_bytes_per_px(Q: int, C: int) -> int:
+    """Algorithmic HBM bytes per pixel of the whole path: the guides and the
+    noisy channels read once, the output written once (FP32)."""
+    return 4 * (Q + C) + 4 * C
 
 
 def kernel_source_digest() -> str:
@@ -88,12 +98,13 @@ def load_traffic(path_name: str):
     return d.get("hbm_bytes_per_launch")
 
 
-CPU_CROP = 640  # side of the square crop the oracle is timed on (about 10-15 s)
+CPU_CROP = 448  # side of the square crop the oracle is timed on (about 5 s per run)
+CPU_RUNS = 3
 
 
 def cpu_baseline_child() -> None:
     """Runs in a child process with one BLAS/OpenMP thread: the oracle on a
-    CPU_CROP x CPU_CROP crop of the 1080p workload frame, once."""
+    CPU_CROP x CPU_CROP crop of the 1080p workload frame, CPU_RUNS times."""
     import numpy as np
     from oracle import flr_ref
     from synth import make_config
@@ -102,9 +113,12 @@ def cpu_baseline_child() -> None:
     y0, x0 = (H - n) // 2, (W - n) // 2
     noisy = np.ascontiguousarray(fr["noisy"][:, y0:y0 + n, x0:x0 + n])
     guides = np.ascontiguousarray(fr["guides"][:, y0:y0 + n, x0:x0 + n])
-    t = time.perf_counter()
-    flr_ref.flr_reference(noisy, guides, R, EPS)
-    print(json.dumps({"seconds": time.perf_counter() - t, "pixels": n * n, "runs": 1}))
+    times = []
+    for _ in range(CPU_RUNS):
+        t = time.perf_counter()
+        flr_ref.flr_reference(noisy, guides, R, EPS)
+        times.append(time.perf_counter() - t)
+    print(json.dumps({"seconds": times, "pixels": n * n}))
 
 
 DOMINANT_KERNEL = {"two_pass": "walk_kernel<8, 3, 3", "fused": "walk_kernel<8, 3, 2",
@@ -395,6 +409,97 @@ def time_batch(flr, torch, np, sets, nsets, dev, stream, args):
             "steps": args.batch_steps}
 
 
+def oracle_sampled_error(got) -> float:
+    """Largest relative error of a timed output of the first buffer set (the
+    seed-1 frame) against the FP64 oracle on three sampled blocks (corner,
+    centre, opposite corner). Part of the CPU leg."""
+    import numpy as np
+    from oracle import flr_ref
+    from synth import make_config
+    fr0 = make_config(1, seed=1)
+    errs = []
+    for (y0, y1, x0, x1) in [(0, 16, 0, 32), (520, 540, 940, 972), (H - 16, H, W - 32, W)]:
+        want = flr_ref.flr_reference_block(fr0["noisy"], fr0["guides"], R, EPS, y0, y1, x0, x1)
+        rms = np.sqrt(np.mean(want ** 2))
+        errs.append(float(np.max(np.abs(got[:, y0:y1, x0:x1] - want) /
+                              np.maximum(np.abs(want), 1e-3 * rms))))
+    return max(errs)
+
+
+def time_path(flr, torch, np, sets, nsets, dev, stream, path, steps, warmup):
+    """Time one flr_denoise execution path on the FLR workload's frames: the
+    whole frame (HIP events around the timed region, on the launch stream)
+    and, for the two-pass path, its first kernel separately (event between
+    the two launches). Returns the path's figures with its roofline: the
+    dominant kernel's algorithmic flops over its average duration against
+    the FP64 (= unpacked FP32) vector peak, and the whole frame's
+    algorithmic HBM bytes over the frame time against the HBM peak."""
+    p = flr.make_params(H, W, Q, C, R, eps=EPS, average=True, fused=path)
+    ws = torch.empty(max(flr.workspace_bytes(p), 1), dtype=torch.uint8, device=dev)
+    coeffs = torch.empty((flr.num_coeff_planes(Q, C), H, W), dtype=torch.float32, device=dev)
+
+    def step(k, evs=None):
+        noisy, guides, out = sets[k % nsets]
+        if evs is not None:
+            evs[0].record(stream)
+        if path == "two_pass":
+            flr.coefficients(guides, noisy, R, eps=EPS, out=coeffs)
+            if evs is not None:
+                evs[1].record(stream)
+            flr.apply(guides, coeffs, R, average=True, out=out)
+        else:
+            flr.denoise(noisy, guides, radius=R, eps=EPS, average=True, fused=path, out=out,
+                        workspace=ws)
+            if evs is not None:
+                evs[1].record(stream)
+        if evs is not None:
+            evs[2].record(stream)
+
+    for k in range(warmup):
+        step(k)
+    torch.cuda.synchronize()
+    ev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(steps)]
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for k in range(steps):
+        step(k, ev[k])
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    per = np.array([a.elapsed_time(c) for a, b, c in ev])
+    first = np.array([a.elapsed_time(b) for a, b, c in ev])
+    pix = H * W
+    if path == "two_pass":
+        dom_ms = float(np.mean(first))
+        dom_flops = algo_flops_per_px(Q, C, "coefficients") * pix
+        dom_name = "flr_coefficients (walk_kernel<8,3,W_COEFFS>)"
+        second_ms = round(float(np.mean(per - first)), 5)
+    else:
+        dom_ms = float(np.mean(per))
+        dom_flops = algo_flops_per_px(Q, C) * pix
+        dom_name = {"fused": "fused walk_kernel<8,3,W_FUSED1>",
+                    "stages": "three-stage path"}[path]
+        second_ms = None
+    achieved = dom_flops / (dom_ms / 1e3) / 1e12
+    frame_bytes = algo_hbm_bytes_per_px(Q, C) * pix
+    hbm_gbps = frame_bytes / (ms / 1e3) / 1e9
+    return {"path": path, "ms_per_frame": round(ms, 5),
+            "value": round(pix / (ms / 1e3) / 1e6, 2), "unit": "Mpixel/s",
+            "ms_per_frame_p10_p50_p90": [round(float(np.percentile(per, q)), 5)
+                                         for q in (10, 50, 90)],
+            "second_kernel_ms": second_ms, "steps": steps,
+            "roofline": {"bound": "alu", "kernel": dom_name, "achieved": round(achieved, 3),
+                         "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                         "kernel_ms": round(dom_ms, 5),
+                         "algo_flops_per_launch": round(dom_flops),
+                         "algo_flops_per_px": round(dom_flops / pix, 1),
+                         "frame_algo_hbm_bytes": frame_bytes,
+                         "hbm_algo_GBps": round(hbm_gbps, 1),
+                         "hbm_frac": round(hbm_gbps / PEAK_HBM_GBPS, 4)}}
+
+
 def cpu_baseline():
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
@@ -406,11 +511,15 @@ def cpu_baseline():
         print(res.stderr[-2000:], file=sys.stderr)
         return None
     d = json.loads(res.stdout.strip().splitlines()[-1])
-    return {"value": round(d["pixels"] / d["seconds"] / 1e6, 5), "unit": "Mpixel/s", "cores": 1,
+    med = sorted(d["seconds"])[len(d["seconds"]) // 2]
+    return {"value": round(d["pixels"] / med / 1e6, 5), "unit": "Mpixel/s", "cores": 1,
             "kind": "oracle",
-            "sample": (f"FP64 NumPy oracle (window sums as shifted adds, batched solves), one "
+            "sample": (f"FP64 NumPy oracle (window sums as shifted adds, batched solves), a "
                        f"{CPU_CROP}x{CPU_CROP} crop of the 1080p workload frame (same guides, "
-                       f"radius, eps), one run of {d['seconds']:.1f} s, 1 thread")}
+                       f"radius, eps), median of {len(d['seconds'])} runs "
+                       f"({', '.join(f'{t:.2f}' for t in d['seconds'])} s) in a child process "
+                       f"with OMP/OPENBLAS/MKL/NUMEXPR_NUM_THREADS=1 (one thread); host has "
+                       f"{os.cpu_count()} logical CPUs")}
 
 
 def main(argv=None):
@@ -421,6 +530,8 @@ def main(argv=None):
     ap.add_argument("--path", default="two_pass", choices=["two_pass", "fused", "stages"],
                     help="flr_denoise execution path to time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-other-path", action="store_true",
+                    help="skip timing the other single-frame path (fused vs two-pass)")
     ap.add_argument("--no-flnr", action="store_true", help="skip the FLNR timing")
     ap.add_argument("--flnr-steps", type=int, default=20)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
@@ -476,66 +587,18 @@ def main(argv=None):
             base = sets[s % 2]
             sets.append((base[0].roll(s, dims=2).contiguous(), base[1].roll(s, dims=2).contiguous(),
                          torch.empty((C, H, W), dtype=torch.float32, device=dev)))
-    path = args.path
-    p = flr.make_params(H, W, Q, C, R, eps=EPS, average=True, fused=path)
-    ws = torch.empty(max(flr.workspace_bytes(p), 1), dtype=torch.uint8, device=dev)
-    coeffs = torch.empty((flr.num_coeff_planes(Q, C), H, W), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream(dev)
-
-    # One step = one frame through the whole path. For two_pass the two
-    # kernels are timed separately (event between the launches).
-    def step(k, evs=None):
-        noisy, guides, out = sets[k % nsets]
-        if evs is not None:
-            evs[0].record(stream)
-        if path == "two_pass":
-            flr.coefficients(guides, noisy, R, eps=EPS, out=coeffs)
-            if evs is not None:
-                evs[1].record(stream)
-            flr.apply(guides, coeffs, R, average=True, out=out)
-        else:
-            flr.denoise(noisy, guides, radius=R, eps=EPS, average=True, fused=path, out=out,
-                        workspace=ws)
-            if evs is not None:
-                evs[1].record(stream)
-        if evs is not None:
-            evs[2].record(stream)
-
-    for k in range(args.warmup):
-        step(k)
-    torch.cuda.synchronize()
-
-    ev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(args.steps)]
-    t_all0 = torch.cuda.Event(enable_timing=True)
-    t_all1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_all0.record(stream)
-    for k in range(args.steps):
-        step(k, ev[k])
-    t_all1.record(stream)
-    torch.cuda.synchronize()
-    total_ms = t_all0.elapsed_time(t_all1)
-    per = np.array([a.elapsed_time(c) for a, b, c in ev])
-    first = np.array([a.elapsed_time(b) for a, b, c in ev])
-    ms_per_step = total_ms / args.steps
     pix = H * W
-
-    # dominant kernel: the coefficient kernel for two_pass, the whole launch
-    # sequence (one kernel) for fused, the whole path for stages
-    if path == "two_pass":
-        dom_ms = float(np.mean(first))
-        dom_flops = algo_flops_per_px(Q, C, "coefficients") * pix
-        dom_bytes = (4 * (Q + C) + 4 * (Q + 1) * C) * pix
-        dom_name = "flr_coefficients (walk_kernel<8,3,W_COEFFS>)"
-        second_ms = float(np.mean(per - first))
-    else:
-        dom_ms = float(np.mean(per))
-        dom_flops = algo_flops_per_px(Q, C) * pix
-        dom_bytes = (4 * (Q + C) + 4 * C) * pix
-        dom_name = "fused walk_kernel<8,3,W_FUSED1>" if path == "fused" else "three-stage path"
-        second_ms = None
-    achieved = dom_flops / (dom_ms / 1e3) / 1e12
-    hbm_gbps = dom_bytes / (dom_ms / 1e3) / 1e9
+    main_path = time_path(flr, torch, np, sets, nsets, dev, stream, args.path, args.steps,
+                          args.warmup)
+    ms_per_step = main_path["ms_per_frame"]
+    outputs = {args.path: sets[0][2].cpu().numpy()}  # the first set's timed output
+    other = None
+    if not args.no_other_path:
+        alt = "fused" if args.path != "fused" else "two_pass"
+        other = time_path(flr, torch, np, sets, nsets, dev, stream, alt,
+                          max(args.steps // 4, 10), 5)
+        outputs[alt] = sets[0][2].cpu().numpy()
 
     # FLNR (the guide network, then FLR over 12 guides) on the same frames,
     # with the network's parameters drawn as in the workload definition
@@ -568,53 +631,43 @@ def main(argv=None):
             dst.copy_(src)
         torch.cuda.synchronize()
 
-    # parity of the timed launches' output against the oracle on sampled blocks
-    from oracle import flr_ref
-    fr0 = make_config(1, seed=1)
-    got = sets[0][2].cpu().numpy()
-    errs = []
-    for (y0, y1, x0, x1) in [(0, 16, 0, 32), (520, 540, 940, 972), (H - 16, H, W - 32, W)]:
-        want = flr_ref.flr_reference_block(fr0["noisy"], fr0["guides"], R, EPS, y0, y1, x0, x1)
-        rms = np.sqrt(np.mean(want ** 2))
-        errs.append(float(np.max(np.abs(got[:, y0:y1, x0:x1] - want) /
-                              np.maximum(np.abs(want), 1e-3 * rms))))
-
+    # the CPU leg: the oracle timed on a bounded sample, and the timed
+    # launches' outputs checked against it on sampled blocks
     cpu = None if args.no_cpu_baseline else cpu_baseline()
+    errs = {k: oracle_sampled_error(v) for k, v in outputs.items()}
+    if other is not None:
+        other["max_rel_err_vs_fp64_sampled"] = errs[other["path"]]
+    roof = dict(main_path["roofline"])
+    roof["traffic"] = load_traffic(args.path)
     line = {
         "metric": "Mpixel/s at 1080p (FLR), ms/frame, % roofline, err vs FP64",
-        "value": round(pix / (ms_per_step / 1e3) / 1e6, 2),
+        "value": main_path["value"],
         "unit": "Mpixel/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
+        "ms_per_step": ms_per_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32-io/f64-sums/f32-cholesky",
         "data": "synthetic",
         "config": {"workload": "FLR 1920x1080 RGB frame, 8 guides + constant, radius 8, "
                                "eps 1e-3, ridge, window-averaged coefficients",
                    "path": {"fused": "fused (one kernel)",
                             "two_pass": "two kernels (moments+solve, average+reconstruct)",
-                            "stages": "three stages (moments, solve, apply)"}[path],
-                   "io_dtype": "f32", "accumulate_dtype": "f64 sums/centring, f32 factorisation",
+                            "stages": "three stages (moments, solve, apply)"}[args.path],
+                   "io_dtype": "f32",
+                   "accumulate_dtype": "f64 window sums, centring, intercepts and average; "
+                                       "f32 Cholesky factorisation and substitution",
                    "buffer_sets": nsets,
-                   "ms_per_frame_p10_p50_p90": [round(float(np.percentile(per, q)), 5)
-                                                for q in (10, 50, 90)],
-                   "second_kernel_ms": None if second_ms is None else round(second_ms, 5),
-                   "max_rel_err_vs_fp64_sampled": max(errs),
-                   "parity_ok": bool(max(errs) <= 1e-4)},
-        "roofline": {"bound": "alu", "kernel": dom_name,
-                     "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                     "traffic": load_traffic(path),
-                     "kernel_ms": round(dom_ms, 5),
-                     "algo_flops_per_launch": dom_flops,
-                     "algo_hbm_bytes_per_launch": dom_bytes,
-                     "hbm_algo_GBps": round(hbm_gbps, 1),
-                     "hbm_frac": round(hbm_gbps / PEAK_HBM_GBPS, 4)},
+                   "ms_per_frame_p10_p50_p90": main_path["ms_per_frame_p10_p50_p90"],
+                   "second_kernel_ms": main_path["second_kernel_ms"],
+                   "max_rel_err_vs_fp64_sampled": errs[args.path],
+                   "parity_ok": bool(errs[args.path] <= 1e-4)},
+        "roofline": roof,
         "cpu_baseline": cpu,
+        "other_path": other,
         "flnr": flnr,
         "adjoint": adjoint,
         "lowres": lowres,

@@ -78,6 +78,35 @@ flr_status flr_net_forward(int32_t height, int32_t width, const float* guides,
                            const float* noisy, const void* packed, float* out,
                            void* workspace, size_t workspace_bytes, void* stream);
 
+/* Verification view of one forward pass (Sec. 3.3's network, layer by
+ * layer): flr_net_forward_trace computes exactly what flr_net_forward
+ * computes, with the same kernels, and leaves every layer's BF16 output
+ * activation in the caller-owned trace buffer, so that each layer can be
+ * checked on the inputs the device actually fed it. Trace tensor index:
+ *   0 x0 (the prepared input: 11 compressed channels, 5 zero)   1 in3
+ *   2 in1 (= e0)   3 e1a   4 e1b (= e1)   5 e2a   6 e2b (= e2)   7 d1a
+ *   8 d1b (= d1)   9 d0a   10 d0b   11 out3
+ * (out1's sigmoid output is `out`, as in flr_net_forward). Each tensor is
+ * HWC BF16 (uint16 bit patterns): [h][w][channels], channels a multiple of
+ * 16 (x0 pads 11 to 16 with zeros). */
+size_t flr_net_trace_bytes(int32_t height, int32_t width);
+
+/* Where trace tensor `index` (0..11) lives in the trace buffer of a height x
+ * width frame: byte offset, channel count and grid (full, half or quarter
+ * resolution: ceil(n/2) per halving). FLR_ERR_SHAPE for invalid sizes,
+ * FLR_ERR_NULL for a null output pointer, FLR_ERR_MODE for an index out of
+ * range. Host only. */
+flr_status flr_net_trace_tensor(int32_t height, int32_t width, int32_t index, size_t* offset,
+                                int32_t* channels, int32_t* tensor_height, int32_t* tensor_width);
+
+/* flr_net_forward with the trace buffer (flr_net_trace_bytes, 16-byte
+ * aligned, caller-owned device memory) in place of the workspace. Errors as
+ * flr_net_forward (FLR_ERR_WORKSPACE when the trace buffer is missing or too
+ * small). */
+flr_status flr_net_forward_trace(int32_t height, int32_t width, const float* guides,
+                                 const float* noisy, const void* packed, float* out, void* trace,
+                                 size_t trace_bytes, void* stream);
+
 /* Workspace bytes of flr_net_backward for a height x width frame: the
  * forward's activations plus FP32 gradient tensors (about 1.3 KB per pixel).
  * 0 for invalid sizes. */

@@ -35,7 +35,8 @@ EXPORTED = ("flr_num_moment_planes", "flr_num_coeff_planes", "flr_denoise_worksp
             # include/flr_net.h
             "flr_net_num_params", "flr_net_packed_bytes", "flr_net_pack", "flr_net_workspace_bytes",
             "flr_net_forward", "flr_net_backward_workspace_bytes", "flr_net_backward",
-            "flr_flnr_workspace_bytes", "flr_flnr_denoise",
+            "flr_flnr_workspace_bytes", "flr_flnr_denoise", "flr_net_trace_bytes",
+            "flr_net_trace_tensor", "flr_net_forward_trace",
             # include/flr_train.h
             "flr_l1_workspace_bytes", "flr_l1_loss_grad", "flr_adamw_step")
 
@@ -164,6 +165,15 @@ def lib() -> ctypes.CDLL:
     L.flr_net_forward.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp,
                                   ctypes.c_size_t, vp]
     L.flr_net_forward.restype = ctypes.c_int
+    L.flr_net_trace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    L.flr_net_trace_bytes.restype = ctypes.c_size_t
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    L.flr_net_trace_tensor.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_size_t), i32p, i32p, i32p]
+    L.flr_net_trace_tensor.restype = ctypes.c_int
+    L.flr_net_forward_trace.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp,
+                                        ctypes.c_size_t, vp]
+    L.flr_net_forward_trace.restype = ctypes.c_int
     L.flr_net_backward_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
     L.flr_net_backward_workspace_bytes.restype = ctypes.c_size_t
     L.flr_net_backward.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp, vp,

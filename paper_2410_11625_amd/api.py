@@ -411,6 +411,46 @@ def net_forward(guides: torch.Tensor, noisy: torch.Tensor, packed: torch.Tensor,
     return out
 
 
+# names of the trace tensors of net_forward_trace, in index order
+NET_TRACE_NAMES = ("x0", "in3", "in1", "e1a", "e1b", "e2a", "e2b", "d1a", "d1b", "d0a", "d0b",
+                   "out3")
+
+
+def net_trace_layout(H: int, W: int) -> dict:
+    """name -> (byte offset, channels, height, width) of each trace tensor."""
+    out = {}
+    for i, name in enumerate(NET_TRACE_NAMES):
+        off = ctypes.c_size_t()
+        c, h, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().flr_net_trace_tensor(H, W, i, ctypes.byref(off), ctypes.byref(c),
+                                         ctypes.byref(h), ctypes.byref(w)),
+              "flr_net_trace_tensor")
+        out[name] = (off.value, c.value, h.value, w.value)
+    return out
+
+
+def net_forward_trace(guides: torch.Tensor, noisy: torch.Tensor, packed: torch.Tensor):
+    """net_forward, also returning every layer's BF16 output activation:
+    (out [4,H,W] float32, {name: int16 tensor [h, w, channels] of BF16 bit
+    patterns}) with the names of NET_TRACE_NAMES."""
+    _need(guides, "guides")
+    _need(noisy, "noisy")
+    if guides.shape[0] != NET_IN_GUIDES or noisy.shape[0] != NET_IN_NOISY:
+        raise ValueError("the network reads 8 guide planes and 3 noisy planes")
+    _, H, W = guides.shape
+    need = int(lib().flr_net_trace_bytes(H, W))
+    trace = torch.empty(max(need, 1), dtype=torch.uint8, device=guides.device)
+    out = torch.empty((NET_OUT, H, W), dtype=torch.float32, device=guides.device)
+    check(lib().flr_net_forward_trace(H, W, guides.data_ptr(), noisy.data_ptr(),
+                                      packed.data_ptr(), out.data_ptr(), trace.data_ptr(), need,
+                                      _stream(guides)),
+          "flr_net_forward_trace")
+    acts = {}
+    for name, (off, c, h, w) in net_trace_layout(H, W).items():
+        acts[name] = trace[off:off + h * w * c * 2].view(torch.int16).view(h, w, c)
+    return out, acts
+
+
 def net_backward(guides: torch.Tensor, noisy: torch.Tensor, params: torch.Tensor,
                  packed: torch.Tensor, grad_out: torch.Tensor,
                  grad_params: torch.Tensor | None = None, accumulate: bool = False,

@@ -43,6 +43,8 @@ struct ConvArgs {
   const float* b2;
   uint16_t* out;        // HWC BF16 output
   float* outf;          // FUSE_1X1_SIGMOID: planar FP32 output
+  uint16_t* mid;        // fused layers: when set, the first layer's BF16
+                        // activations are stored here too (HWC, 16 channels)
   int Hi, Wi;           // input grid
   int Hl, Wl;           // IN_UPCAT: grid of in0
   int Ho, Wo;           // output grid
@@ -145,6 +147,8 @@ __device__ __forceinline__ void epilogue(const ConvArgs& a, int y, int px, bool 
 #pragma unroll
     for (int i = 0; i < 4; ++i) h[i] = f2bf(fmaxf(acc[0][i] + a.b[4 * kq + i], 0.f));
     const bf16x4_t hv = pack4(h[0], h[1], h[2], h[3]);
+    if (a.mid && pin)
+      *reinterpret_cast<bf16x4_t*>(a.mid + ((size_t)y * a.Wo + px) * 16 + 4 * kq) = hv;
     constexpr int NB2 = (COUT2 + 15) / 16;
 #pragma unroll
     for (int nb = 0; nb < NB2; ++nb) {
@@ -541,6 +545,26 @@ inline void act_layout(const Grids& g, size_t off[kActBufs + 1]) {
   for (int i = 0; i < kActBufs; ++i) off[i + 1] = off[i] + align256(sz[i]);
 }
 
+// Forward trace (flr_net_forward_trace): every layer's output activation,
+// in the order of the header's layer table: x0 (the prepared input), in3,
+// e0, e1a, e1, e2a, e2, d1a, d1, d0a, d0b, out3. The forward's own buffers
+// (act_layout) come first; in3's and out3's outputs follow them.
+constexpr int kTraceTensors = 12;
+constexpr int kTraceChannels[kTraceTensors] = {16, 16, 16, 32, 32, 64, 64, 32, 32, 16, 16, 16};
+constexpr int kTraceGrid[kTraceTensors] = {0, 0, 0, 0, 1, 1, 2, 1, 1, 0, 0, 0};
+// trace index -> act_layout buffer (-1: the two stored after them)
+constexpr int kTraceAct[kTraceTensors] = {0, -1, 1, 2, 3, 4, 5, 6, 7, 8, 9, -1};
+inline void trace_layout(const Grids& g, size_t off[kTraceTensors + 1]) {
+  size_t act[kActBufs + 1];
+  act_layout(g, act);
+  const size_t full16 = align256((size_t)g.H * g.W * 2 * 16);
+  for (int i = 0; i < kTraceTensors; ++i)
+    if (kTraceAct[i] >= 0) off[i] = act[kTraceAct[i]];
+  off[1] = act[kActBufs];
+  off[11] = act[kActBufs] + full16;
+  off[kTraceTensors] = act[kActBufs] + 2 * full16;
+}
+
 bool valid_dims(int H, int W) {
   return H >= 1 && W >= 1 && H <= FLR_MAX_DIM && W <= FLR_MAX_DIM &&
          (int64_t)H * W <= ((int64_t)1 << 28);
@@ -572,9 +596,13 @@ hipError_t launch(const ConvArgs& a, hipStream_t s) {
 }
 
 // The forward pass into the activation buffers at the start of ws (the
-// act_layout offsets), the sigmoid output planar FP32 into out.
+// act_layout offsets), the sigmoid output planar FP32 into out. When set,
+// mid_in3 and mid_out3 receive the activations of in3 and out3, which the
+// fused kernels otherwise keep in registers (HWC BF16, 16 channels, full
+// resolution).
 flr_status run_forward(const Grids& g, const float* guides, const float* noisy, const void* packed,
-                       float* out, char* ws, hipStream_t s) {
+                       float* out, char* ws, hipStream_t s, uint16_t* mid_in3 = nullptr,
+                       uint16_t* mid_out3 = nullptr) {
   size_t off[kActBufs + 1];
   act_layout(g, off);
   auto buf = [&](int i) { return reinterpret_cast<uint16_t*>(ws + off[i]); };
@@ -603,6 +631,7 @@ flr_status run_forward(const Grids& g, const float* guides, const float* noisy, 
     a.w2 = layer_w(packed, 1);
     a.b2 = layer_b(packed, 1);
     a.out = e0;
+    a.mid = mid_in3;
     if ((e = launch<16, 16, 3, 1, IN_HWC, 0, FUSE_1X1_RELU, 16>(a, s)) != hipSuccess) return FLR_ERR_HIP;
   }
   {  // e1a
@@ -665,6 +694,7 @@ flr_status run_forward(const Grids& g, const float* guides, const float* noisy, 
     a.w2 = layer_w(packed, 11);
     a.b2 = layer_b(packed, 11);
     a.outf = out;
+    a.mid = mid_out3;
     if ((e = launch<16, 16, 3, 1, IN_HWC, 0, FUSE_1X1_SIGMOID, FLR_NET_OUT>(a, s)) != hipSuccess)
       return FLR_ERR_HIP;
   }
@@ -822,23 +852,9 @@ flr_status run_backward(const Grids& g, const float* guides, const float* noisy,
   const RoundArgs ra = {params, wr, np};
   hipLaunchKernelGGL(round_params_kernel, dim3((np + 255) / 256), dim3(256), 0, s, ra);
   if (hipGetLastError() != hipSuccess) return FLR_ERR_HIP;
-  flr_status st = run_forward(g, guides, noisy, packed, sig, ws, s);
+  // the forward, also storing in3's and out3's activations
+  flr_status st = run_forward(g, guides, noisy, packed, sig, ws, s, a16, t6);
   if (st != FLR_OK) return st;
-  {  // in3 and out3 outputs, which the forward keeps in registers
-    ConvArgs a = {};
-    a.Hi = a.Ho = g.H;
-    a.Wi = a.Wo = g.W;
-    a.w = layer_w(packed, 0);
-    a.b = layer_b(packed, 0);
-    a.in0 = x0;
-    a.out = a16;
-    if (launch<16, 16, 3, 1, IN_HWC, 0, FUSE_NONE, 0>(a, s) != hipSuccess) return FLR_ERR_HIP;
-    a.w = layer_w(packed, 10);
-    a.b = layer_b(packed, 10);
-    a.in0 = t5;
-    a.out = t6;
-    if (launch<16, 16, 3, 1, IN_HWC, 0, FUSE_NONE, 0>(a, s) != hipSuccess) return FLR_ERR_HIP;
-  }
   const SigmoidBwdArgs sa = {dout, sig, fbuf(B_DZ1), F, FLR_NET_OUT};
   hipLaunchKernelGGL(sigmoid_bwd_kernel, dim3((F + 255) / 256), dim3(256), 0, s, sa);
   if (hipGetLastError() != hipSuccess) return FLR_ERR_HIP;
@@ -938,6 +954,55 @@ flr_status flr_net_forward(int32_t height, int32_t width, const float* guides, c
     return FLR_ERR_ALIAS;
   return run_forward(grids(height, width), guides, noisy, packed, out,
                      static_cast<char*>(workspace), reinterpret_cast<hipStream_t>(stream));
+}
+
+size_t flr_net_trace_bytes(int32_t height, int32_t width) {
+  if (!valid_dims(height, width)) return 0;
+  size_t off[kTraceTensors + 1];
+  trace_layout(grids(height, width), off);
+  return off[kTraceTensors];
+}
+
+flr_status flr_net_trace_tensor(int32_t height, int32_t width, int32_t index, size_t* offset,
+                                int32_t* channels, int32_t* tensor_height, int32_t* tensor_width) {
+  if (!valid_dims(height, width)) return FLR_ERR_SHAPE;
+  if (!offset || !channels || !tensor_height || !tensor_width) return FLR_ERR_NULL;
+  if (index < 0 || index >= kTraceTensors) return FLR_ERR_MODE;
+  const Grids g = grids(height, width);
+  size_t off[kTraceTensors + 1];
+  trace_layout(g, off);
+  const int which = kTraceGrid[index];
+  *offset = off[index];
+  *channels = kTraceChannels[index];
+  *tensor_height = which == 0 ? g.H : which == 1 ? g.Hh : g.Hq;
+  *tensor_width = which == 0 ? g.W : which == 1 ? g.Wh : g.Wq;
+  return FLR_OK;
+}
+
+flr_status flr_net_forward_trace(int32_t height, int32_t width, const float* guides,
+                                 const float* noisy, const void* packed, float* out, void* trace,
+                                 size_t trace_bytes, void* stream) {
+  if (!valid_dims(height, width)) return FLR_ERR_SHAPE;
+  if (!guides || !noisy || !packed || !out) return FLR_ERR_NULL;
+  if (!aligned16(guides) || !aligned16(noisy) || !aligned16(packed) || !aligned16(out))
+    return FLR_ERR_ALIGN;
+  const size_t need = flr_net_trace_bytes(height, width);
+  if (!trace || trace_bytes < need) return FLR_ERR_WORKSPACE;
+  if (!aligned16(trace)) return FLR_ERR_ALIGN;
+  const size_t pb = (size_t)height * width * sizeof(float);
+  const size_t gb = FLR_NET_IN_GUIDES * pb, nb = FLR_NET_IN_NOISY * pb, ob = FLR_NET_OUT * pb;
+  const size_t kb = flr_net_packed_bytes();
+  if (overlaps(out, ob, guides, gb) || overlaps(out, ob, noisy, nb) || overlaps(out, ob, packed, kb) ||
+      overlaps(trace, need, guides, gb) || overlaps(trace, need, noisy, nb) ||
+      overlaps(trace, need, packed, kb) || overlaps(trace, need, out, ob))
+    return FLR_ERR_ALIAS;
+  const Grids g = grids(height, width);
+  size_t off[kTraceTensors + 1];
+  trace_layout(g, off);
+  char* t = static_cast<char*>(trace);
+  return run_forward(g, guides, noisy, packed, out, t, reinterpret_cast<hipStream_t>(stream),
+                     reinterpret_cast<uint16_t*>(t + off[1]),
+                     reinterpret_cast<uint16_t*>(t + off[11]));
 }
 
 size_t flr_net_backward_workspace_bytes(int32_t height, int32_t width) {

@@ -9,6 +9,7 @@ emulated kernels cannot take down the test runner. Test infrastructure only.
 from __future__ import annotations
 
 import ctypes
+import fcntl
 import json
 import os
 import subprocess
@@ -41,16 +42,25 @@ def build(force: bool = False) -> str:
                    os.path.join(CSRC, "flr_adjoint.hpp"), os.path.join(CSRC, "flr_lowres.hpp"),
                    os.path.join(CSRC, "flr_net_bwd.hpp"),
                    os.path.join(INCLUDE, "flr.h"), os.path.join(INCLUDE, "flr_net.h")]
-    if not force and os.path.exists(SO) and \
-            os.path.getmtime(SO) >= max(os.path.getmtime(d) for d in deps):
+    def fresh():
+        return os.path.exists(SO) and \
+            os.path.getmtime(SO) >= max(os.path.getmtime(d) for d in deps)
+
+    if not force and fresh():
         return SO
     os.makedirs(BUILD, exist_ok=True)
-    defs = [f"-D{d}" for d in VARIANT.split(",") if d]
-    cmd = ["g++", "-std=c++20", "-O1", "-g", "-pthread", "-fno-extern-tls-init", "-shared", "-fPIC", *defs,
-           f"-I{HERE}", f"-I{INCLUDE}", f"-I{CSRC}", *srcs, "-x", "c++", net_src, adj_src, lr_src,
-           "-o", SO + ".tmp"]
-    subprocess.run(cmd, check=True)
-    os.replace(SO + ".tmp", SO)
+    # one builder at a time (test workers may ask concurrently)
+    with open(SO + ".lock", "w") as lk:
+        fcntl.flock(lk, fcntl.LOCK_EX)
+        if not force and fresh():
+            return SO
+        defs = [f"-D{d}" for d in VARIANT.split(",") if d]
+        tmp = f"{SO}.tmp{os.getpid()}"
+        cmd = ["g++", "-std=c++20", "-O1", "-g", "-pthread", "-fno-extern-tls-init", "-shared",
+               "-fPIC", *defs, f"-I{HERE}", f"-I{INCLUDE}", f"-I{CSRC}", *srcs, "-x", "c++",
+               net_src, adj_src, lr_src, "-o", tmp]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, SO)
     return SO
 
 
@@ -131,6 +141,45 @@ class Emu:
         wp, _ = self.buf(shape=(need // 4,))
         self.check(L.flr_net_forward(H, W, gp, yp, kp, op, wp, need, None), "flr_net_forward")
         return out.copy()
+
+    def net_trace(self, guides, noisy, params):
+        """flr_net_forward_trace -> (out [4,H,W], {name: HWC int16 BF16 tensor})."""
+        L = self.L
+        vp = ctypes.c_void_p
+        i32 = ctypes.c_int32
+        L.flr_net_packed_bytes.restype = ctypes.c_size_t
+        L.flr_net_pack.argtypes = [vp, vp, vp]
+        L.flr_net_trace_bytes.restype = ctypes.c_size_t
+        L.flr_net_trace_bytes.argtypes = [i32, i32]
+        L.flr_net_trace_tensor.argtypes = [i32, i32, i32, ctypes.POINTER(ctypes.c_size_t),
+                                           ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                           ctypes.POINTER(i32)]
+        L.flr_net_forward_trace.argtypes = [i32, i32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        _, H, W = guides.shape
+        pp, _ = self.buf(params)
+        kb = int(L.flr_net_packed_bytes())
+        kp, _ = self.buf(shape=(kb // 4,))
+        self.check(L.flr_net_pack(pp, kp, None), "flr_net_pack")
+        gp, _ = self.buf(guides)
+        yp, _ = self.buf(noisy)
+        op, out = self.buf(shape=(4, H, W))
+        need = int(L.flr_net_trace_bytes(H, W))
+        tp, tr = self.buf(shape=((need + 3) // 4,))
+        self.check(L.flr_net_forward_trace(H, W, gp, yp, kp, op, tp, need, None),
+                   "flr_net_forward_trace")
+        raw = tr.view(np.uint8)
+        names = ("x0", "in3", "in1", "e1a", "e1b", "e2a", "e2b", "d1a", "d1b", "d0a", "d0b",
+                 "out3")
+        acts = {}
+        for i, name in enumerate(names):
+            off, c, h, w = ctypes.c_size_t(), i32(), i32(), i32()
+            self.check(L.flr_net_trace_tensor(H, W, i, ctypes.byref(off), ctypes.byref(c),
+                                              ctypes.byref(h), ctypes.byref(w)),
+                       "flr_net_trace_tensor")
+            n = h.value * w.value * c.value * 2
+            acts[name] = raw[off.value:off.value + n].view(np.int16).reshape(
+                h.value, w.value, c.value).copy()
+        return out.copy(), acts
 
     def net_backward(self, guides, noisy, params, grad_out):
         """flr_net_backward -> FP32 parameter gradients (layout of params)."""
@@ -315,6 +364,15 @@ def run_case(spec: dict) -> dict:
             d = np.abs(got - want)
             return {"maxabs": float(d.max()), "median": float(np.median(d)),
                     "within": float(np.mean(d <= 2e-3)), "shape": list(got.shape)}
+        if kind == "net_trace":
+            from synth.net_weights import flatten_net_weights, make_net_weights
+            from tests.net_check import check_network
+            fr = make_config(1, h=H, w=W)
+            wts = make_net_weights(spec.get("seed", 2))
+            out, acts = emu.net_trace(fr["guides"], fr["noisy"], flatten_net_weights(wts))
+            plain = emu.net(fr["guides"], fr["noisy"], flatten_net_weights(wts))
+            report, _ = check_network(acts, out, fr["guides"], fr["noisy"], wts)
+            return {"report": report, "trace_equals_forward": bool(np.array_equal(out, plain))}
         if kind == "net_bwd":
             from oracle import net_adjoint, net_ref
             from synth.net_weights import flatten_net_weights, make_net_weights

@@ -142,6 +142,47 @@ def test_adjoint_matches_brute_force_autograd(avg, r, Q):
     assert abs(de - ge.item()) <= 1e-9 * max(abs(ge.item()), 1.0)
 
 
+@pytest.mark.parametrize("mode,eps,em", [("ridge", 1e-3, 0.0), ("paper", 1e-2, 0.1)])
+def test_gradient_check_instance_32x32(mode, eps, em):
+    """The training workload's named gradient check: a 32x32 frame with 4
+    guides plus the constant (5 features), radius 3, FP64. dL/d(noisy) in
+    full by linearity, dL/d(guides) by central differences on 160 seeded
+    entries (borders, corners and interior), dL/d(eps) and, for the
+    Appendix regulariser, dL/d(eps') by central differences."""
+    from synth import make_config
+    fr = make_config(0, h=32, w=32)
+    y = fr["noisy"].astype(np.float32).astype(np.float64)
+    g = fr["guides"].astype(np.float32).astype(np.float64)
+    assert g.shape == (4, 32, 32)
+    G = np.random.default_rng(33).standard_normal(y.shape)
+    r = 3
+    dy, dg, de, dm = adj.flr_backward(y, g, G, r, eps, mode, em, True)
+
+    def L(yy, gg, e=eps, m=em):
+        return float(np.sum(G * flr_reference(yy, gg, r, e, mode, m, average=True)))
+
+    d = np.random.default_rng(34).standard_normal(y.shape)
+    lhs = L(y + d, g) - L(y, g)
+    assert abs(lhs - np.sum(dy * d)) <= 1e-10 * np.sum(np.abs(dy * d))
+    rng = np.random.default_rng(35)
+    idx = [tuple(rng.integers(0, s) for s in g.shape) for _ in range(150)]
+    idx += [(q, a, b) for q in range(4) for a, b in [(0, 0), (31, 31), (0, 31)]][:10]
+    h = 1e-5
+    scale = np.max(np.abs(dg))
+    for i in idx:
+        gp, gm = g.copy(), g.copy()
+        gp[i] += h
+        gm[i] -= h
+        fd = (L(y, gp) - L(y, gm)) / (2 * h)
+        assert abs(fd - dg[i]) <= 1e-6 * scale, (i, fd, dg[i])
+    he = eps * 1e-4
+    fde = (L(y, g, eps + he) - L(y, g, eps - he)) / (2 * he)
+    assert abs(de - fde) <= 1e-6 * max(abs(fde), 1.0)
+    if mode == "paper":
+        fdm = (L(y, g, eps, em + 1e-5) - L(y, g, eps, em - 1e-5)) / 2e-5
+        assert abs(dm - fdm) <= 1e-6 * max(abs(fdm), 1.0)
+
+
 def test_radius_zero_is_identity():
     """r = 0: each window is one pixel, W = V = 0, a = 0, out = noisy."""
     y, g, G = _frame(H=4, W=5, Q=2, C=3, seed=6)

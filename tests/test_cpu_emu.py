@@ -57,14 +57,21 @@ def test_emulated_stages_match_oracle():
     assert res["apply_err"] < 1e-5
 
 
-# The guide network's kernels (MFMA emulated per the 16x16x16 BF16 lane layout)
-# against the FP64 network oracle with its BF16 rounding points.
+# The guide network's kernels (MFMA emulated per the 16x16x16 BF16 lane
+# layout), every layer checked on the inputs the kernels fed it: the oracle's
+# BF16 rounding of the exact convolution, a neighbouring value only within the
+# FP32 accumulation bound of a rounding boundary (criteria: tests/net_check.py).
 @pytest.mark.parametrize("H,W", [(20, 70), (33, 131), (1, 1), (7, 3)])
-def test_emulated_net_matches_oracle(H, W):
-    res = run_in_subprocess(dict(kind="net", H=H, W=W, Q=8, C=3, r=0))
-    assert res["shape"] == [4, H, W]
-    # criteria and their reasons: tests/test_gpu_net.py
-    assert res["median"] <= 1e-5 and res["within"] >= 0.99 and res["maxabs"] <= 2e-2, res
+def test_emulated_net_layers_valid(H, W):
+    res = run_in_subprocess(dict(kind="net_trace", H=H, W=W, Q=8, C=3, r=0))
+    assert res["trace_equals_forward"]
+    rep = res["report"]
+    assert rep["head_rel"] <= 2e-3
+    for name, v in rep.items():
+        if name == "head_rel":
+            continue
+        n, band, flips = v
+        assert flips <= band and flips <= max(4, n // 1000), (name, n, band, flips)
 
 
 # The network's backward (flr_net_backward) against the FP64 backward oracle

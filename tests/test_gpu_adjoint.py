@@ -63,6 +63,9 @@ def _frame(case):
 
 CASES = [
     dict(H=256, W=256, Q=4, C=1, r=8, config=0),
+    # the training workload's gradient-check instance: 32x32, 4 guides + 1, r 3
+    dict(H=32, W=32, Q=4, C=1, r=3, config=0),
+    dict(H=32, W=32, Q=4, C=1, r=3, config=0, mode="paper", eps=1e-2, eps_mul=0.1),
     dict(H=70, W=300, Q=8, C=3, r=8, config=1),
     dict(H=50, W=270, Q=8, C=3, r=8, config=1, average=False),
     dict(H=33, W=131, Q=3, C=2, r=3, mode="paper", eps=1e-2, eps_mul=0.2, offset=2.0),

@@ -1,21 +1,23 @@
-"""GPU parity of the FLNR guide network and of FLNR denoising.
+"""GPU parity of the FLNR guide network and of FLNR denoising (Sec. 3.3).
 
-Network (BF16 weights and activations, FP32 accumulation) against the FP64
-oracle that rounds at the same points. The two agree to FP32 level wherever
-every intermediate BF16 rounding decision agrees; where an exact layer value
-lies within FP32 accumulation error of a BF16 rounding boundary the two may
-round it to neighbouring BF16 values (one unit in the 8th bit), and such a
-flip propagates through the later layers. The tolerance therefore has three
-parts: median |error| <= 1e-5 (agreement without flips), at least 99% of
-outputs within 2e-3 (the BF16-network tolerance of the workload definition)
-and max <= 2e-2 (bounded effect of flips).
+Network (BF16 weights and activations, FP32 accumulation): every layer is
+checked element by element on the BF16 inputs the device fed it, read from
+a forward trace (tests/net_check.py): the device's output must equal the
+oracle's BF16 rounding of the exact FP64 convolution, except where that
+exact value lies within the FP32 accumulation bound of a BF16 rounding
+boundary, where the neighbouring BF16 value is also accepted; the sigmoid
+head must agree with the oracle's sigmoid of the exact logit to FP32
+rounding and to 2e-3 relative. Comparing the final output with the oracle
+network run on its own would compare where rounding flips (each one valid)
+happened to occur and how later layers amplify them, not the kernels.
 
-FLNR is the network followed by FLR over 12 guides. Its regression part is
-checked on the oracle's network output against the FLR oracle at the FP32
-regression tolerance (1e-4), and the full entry point must equal its two
-parts run separately, bit for bit. (Comparing FLNR end to end with the
-oracle would compare how an ill-conditioned 12-guide fit with untrained
-guides amplifies BF16 rounding flips, not the implementation.)
+FLNR end to end: the device's flr_flnr_denoise against the FLR oracle run
+on the guides plus the oracle's sigmoid head of the validated network, at
+the BF16-path tolerance 2e-3 (the 12-guide regression with untrained guides
+amplifies the FP32-level difference of the two heads, about 1e-7, to about
+1.3e-4 at the worst pixel). The regression part alone is also checked on the
+oracle network's output at the FP32 tolerance 1e-4, and the entry point
+must equal its two parts run separately, bit for bit.
 """
 import numpy as np
 import pytest
@@ -26,6 +28,7 @@ import paper_2410_11625_amd as flr  # noqa: E402
 from oracle import flr_ref, net_ref  # noqa: E402
 from synth import make_config  # noqa: E402
 from synth.net_weights import flatten_net_weights, make_net_weights  # noqa: E402
+from tests.net_check import check_network  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -50,38 +53,96 @@ def packed(weights):
     return flr.net_pack(_t(flatten_net_weights(weights)))
 
 
-def check_net(got, want):
-    d = np.abs(np.asarray(got, np.float64) - want)
-    assert np.all(np.isfinite(got))
-    assert np.median(d) <= 1e-5, np.median(d)
-    assert np.mean(d <= 2e-3) >= 0.99, np.mean(d <= 2e-3)
-    assert d.max() <= 2e-2, d.max()
+def _trace(fr, packed):
+    out, acts = flr.net_forward_trace(_t(fr["guides"]), _t(fr["noisy"]), packed)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), {k: v.cpu().numpy() for k, v in acts.items()}
+
+
+def _assert_few_flips(report):
+    """Flips are the rare exception (about 1e-4 of the activations where the
+    FP32 sum straddles a rounding boundary); every one was already checked to
+    be a valid rounding of a value within the accumulation bound."""
+    for name, v in report.items():
+        if name != "head_rel":
+            n, band, flips = v
+            assert flips <= band and flips <= max(4, n // 1000), (name, v)
 
 
 @pytest.mark.parametrize("H,W", [(1, 1), (7, 3), (20, 70), (33, 131), (64, 128), (96, 250)])
-def test_net_matches_oracle(weights, packed, H, W):
+def test_net_layers_valid(weights, packed, H, W):
     fr = make_config(1, h=H, w=W)
-    got = flr.net_forward(_t(fr["guides"]), _t(fr["noisy"]), packed)
-    torch.cuda.synchronize()
-    want = net_ref.net_forward(fr["guides"], fr["noisy"], weights)
-    check_net(got.cpu().numpy(), want)
+    out, acts = _trace(fr, packed)
+    plain = flr.net_forward(_t(fr["guides"]), _t(fr["noisy"]), packed).cpu().numpy()
+    assert np.array_equal(out, plain)  # the trace runs the forward's kernels
+    report, _ = check_network(acts, out, fr["guides"], fr["noisy"], weights)
+    _assert_few_flips(report)
 
 
-def test_net_1080p_sampled_crops(weights, packed):
-    """Full 1080p frame on the GPU; the oracle on crops with a 32-pixel margin
-    (beyond the network's reach of 23 pixels) whose origins are multiples of
-    4, so the stride-2 grids of crop and frame coincide."""
+def test_net_1080p_sampled_regions(weights, packed):
+    """The full 1080p frame through the forward's kernels; every layer checked
+    on sampled regions (the check needs only the device's own inputs around
+    each region), including the frame's corners and ragged stride-2 edges."""
     fr = make_config(1)
-    got = flr.net_forward(_t(fr["guides"]), _t(fr["noisy"]), packed).cpu().numpy()
+    out, acts = _trace(fr, packed)
     H, W = 1080, 1920
-    for (y0, y1, x0, x1) in [(0, 32, 0, 64), (520, 552, 944, 1008), (H - 32, H, W - 64, W),
-                             (0, 24, W - 40, W), (700, 740, 0, 48)]:
-        ry0, rx0 = max(y0 - 32, 0), max(x0 - 32, 0)
-        ry1, rx1 = min(y1 + 32, H), min(x1 + 32, W)
-        assert ry0 % 4 == 0 and rx0 % 4 == 0
-        want = net_ref.net_forward(fr["guides"][:, ry0:ry1, rx0:rx1],
-                                   fr["noisy"][:, ry0:ry1, rx0:rx1], weights)
-        check_net(got[:, y0:y1, x0:x1], want[:, y0 - ry0:y1 - ry0, x0 - rx0:x1 - rx0])
+    for region in [(0, 32, 0, 64), (520, 552, 944, 1008), (H - 32, H, W - 64, W),
+                   (0, 24, W - 40, W), (700, 740, 0, 48), (333, 347, 1201, 1263)]:
+        report, _ = check_network(acts, out, fr["guides"], fr["noisy"], weights, region)
+        _assert_few_flips(report)
+
+
+def _flnr_oracle(fr, head, region, block, r=8, eps=1e-3):
+    """FLR oracle over the 8 guides and the validated network head, on
+    output block (y0, y1, x0, x1); head covers `region`, which contains the
+    block extended by 2r (clipped to the frame)."""
+    _, H, W = fr["guides"].shape
+    extra = np.full((4, H, W), np.nan)
+    ry0, ry1, rx0, rx1 = region
+    extra[:, ry0:ry1, rx0:rx1] = head.astype(np.float32)
+    g12 = np.concatenate([fr["guides"].astype(np.float64), extra])
+    return flr_ref.flr_reference_block(fr["noisy"].astype(np.float64), g12, r, eps, *block)
+
+
+def _rel(got, want):
+    rms = np.sqrt(np.mean(want ** 2))
+    return float(np.max(np.abs(got - want) / np.maximum(np.abs(want), 1e-3 * rms)))
+
+
+@pytest.mark.parametrize("H,W", [(48, 96), (64, 160)])
+def test_flnr_end_to_end(weights, packed, H, W):
+    fr = make_config(1, h=H, w=W)
+    out, acts = _trace(fr, packed)
+    report, head = check_network(acts, out, fr["guides"], fr["noisy"], weights)
+    _assert_few_flips(report)
+    g12 = torch.zeros((12, H, W), dtype=torch.float32, device=_dev())
+    g12[:8] = _t(fr["guides"])
+    got = flr.flnr_denoise(_t(fr["noisy"]), g12, packed, radius=8, eps=1e-3,
+                           fused="two_pass").cpu().numpy()
+    assert np.array_equal(g12[8:].cpu().numpy(), out)
+    want = _flnr_oracle(fr, head, (0, H, 0, W), (0, H, 0, W))
+    assert _rel(got, want) <= 2e-3, _rel(got, want)
+
+
+def test_flnr_end_to_end_1080p_sampled(weights, packed):
+    """FLNR at 1080p in the launch configuration the benchmark times, on
+    sampled blocks: the network validated on each block's 2r neighbourhood,
+    the FLR oracle on the guides plus that validated head."""
+    fr = make_config(1)
+    H, W = 1080, 1920
+    out, acts = _trace(fr, packed)
+    g12 = torch.zeros((12, H, W), dtype=torch.float32, device=_dev())
+    g12[:8] = _t(fr["guides"])
+    got = flr.flnr_denoise(_t(fr["noisy"]), g12, packed, radius=8, eps=1e-3,
+                           fused="two_pass").cpu().numpy()
+    assert np.array_equal(g12[8:].cpu().numpy(), out)
+    for (y0, y1, x0, x1) in [(0, 16, 0, 32), (530, 546, 950, 982), (H - 16, H, W - 32, W)]:
+        region = (max(y0 - 16, 0), min(y1 + 16, H), max(x0 - 16, 0), min(x1 + 16, W))
+        report, head = check_network(acts, out, fr["guides"], fr["noisy"], weights, region)
+        _assert_few_flips(report)
+        want = _flnr_oracle(fr, head, region, (y0, y1, x0, x1))
+        e = _rel(got[:, y0:y1, x0:x1], want)
+        assert e <= 2e-3, ((y0, x0), e)
 
 
 def test_net_repeatable(packed):
