@@ -40,6 +40,21 @@ flr_status flr_l1_loss_grad(int64_t n, const float* out, const float* target, fl
                             float* grad, double* loss, void* workspace, size_t workspace_bytes,
                             void* stream);
 
+/* flr_l1_loss_grad for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving or training loops, harnesses that
+ * forbid allocation): the same kernels and the same fixed-order sums, so the
+ * results equal flr_l1_loss_grad's bit for bit, with the per-workgroup
+ * partial sums in a scratch array the library holds on each GPU for the
+ * life of the process (1024 doubles, 8 KiB; enough for every n up to 2^34,
+ * larger n is FLR_ERR_SHAPE). The call allocates nothing. Every call on one
+ * GPU shares that GPU's array: calls that may overlap on one GPU (on
+ * different streams without ordering) race and must not be issued. The
+ * array's device address is looked up on the first call made with each
+ * device current (FLR_ERR_HIP if that fails). Other errors as
+ * flr_l1_loss_grad. */
+flr_status flr_l1_loss_grad_noalloc(int64_t n, const float* out, const float* target,
+                                    float scale, float* grad, double* loss, void* stream);
+
 /* One AdamW step (Adam with decoupled weight decay) on n FP32 parameters, in
  * place: with t = step (1 for the first update),
  *   p <- p - lr * weight_decay * p

@@ -38,7 +38,8 @@ EXPORTED = ("flr_num_moment_planes", "flr_num_coeff_planes", "flr_denoise_worksp
             "flr_flnr_workspace_bytes", "flr_flnr_denoise", "flr_net_trace_bytes",
             "flr_net_trace_tensor", "flr_net_forward_trace",
             # include/flr_train.h
-            "flr_l1_workspace_bytes", "flr_l1_loss_grad", "flr_adamw_step")
+            "flr_l1_workspace_bytes", "flr_l1_loss_grad", "flr_adamw_step",
+            "flr_l1_loss_grad_noalloc")
 
 
 class FlrParams(ctypes.Structure):
@@ -188,6 +189,8 @@ def lib() -> ctypes.CDLL:
     L.flr_l1_loss_grad.argtypes = [ctypes.c_int64, vp, vp, ctypes.c_float, vp, vp, vp,
                                    ctypes.c_size_t, vp]
     L.flr_l1_loss_grad.restype = ctypes.c_int
+    L.flr_l1_loss_grad_noalloc.argtypes = [ctypes.c_int64, vp, vp, ctypes.c_float, vp, vp, vp]
+    L.flr_l1_loss_grad_noalloc.restype = ctypes.c_int
     f = ctypes.c_float
     L.flr_adamw_step.argtypes = [ctypes.c_int64, vp, vp, vp, vp, ctypes.c_int32, f, f, f, f, f, vp]
     L.flr_adamw_step.restype = ctypes.c_int

@@ -7,6 +7,8 @@
 
 #include <stdint.h>
 
+#include <mutex>
+
 #include "flr.h"
 #include "flr_train.h"
 
@@ -102,6 +104,68 @@ inline bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 }
 constexpr int64_t kMaxElems = (int64_t)1 << 34;
 
+// flr_l1_loss_grad_noalloc's partial sums: at most kMaxBlocks doubles
+// (8 KiB), one copy per GPU, held until the process ends. Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in);
+// it resolves the array's device address once per device and uses that.
+static __device__ __align__(256) double scratch[kMaxBlocks];
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices];
+
+// Device address of `scratch` on the current device (resolved on the first
+// call made with that device current).
+hipError_t scratch_address(double** addr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_addr[dev] = p;
+  }
+  *addr = static_cast<double*>(g_scratch_addr[dev]);
+  return hipSuccess;
+}
+
+// Argument checks shared by both L1 entry points: sizes, pointers and the
+// scale (l1_check), then overlaps of the outputs with the inputs (l1_alias).
+flr_status l1_check(int64_t n, const float* out, const float* target, float scale, float* grad,
+                    double* loss) {
+  if (n < 1 || n > kMaxElems) return FLR_ERR_SHAPE;
+  if (!out || !target || !grad || !loss) return FLR_ERR_NULL;
+  if (!aligned16(out) || !aligned16(target) || !aligned16(grad) ||
+      (reinterpret_cast<uintptr_t>(loss) & 7u) != 0)
+    return FLR_ERR_ALIGN;
+  if (!(scale == scale) || scale == __builtin_huge_valf() || scale == -__builtin_huge_valf())
+    return FLR_ERR_EPS;
+  return FLR_OK;
+}
+flr_status l1_alias(int64_t n, const float* out, const float* target, float* grad, double* loss) {
+  const size_t fb = (size_t)n * sizeof(float);
+  if (overlaps(grad, fb, out, fb) || overlaps(grad, fb, target, fb) ||
+      overlaps(loss, sizeof(double), out, fb) || overlaps(loss, sizeof(double), target, fb) ||
+      overlaps(loss, sizeof(double), grad, fb))
+    return FLR_ERR_ALIAS;
+  return FLR_OK;
+}
+
+// The two launches, partial sums in `part` (l1_blocks(n) doubles).
+flr_status l1_launch(int64_t n, const float* out, const float* target, float scale, float* grad,
+                     double* loss, double* part, hipStream_t s) {
+  const int nb = l1_blocks(n);
+  const L1Args a = {out, target, grad, part, n, scale};
+  hipLaunchKernelGGL(l1_kernel, dim3(nb), dim3(kBlock), 0, s, a);
+  if (hipGetLastError() != hipSuccess) return FLR_ERR_HIP;
+  const L1SumArgs b = {part, nb, (double)scale, loss};
+  hipLaunchKernelGGL(l1_sum_kernel, dim3(1), dim3(kBlock), 0, s, b);
+  return hipGetLastError() == hipSuccess ? FLR_OK : FLR_ERR_HIP;
+}
+
 }  // namespace flrtrain
 
 using namespace flrtrain;
@@ -116,31 +180,29 @@ size_t flr_l1_workspace_bytes(int64_t n) {
 flr_status flr_l1_loss_grad(int64_t n, const float* out, const float* target, float scale,
                             float* grad, double* loss, void* workspace, size_t workspace_bytes,
                             void* stream) {
-  if (n < 1 || n > kMaxElems) return FLR_ERR_SHAPE;
-  if (!out || !target || !grad || !loss) return FLR_ERR_NULL;
-  if (!aligned16(out) || !aligned16(target) || !aligned16(grad) ||
-      (reinterpret_cast<uintptr_t>(loss) & 7u) != 0)
-    return FLR_ERR_ALIGN;
-  if (!(scale == scale) || scale == __builtin_huge_valf() || scale == -__builtin_huge_valf())
-    return FLR_ERR_EPS;
+  flr_status st = l1_check(n, out, target, scale, grad, loss);
+  if (st != FLR_OK) return st;
   const size_t need = flr_l1_workspace_bytes(n);
   if (!workspace || workspace_bytes < need) return FLR_ERR_WORKSPACE;
   if (!aligned16(workspace)) return FLR_ERR_ALIGN;
+  if ((st = l1_alias(n, out, target, grad, loss)) != FLR_OK) return st;
   const size_t fb = (size_t)n * sizeof(float);
-  if (overlaps(grad, fb, out, fb) || overlaps(grad, fb, target, fb) ||
-      overlaps(loss, sizeof(double), out, fb) || overlaps(loss, sizeof(double), target, fb) ||
-      overlaps(loss, sizeof(double), grad, fb) || overlaps(workspace, need, out, fb) ||
-      overlaps(workspace, need, target, fb) || overlaps(workspace, need, grad, fb) ||
-      overlaps(workspace, need, loss, sizeof(double)))
+  if (overlaps(workspace, need, out, fb) || overlaps(workspace, need, target, fb) ||
+      overlaps(workspace, need, grad, fb) || overlaps(workspace, need, loss, sizeof(double)))
     return FLR_ERR_ALIAS;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const int nb = l1_blocks(n);
-  const L1Args a = {out, target, grad, static_cast<double*>(workspace), n, scale};
-  hipLaunchKernelGGL(l1_kernel, dim3(nb), dim3(kBlock), 0, s, a);
-  if (hipGetLastError() != hipSuccess) return FLR_ERR_HIP;
-  const L1SumArgs b = {static_cast<const double*>(workspace), nb, (double)scale, loss};
-  hipLaunchKernelGGL(l1_sum_kernel, dim3(1), dim3(kBlock), 0, s, b);
-  return hipGetLastError() == hipSuccess ? FLR_OK : FLR_ERR_HIP;
+  return l1_launch(n, out, target, scale, grad, loss, static_cast<double*>(workspace),
+                   reinterpret_cast<hipStream_t>(stream));
+}
+
+flr_status flr_l1_loss_grad_noalloc(int64_t n, const float* out, const float* target,
+                                    float scale, float* grad, double* loss, void* stream) {
+  flr_status st = l1_check(n, out, target, scale, grad, loss);
+  if (st != FLR_OK) return st;
+  if ((st = l1_alias(n, out, target, grad, loss)) != FLR_OK) return st;
+  if (l1_blocks(n) > kMaxBlocks) return FLR_ERR_SHAPE;  // never for n <= 2^34
+  double* part = nullptr;
+  if (scratch_address(&part) != hipSuccess) return FLR_ERR_HIP;
+  return l1_launch(n, out, target, scale, grad, loss, part, reinterpret_cast<hipStream_t>(stream));
 }
 
 flr_status flr_adamw_step(int64_t n, float* params, const float* grads, float* m, float* v,
