@@ -743,8 +743,10 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs ain) {
 #pragma unroll
     for (int f = 0; f < FC; ++f) VAL[f * kLdsStride + tid] = T(0);
   }
-  ring_t* ring =
-      reinterpret_cast<ring_t*>(a.ring) + (size_t)bid * (size_t)(2 * r + 1) * FC * kThreads + tid;
+  // the workgroup's ring (K_FUSED1 only; no ring otherwise)
+  ring_t* ring = a.ring ? reinterpret_cast<ring_t*>(a.ring) +
+                              (size_t)bid * (size_t)(2 * r + 1) * FC * kThreads + tid
+                        : nullptr;
 
   // inputs of the rows entering (ym + r) and leaving (ym - r - 1) the window
   float fa[Q + C], fs[Q + C];

@@ -31,9 +31,13 @@ constexpr int kCUs = 256;
 #ifndef FLR_RING_T
 #define FLR_RING_T float
 #endif
-// Factorisation and triangular solves of the per-pixel system.
+// Factorisation and triangular solves of the per-pixel system. FP64: with
+// the regulariser at 1e-3 of unit-scale guides, windows of near-constant
+// guides make the centred system's condition number reach 1e4 and more, and
+// an FP32 factorisation then errs by up to 2e-4 relative in the output
+// (measured on 40 x 270 frames of the RGB workload); in FP64 it is below 2e-5.
 #ifndef FLR_CHOL_T
-#define FLR_CHOL_T float
+#define FLR_CHOL_T double
 #endif
 typedef FLR_CHOL_T chol_t;
 typedef FLR_SUM_T sum_t;

@@ -33,6 +33,21 @@
 
 #include "hip/hip_runtime.h"
 
+// AddressSanitizer builds: tell ASan about every switch between the
+// scheduler's stack and a lane's fiber stack.
+#if defined(__SANITIZE_ADDRESS__)
+#include <sanitizer/common_interface_defs.h>
+static inline void fiber_start(void** save, const void* bottom, size_t size) {
+  __sanitizer_start_switch_fiber(save, bottom, size);
+}
+static inline void fiber_finish(void* save, const void** bottom_old, size_t* size_old) {
+  __sanitizer_finish_switch_fiber(save, bottom_old, size_old);
+}
+#else
+static inline void fiber_start(void**, const void*, size_t) {}
+static inline void fiber_finish(void*, const void**, size_t*) {}
+#endif
+
 thread_local dim3 threadIdx;
 thread_local dim3 blockIdx;
 dim3 blockDim;
@@ -59,7 +74,13 @@ hipError_t hipGetLastError() {
 namespace {
 
 constexpr unsigned kWave = 64;
+#if defined(__SANITIZE_ADDRESS__)
+// ASan clears the shadow of a fiber's whole stack at every switch into it:
+// smaller stacks keep that a short memset
+constexpr size_t kStackBytes = 128 * 1024;
+#else
 constexpr size_t kStackBytes = 512 * 1024;
+#endif
 
 enum LaneState : int { READY, AT_BLOCK_BARRIER, AT_WAVE_BARRIER, DONE };
 
@@ -69,11 +90,15 @@ struct Lane {
   unsigned dpp_calls;
   unsigned mfma_calls;
   char* stack;  // kStackBytes above one guard page
+  void* fake = nullptr;  // ASan fake-stack handle while switched out
 };
 
 // One host thread's workgroup scheduler.
 struct Workgroup {
   ucontext_t sched;
+  const void* sched_bottom = nullptr;  // the scheduler's (thread's) stack, for ASan
+  size_t sched_size = 0;
+  void* sched_fake = nullptr;
   std::vector<Lane> lanes;
   unsigned cur = 0;
   int dpp[2][1024];
@@ -98,7 +123,9 @@ struct Workgroup {
   void park(LaneState s) {
     Lane& l = lanes[cur];
     l.state = s;
+    fiber_start(&l.fake, sched_bottom, sched_size);
     swapcontext(&l.ctx, &sched);
+    fiber_finish(l.fake, nullptr, nullptr);
   }
 
   static void entry();
@@ -122,7 +149,9 @@ struct Workgroup {
         if (lanes[t].state != READY) continue;
         cur = t;
         threadIdx = dim3(t);
+        fiber_start(&sched_fake, lanes[t].stack, kStackBytes);
         swapcontext(&sched, &lanes[t].ctx);
+        fiber_finish(sched_fake, nullptr, nullptr);
       }
       unsigned done = 0, at_block = 0;
       bool released = false;
@@ -157,8 +186,10 @@ thread_local Workgroup* t_wg = nullptr;
 
 void Workgroup::entry() {
   Workgroup* w = t_wg;
+  fiber_finish(nullptr, &w->sched_bottom, &w->sched_size);
   w->body();
   w->lanes[w->cur].state = DONE;
+  fiber_start(nullptr, w->sched_bottom, w->sched_size);  // this fiber ends here
 }
 
 }  // namespace

@@ -25,11 +25,45 @@ BUILD = os.path.join(HERE, "_build")
 # Optional numeric-policy override, e.g. "FLR_SUM_T=double,FLR_SOLVE_T=double"
 # (used to compare precision variants of the same sources).
 VARIANT = os.environ.get("FLR_EMU_VARIANT", "")
-SO = os.path.join(BUILD, "libflr_emu%s.so" % ("_" + VARIANT.replace("=", "-").replace(",", "_")
-                                              if VARIANT else ""))
+# FLR_EMU_SANITIZE=1: AddressSanitizer + UndefinedBehaviorSanitizer build of
+# the same sources (host code only: the kernels run on the host here), with
+# the ROCm LLVM clang++ as host compiler (GCC 11's UBSan instrumentation of
+# these sources gives wrong results without a report; clang's is clean); the
+# process that loads it needs the ASan runtime preloaded (sanitizer_env()).
+SANITIZE = os.environ.get("FLR_EMU_SANITIZE", "") == "1"
+SAN_CXX = "/opt/rocm/llvm/bin/clang++"
+SO = os.path.join(BUILD, "libflr_emu%s%s.so" % (
+    "_" + VARIANT.replace("=", "-").replace(",", "_") if VARIANT else "",
+    "_asan_ubsan" if SANITIZE else ""))
+# FLR_EMU_EXTRA: further compiler flags for a one-off build (named in the .so)
+EXTRA = os.environ.get("FLR_EMU_EXTRA", "").split()
+if EXTRA:
+    SO = SO[:-3] + "_x%08x.so" % (hash(" ".join(EXTRA)) & 0xffffffff)
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+             "-shared-libsan", "-fno-omit-frame-pointer"]
 
 sys.path.insert(0, ROOT)
 from paper_2410_11625_amd._lib import FlrParams  # noqa: E402  (ctypes struct layout only)
+
+
+def sanitizer_env() -> dict:
+    """Environment of a subprocess that loads the sanitizer build: the ASan
+    runtime preloaded into the (uninstrumented) Python process, leak
+    checking off (the interpreter's own allocations), every report fatal."""
+    asan = subprocess.run([SAN_CXX, "-print-file-name=libclang_rt.asan-x86_64.so"],
+                          stdout=subprocess.PIPE, text=True, check=True).stdout.strip()
+    if not os.path.isabs(asan):
+        import glob
+        asan = sorted(glob.glob(os.path.join(os.path.dirname(os.path.dirname(SAN_CXX)), "lib",
+                                             "clang", "*", "lib", "linux",
+                                             "libclang_rt.asan-x86_64.so")))[-1]
+    env = dict(os.environ)
+    env["FLR_EMU_SANITIZE"] = "1"
+    env["LD_PRELOAD"] = asan
+    env["ASAN_OPTIONS"] = ("detect_leaks=0:abort_on_error=1:detect_stack_use_after_return=0:"
+                           "clear_shadow_mmap_threshold=1048576")
+    env["UBSAN_OPTIONS"] = "halt_on_error=1:print_stacktrace=1"
+    return env
 
 
 def build(force: bool = False) -> str:
@@ -56,10 +90,27 @@ def build(force: bool = False) -> str:
             return SO
         defs = [f"-D{d}" for d in VARIANT.split(",") if d]
         tmp = f"{SO}.tmp{os.getpid()}"
-        cmd = ["g++", "-std=c++20", "-O1", "-g", "-pthread", "-fno-extern-tls-init", "-shared",
-               "-fPIC", *defs, f"-I{HERE}", f"-I{INCLUDE}", f"-I{CSRC}", *srcs, "-x", "c++",
-               net_src, adj_src, lr_src, "-o", tmp]
-        subprocess.run(cmd, check=True)
+        cxx = SAN_CXX if SANITIZE else os.environ.get("FLR_EMU_CXX", "g++")
+        tls = [] if "clang" in os.path.basename(cxx) else ["-fno-extern-tls-init"]
+        # the sanitizer build compiles unoptimised (minutes faster to build;
+        # its cases are small)
+        opt = ["-O0", "-g1"] if SANITIZE else ["-O1", "-g"]
+        flags = [cxx, "-std=c++20", *opt, "-pthread", *tls, "-fPIC", *defs,
+                 *(SAN_FLAGS if SANITIZE else []), *EXTRA, f"-I{HERE}", f"-I{INCLUDE}",
+                 f"-I{CSRC}"]
+        units = srcs + [net_src, adj_src, lr_src]
+        objs = [f"{tmp}.{i}.o" for i in range(len(units))]
+
+        def compile_unit(i):
+            subprocess.run([*flags, "-x", "c++", "-c", units[i], "-o", objs[i]], check=True)
+
+        import concurrent.futures as cf
+        with cf.ThreadPoolExecutor(max_workers=len(units)) as ex:
+            list(ex.map(compile_unit, range(len(units))))
+        link = [cxx, "-shared", "-pthread", *(SAN_FLAGS if SANITIZE else []), *objs, "-o", tmp]
+        subprocess.run(link, check=True)
+        for o in objs:
+            os.remove(o)
         os.replace(tmp, SO)
     return SO
 
@@ -342,6 +393,29 @@ def run_case(spec: dict) -> dict:
     H, W, Q, C, r = spec["H"], spec["W"], spec["Q"], spec["C"], spec["r"]
     emu = Emu()
     try:
+        if kind == "abi_checks":
+            # the host dispatcher's argument checks on invalid calls (no launch)
+            L = emu.L
+            vp = ctypes.c_void_p
+            P = ctypes.POINTER(FlrParams)
+            L.flr_validate_params.argtypes = [P]
+            L.flr_validate_params.restype = ctypes.c_int
+            codes = []
+            for field, value in [("height", 0), ("width", 40000), ("radius", -1),
+                                 ("radius", 99), ("eps", float("nan")), ("eps", -1.0),
+                                 ("num_guides", 0), ("num_guides", 99), ("num_channels", 9),
+                                 ("reg_mode", 7), ("fused", 5), ("average_coeffs", 3),
+                                 ("tile_rows", -2)]:
+                p = params(8, 8, 2, 1, 2)
+                setattr(p, field, value)
+                codes.append(int(L.flr_validate_params(ctypes.byref(p))))
+            p = params(8, 8, 2, 1, 2, fused=2)
+            gp, _ = emu.buf(shape=(2, 8, 8))
+            yp, _ = emu.buf(shape=(1, 8, 8))
+            codes.append(int(L.flr_denoise(ctypes.byref(p), gp, yp, gp, None, 0, None)))
+            codes.append(int(L.flr_denoise(ctypes.byref(p), None, yp, yp, None, 0, None)))
+            codes.append(int(L.flr_denoise(ctypes.byref(p), gp + 4, yp, yp, None, 0, None)))
+            return {"codes": codes}
         if kind == "raw_moments":
             fr = small_integer_frame(H, W, Q, C, seed=spec.get("seed", 0))
             p = params(H, W, Q, C, r, raw=True, tile_rows=spec.get("tile_rows", 0))
@@ -512,10 +586,15 @@ def run_case(spec: dict) -> dict:
         emu.close()
 
 
-def run_in_subprocess(spec: dict, timeout: float = 600.0) -> dict:
+def run_in_subprocess(spec: dict, timeout: float = 600.0, sanitize: bool = False) -> dict:
+    env = None
+    if sanitize:
+        env = sanitizer_env()
+        subprocess.run([sys.executable, "-c", "from tests.cpu_emu import harness; "
+                        "harness.build()"], check=True, cwd=ROOT, env=dict(env, LD_PRELOAD=""))
     res = subprocess.run([sys.executable, os.path.abspath(__file__), json.dumps(spec)],
                          stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True,
-                         timeout=timeout, cwd=ROOT)
+                         timeout=timeout, cwd=ROOT, env=env)
     if res.returncode != 0:
         raise RuntimeError(f"emulated case {spec} failed (rc={res.returncode}):\n"
                            f"{res.stdout[-2000:]}\n{res.stderr[-4000:]}")

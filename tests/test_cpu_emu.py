@@ -22,6 +22,8 @@ CASES = [
     # several strips and segments, workload-like frames
     dict(kind="both", H=30, W=500, Q=4, C=1, r=8, tile_rows=7, frame="config", config=0),
     dict(kind="both", H=41, W=260, Q=8, C=3, r=8, tile_rows=9, frame="config", config=1),
+    # windows of near-constant guides: an FP32 factorisation erred by 1.9e-4 here
+    dict(kind="both", H=40, W=270, Q=8, C=3, r=8, tile_rows=7, frame="config", config=1),
     # no averaging, Appendix regulariser
     dict(kind="both", H=33, W=250, Q=3, C=2, r=5, average=0, tile_rows=6),
     # 80 moment channels: the two-pass path splits the walk into two slices

@@ -96,6 +96,20 @@ def test_config1_crop(cfg1_crop, fused, tile_rows):
     assert rel_err(got, cfg1_crop["ref"]) <= TOL
 
 
+@pytest.mark.parametrize("H,W,seed", [(16, 270, 1), (24, 270, 1), (40, 270, 1), (40, 270, 7),
+                                       (64, 300, 3), (33, 600, 5), (90, 256, 11)])
+def test_config1_scenes(H, W, seed):
+    """RGB workload scenes of several sizes and seeds, each a different
+    random layout of regions, albedo cells and fireflies; windows of
+    near-constant guides make several local systems ill-conditioned at
+    eps 1e-3 (an FP32 factorisation erred by up to 1.9e-4 on these)."""
+    fr = make_config(1, seed=seed, h=H, w=W)
+    want = ref.flr_reference(fr["noisy"], fr["guides"], 8, 1e-3)
+    for fused in PATHS:
+        got = gpu_denoise(fr, 8, 1e-3, fused=fused)
+        assert rel_err(got, want) <= TOL, (fused, rel_err(got, want))
+
+
 def test_config1_stages(cfg1_crop):
     fr = cfg1_crop
     g, y = _t(fr["guides"]), _t(fr["noisy"])
