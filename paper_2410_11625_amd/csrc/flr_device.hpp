@@ -822,27 +822,27 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs ain) {
         for (int m0 = 0; m0 < gn; m0 += IL) {
           sum_t x[IL];
           if (VL) {
-            // previous row's sums from its prefixes (own and left lanes of
-            // the segment are in this wavefront, whose reads precede its
-            // writes), then this row's update
+            // The segment prefix of the vertical sums telescopes: this row's
+            // prefix is the previous row's (own column, read one chunk
+            // ahead) plus the segment prefix of this row's change.
 #pragma unroll
             for (int i = 0; i < IL; ++i) x[i] = nx[i];
 #pragma unroll
             for (int i = 0; i < IL; ++i)
               nx[i] = m0 + IL + i < gn ? P[(m0 + IL + i) * kLdsStride + tid] : sum_t(0);
             __builtin_amdgcn_sched_barrier(0);
-            sum_t lf[IL];
-#pragma unroll
-            for (int i = 0; i < IL; ++i) lf[i] = seg_left<WIDE>(x[i]);
             sum_t dl[IL];  // this row's change of the chunk's channels
             group_deltas<Q, C, IL, POFF, PC>(g0 + m0, gn - m0 < IL ? gn - m0 : IL, ga, yA, gs, yS, dl);
 #pragma unroll
-            for (int i = 0; i < IL; ++i) x[i] = m0 + i < gn ? (x[i] - lf[i]) + dl[i] : sum_t(0);
+            for (int i = 0; i < IL; ++i) dl[i] = m0 + i < gn ? dl[i] : sum_t(0);
+            seg_prefix_n<WIDE>(dl);
+#pragma unroll
+            for (int i = 0; i < IL; ++i) x[i] += dl[i];
           } else {
 #pragma unroll
             for (int i = 0; i < IL; ++i) x[i] = m0 + i < gn ? V[g0 + m0 + i] : sum_t(0);
+            seg_prefix_n<WIDE>(x);
           }
-          seg_prefix_n<WIDE>(x);
 #pragma unroll
           for (int i = 0; i < IL; ++i)
             if (m0 + i < gn) P[(m0 + i) * kLdsStride + tid] = x[i];
