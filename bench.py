@@ -343,10 +343,12 @@ def time_lowres(flr, torch, np, sets, nsets, dev, stream, args):
 def time_batch(flr, torch, np, sets, nsets, dev, stream, args):
     """Batched serving of 16 frames: 4 at 1280x720, 6 at 1920x1080, 4 at
     2560x1440 and 2 joint 1920x1080 frames from 960x540 noisy inputs (2x
-    upsampling), 8 guides + constant, r 8, eps 1e-3. Segment lengths from
-    the autotuner; the batch (one launch per stage) captured in a HIP graph
-    and replayed. Frames of one size are shifted copies of one synthetic
-    frame (distinct memory, same statistics)."""
+    upsampling), 8 guides + constant, r 8, eps 1e-3. Walk segment lengths,
+    averaging tile heights and the batch schedule (one persistent launch or
+    one launch per stage) from the autotuner; the batch captured in a HIP
+    graph and replayed; the other schedules and the planner's own choices
+    are timed beside it. Frames of one size are shifted copies of one
+    synthetic frame (distinct memory, same statistics)."""
     from paper_2410_11625_amd import autotune
     from synth import make_config
 
@@ -370,42 +372,62 @@ def time_batch(flr, torch, np, sets, nsets, dev, stream, args):
     for k in range(2):
         frames.append(dict(guides=sets[k][1], guides_low=glo.roll(k, dims=2).contiguous(),
                            noisy=ylo.roll(k, dims=2).contiguous()))
-    frames = autotune.tune_frames(frames, radius=R, eps=EPS)
-    b = flr.Batch(frames, radius=R, eps=EPS)
-    for _ in range(3):
-        b.run()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.batch_steps):
-        b.run()
-    e1.record()
-    torch.cuda.synchronize()
-    eager_ms = e0.elapsed_time(e1) / args.batch_steps
-    g = torch.cuda.CUDAGraph()
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        b.run()
-    torch.cuda.current_stream().wait_stream(side)
-    torch.cuda.synchronize()
-    with torch.cuda.graph(g):
-        b.run()
-    g.replay()
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(args.batch_steps):
+    tuned = autotune.tune_frames(frames, radius=R, eps=EPS)
+    sched = autotune.tune_batch(tuned, radius=R, eps=EPS)
+
+    def timed(fs, blocks, graph):
+        b = flr.Batch(fs, radius=R, eps=EPS, persistent_blocks=blocks)
+        for _ in range(3):
+            b.run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        if not graph:
+            e0.record()
+            for _ in range(args.batch_steps):
+                b.run()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / args.batch_steps, b
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            b.run()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            b.run()
         g.replay()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.batch_steps
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.batch_steps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.batch_steps, b
+
+    ms, b = timed(tuned, sched["persistent_blocks"], True)
+    eager_ms, _ = timed(tuned, sched["persistent_blocks"], False)
+    persistent_ms, pb = timed(tuned, None, True)
+    per_stage_ms, _ = timed(tuned, 0, True)
+    untuned_ms, _ = timed(frames, 0, True)
     pix = sum(int(f["guides"].shape[1]) * int(f["guides"].shape[2]) for f in frames)
-    rows = {f"{f['noisy'].shape[1]}x{f['noisy'].shape[2]}": f["tile_rows"] for f in frames}
+    rows = {f"{f['noisy'].shape[1]}x{f['noisy'].shape[2]}": [f["tile_rows"], f["apply_rows"]]
+            for f in tuned}
     return {"ms_per_batch": round(ms, 5), "value": round(pix / (ms / 1e3) / 1e6, 2),
             "unit": "Mpixel/s", "frames": len(frames), "output_pixels": pix,
-            "eager_ms_per_batch": round(eager_ms, 5), "tile_rows": rows,
+            "us_per_mpixel": round(ms * 1e3 / (pix / 1e6), 1),
+            "eager_ms_per_batch": round(eager_ms, 5),
+            "schedule": "persistent" if sched["persistent_blocks"] else "per_stage",
+            "persistent_ms_per_batch": round(persistent_ms, 5),
+            "persistent_workgroups": int(pb.plan.persistent_blocks),
+            "persistent_items": int(pb.plan.num_items),
+            "per_stage_ms_per_batch": round(per_stage_ms, 5),
+            "planner_schedule_ms_per_batch": round(untuned_ms, 5),
+            "tile_rows_apply_rows": rows,
             "config": "4x1280x720 + 6x1920x1080 + 4x2560x1440 + 2 joint 1920x1080 from "
-                      "960x540 (2x), 8 guides + constant, r 8, eps 1e-3; graph replay",
+                      "960x540 (2x), 8 guides + constant, r 8, eps 1e-3; graph replay of the "
+                      "tuned schedule",
             "steps": args.batch_steps}
 
 

@@ -235,6 +235,9 @@ typedef struct {
   int32_t height, width;              /* output grid, and the guides' */
   int32_t noisy_height, noisy_width;  /* the noisy input's grid */
   int32_t tile_rows;                  /* rows per workgroup of the coefficient walk; 0 = planned */
+  int32_t apply_rows;                 /* rows per workgroup of the averaging (at most 17); 0 =
+                                         as tile_rows (flr_denoise's choice: same tiles, same
+                                         results bit for bit) */
   const float* guides;                /* [Q][height][width] */
   const float* guides_low;            /* joint frames: [Q][noisy_height][noisy_width]; else NULL */
   const float* noisy;                 /* [C][noisy_height][noisy_width] */
@@ -248,10 +251,17 @@ typedef struct {
   flr_params params;
   int32_t num_frames, num_joint;
   int32_t coeff_blocks, apply_blocks, up_blocks;
+  int32_t persistent_blocks;          /* workgroups of the persistent launch (the plan sets
+                                         one per compute unit, at most num_items); 0 runs
+                                         one launch per stage instead. The caller may
+                                         change it between flr_batch_plan and flr_batch_run. */
+  int32_t num_items;                  /* work items of the persistent launch */
   void* walk_table;                   /* device: per-frame launch arguments of the walk */
   void* apply_table;                  /* device: ... of the averaging kernel (plain frames) */
   void* up_table;                     /* device: ... of the upsampling kernel (joint frames) */
-  int* walk_starts;                   /* device: workgroup offsets of the three launches */
+  int* walk_starts;                   /* device: workgroup offsets of the per-stage launches */
+  void* persistent_plan;              /* device: the persistent launch's stage table, launch
+                                         arguments, queue head and completion counters */
   /* joint frames, fitted on the noisy grid in FP64 */
   const float* joint_guides[FLR_BATCH_MAX]; /* the frame's guides_low */
   const float* joint_noisy[FLR_BATCH_MAX];  /* the frame's noisy input */
@@ -278,12 +288,28 @@ size_t flr_batch_workspace_bytes(const flr_params* p, const flr_frame* frames,
 flr_status flr_batch_plan(const flr_params* p, const flr_frame* frames, int32_t num_frames,
                           void* workspace, size_t workspace_bytes, flr_batch* plan);
 
-/* Runs a planned batch on `stream`: the coefficient walk over the plain
- * frames, their averaging and reconstruction; per joint frame the FP64
- * window sums, solve and window mean of the models; the upsampling and
- * reconstruction over the joint frames. Kernel launches only, so the call can be captured
- * in a HIP graph and replayed. */
+/* Runs a planned batch on `stream`. With plan->persistent_blocks > 0 (the
+ * default) it is ONE launch of that many persistent workgroups, which take
+ * work items in order from a device queue: the coefficient walk's tiles of
+ * every plain frame (largest frames first); per joint frame the tiles of
+ * its FP64 window sums, its per-pixel solve and the window mean of its
+ * models; the averaging and reconstruction tiles of the plain frames; the
+ * upsampling of the joint frames. An item waits (on device counters) only
+ * for the items it reads, all of which come earlier in the queue; a
+ * workgroup always finishes its item before taking the next, so every wait
+ * ends. The last workgroup to finish resets the queue and the counters, so
+ * the launch can be captured in a HIP graph and replayed (runs of one plan
+ * must not overlap). With persistent_blocks = 0: one launch per stage (the
+ * walk over all plain frames, their averaging, per joint frame its three
+ * FP64 stages, the upsampling). Kernel launches only, in both cases. */
 flr_status flr_batch_run(const flr_batch* plan, void* stream);
+
+/* Whether a persistent run of this plan gave up waiting for an item's
+ * inputs (a wait longer than about a second, which a correct run never
+ * has): *failed = 1 (kept until the plan is made again), else 0. A
+ * synchronous read of a device flag: call after the runs have completed.
+ * FLR_ERR_NULL for null pointers, FLR_ERR_HIP if the read fails. */
+flr_status flr_batch_failed(const flr_batch* plan, int32_t* failed);
 
 /* Static description of a status code. */
 const char* flr_status_str(flr_status s);

@@ -31,7 +31,7 @@ EXPORTED = ("flr_num_moment_planes", "flr_num_coeff_planes", "flr_denoise_worksp
             "flr_moments", "flr_solve", "flr_coefficients", "flr_apply", "flr_denoise",
             "flr_status_str", "flr_validate_params", "flr_denoise_backward_workspace_bytes",
             "flr_denoise_backward", "flr_lowres_workspace_bytes", "flr_denoise_lowres",
-            "flr_batch_workspace_bytes", "flr_batch_plan", "flr_batch_run",
+            "flr_batch_workspace_bytes", "flr_batch_plan", "flr_batch_run", "flr_batch_failed",
             # include/flr_net.h
             "flr_net_num_params", "flr_net_packed_bytes", "flr_net_pack", "flr_net_workspace_bytes",
             "flr_net_forward", "flr_net_backward_workspace_bytes", "flr_net_backward",
@@ -70,6 +70,7 @@ class FlrFrame(ctypes.Structure):
         ("noisy_height", ctypes.c_int32),
         ("noisy_width", ctypes.c_int32),
         ("tile_rows", ctypes.c_int32),
+        ("apply_rows", ctypes.c_int32),
         ("guides", ctypes.c_void_p),
         ("guides_low", ctypes.c_void_p),
         ("noisy", ctypes.c_void_p),
@@ -86,10 +87,13 @@ class FlrBatch(ctypes.Structure):
         ("coeff_blocks", ctypes.c_int32),
         ("apply_blocks", ctypes.c_int32),
         ("up_blocks", ctypes.c_int32),
+        ("persistent_blocks", ctypes.c_int32),
+        ("num_items", ctypes.c_int32),
         ("walk_table", ctypes.c_void_p),
         ("apply_table", ctypes.c_void_p),
         ("up_table", ctypes.c_void_p),
         ("walk_starts", ctypes.c_void_p),
+        ("persistent_plan", ctypes.c_void_p),
         ("joint_guides", ctypes.c_void_p * FLR_BATCH_MAX),
         ("joint_noisy", ctypes.c_void_p * FLR_BATCH_MAX),
         ("joint_sums", ctypes.c_void_p * FLR_BATCH_MAX),
@@ -157,6 +161,8 @@ def lib() -> ctypes.CDLL:
     L.flr_batch_plan.restype = ctypes.c_int
     L.flr_batch_run.argtypes = [Bp, vp]
     L.flr_batch_run.restype = ctypes.c_int
+    L.flr_batch_failed.argtypes = [Bp, ctypes.POINTER(ctypes.c_int32)]
+    L.flr_batch_failed.restype = ctypes.c_int
     L.flr_net_num_params.restype = ctypes.c_size_t
     L.flr_net_packed_bytes.restype = ctypes.c_size_t
     L.flr_net_pack.argtypes = [vp, vp, vp]

@@ -219,15 +219,16 @@ def denoise_lowres(noisy: torch.Tensor, guides: torch.Tensor, block: int = 8,
 
 
 class Batch:
-    """Frames of uneven size through the two-pass path, each stage one
-    launch over all frames. ``frames``: dicts with ``guides`` [Q,H,W] and
-    ``noisy`` [C,h,w] (h, w = H, W, or H/up, W/up for a joint frame, which
-    then also gives ``guides_low`` [Q,h,w]); optional ``out`` [C,H,W] and
-    ``tile_rows``. ``run()`` only launches kernels (graph-capturable); the
-    plan and its workspace stay with the object."""
+    """Frames of uneven size through the two-pass path: one persistent
+    launch over a work queue of every frame's tiles (``persistent_blocks``
+    workgroups; 0 = one launch per stage). ``frames``: dicts with ``guides``
+    [Q,H,W] and ``noisy`` [C,h,w] (h, w = H, W, or H/up, W/up for a joint
+    frame, which then also gives ``guides_low`` [Q,h,w]); optional ``out``
+    [C,H,W], ``tile_rows`` and ``apply_rows``. ``run()`` only launches kernels
+    (graph-capturable); the plan and its workspace stay with the object."""
 
     def __init__(self, frames, radius: int = 8, eps: float = 1e-3, mode: str = "ridge",
-                 eps_mul: float = 0.0):
+                 eps_mul: float = 0.0, persistent_blocks: int | None = None):
         if not 1 <= len(frames) <= FLR_BATCH_MAX:
             raise ValueError(f"1..{FLR_BATCH_MAX} frames")
         Q = frames[0]["guides"].shape[0]
@@ -253,6 +254,7 @@ class Batch:
             self._keep += [g, y, out] + ([low] if low is not None else [])
             arr[i] = FlrFrame(height=g.shape[1], width=g.shape[2], noisy_height=y.shape[1],
                               noisy_width=y.shape[2], tile_rows=int(f.get("tile_rows", 0)),
+                              apply_rows=int(f.get("apply_rows", 0)),
                               guides=g.data_ptr(),
                               guides_low=low.data_ptr() if low is not None else None,
                               noisy=y.data_ptr(), out=out.data_ptr())
@@ -268,7 +270,17 @@ class Batch:
         check(lib().flr_batch_plan(ctypes.byref(self.params), arr, len(frames),
                                    self.workspace.data_ptr(), need, ctypes.byref(self.plan)),
               "flr_batch_plan")
+        if persistent_blocks is not None:
+            self.plan.persistent_blocks = int(persistent_blocks)
         self.device = dev
+
+    def failed(self) -> bool:
+        """Whether a persistent run gave up waiting (synchronises first)."""
+        torch.cuda.synchronize(self.device)
+        flag = ctypes.c_int32(0)
+        check(lib().flr_batch_failed(ctypes.byref(self.plan), ctypes.byref(flag)),
+              "flr_batch_failed")
+        return bool(flag.value)
 
     def run(self):
         check(lib().flr_batch_run(ctypes.byref(self.plan),

@@ -159,9 +159,11 @@ flr_status validate_lowres(const flr_params* p, int block, float sigma, int radi
 // Workspace of a batch: the launch tables, then per frame its coefficient
 // image on the noisy grid, then per joint frame its averaged coefficients.
 struct BatchLayout {
-  // coef: a plain frame's coefficient image, or a joint frame's FP64 sums
-  size_t walk, apply, up, starts, coef[FLR_BATCH_MAX], models[FLR_BATCH_MAX],
-      mean[FLR_BATCH_MAX], total;
+  // coef: a plain frame's coefficient image, or a joint frame's FP64 sums;
+  // the persistent launch's tables: launch arguments (largs), box-pass
+  // arguments (bargs), stages, its header (pdev), control words and counters
+  size_t walk, apply, up, starts, largs, bargs, stages, pdev, ctl, counters, ncounters,
+      coef[FLR_BATCH_MAX], models[FLR_BATCH_MAX], mean[FLR_BATCH_MAX], total;
 };
 
 bool frame_is_joint(const flr_frame& f) { return f.guides_low != nullptr; }
@@ -183,6 +185,21 @@ BatchLayout batch_layout(const flr_params* p, const flr_frame* frames, int n) {
   o += al(n * sizeof(LaunchArgs));
   L.starts = o;
   o += al(3 * (n + 1) * sizeof(int));
+  L.largs = o;
+  o += al(4 * n * sizeof(LaunchArgs));
+  L.bargs = o;
+  o += al(2 * n * sizeof(flr::AdjBoxArgs));
+  L.stages = o;
+  o += al(4 * n * sizeof(flr::BatchStage));
+  L.pdev = o;
+  o += al(sizeof(flr::BatchPlanDev));
+  L.ctl = o;
+  o += al(4 * sizeof(int));
+  // at most one counter per row of each frame's walk, three per joint frame
+  L.ncounters = 3 * (size_t)n;
+  for (int i = 0; i < n; ++i) L.ncounters += (size_t)frames[i].noisy_height;
+  L.counters = o;
+  o += al(L.ncounters * sizeof(int));
   const size_t ns1 = 1 + (size_t)flr::num_sums(p->num_guides, p->num_channels);
   for (int i = 0; i < n; ++i) {
     const size_t px = (size_t)frames[i].noisy_height * frames[i].noisy_width;
@@ -218,7 +235,8 @@ flr_status validate_batch(const flr_params* p, const flr_frame* frames, int n) {
     q.height = f.height;
     q.width = f.width;
     if ((st = flr_validate_params(&q)) != FLR_OK) return st;
-    if (f.noisy_height < 1 || f.noisy_width < 1 || f.tile_rows < 0) return FLR_ERR_SHAPE;
+    if (f.noisy_height < 1 || f.noisy_width < 1 || f.tile_rows < 0 || f.apply_rows < 0)
+      return FLR_ERR_SHAPE;
     if (frame_is_joint(f)) {
       const int up = frame_up(f);
       if ((up != 2 && up != 4 && up != 8) || f.height != up * f.noisy_height ||
@@ -610,7 +628,9 @@ flr_status flr_batch_plan(const flr_params* p, const flr_frame* frames, int32_t 
     const flr_frame& f = frames[i];
     q.height = f.height;
     q.width = f.width;
-    q.tile_rows = f.tile_rows;  // as flr_denoise: the segment length of both kernels
+    // as flr_denoise: the segment length of both kernels, unless the frame
+    // sets the averaging tiles itself
+    q.tile_rows = f.apply_rows > 0 ? f.apply_rows : f.tile_rows;
     LaunchArgs a = base_args(&q);
     a.guides = f.guides;
     a.out = f.out;
@@ -639,7 +659,116 @@ flr_status flr_batch_plan(const flr_params* p, const flr_frame* frames, int32_t 
       ++nj;
     }
   }
-  // tables: launch arguments, then the three workgroup offset arrays
+  // The persistent launch: one table of launch arguments (the walks, in
+  // their sorted order, the averaging, the joint frames' solves and
+  // upsampling), the joint frames' box passes, and the stages in queue
+  // order: walks, joint sums, joint solves, joint means, averaging, upsampling.
+  static thread_local LaunchArgs largs[4 * FLR_BATCH_MAX];
+  static thread_local flr::AdjBoxArgs bargs[2 * FLR_BATCH_MAX];
+  static thread_local flr::BatchStage stages[4 * FLR_BATCH_MAX];
+  int nl = 0, nb = 0, nst = 0, nctr = 0, items = 0;
+  int walk_ctr[FLR_BATCH_MAX], inv[FLR_BATCH_MAX];
+  auto stage = [&](int kind, int arg, int count, int nx, int wait, int need, int done,
+                   int seg_rows, int nseg) {
+    stages[nst++] = flr::BatchStage{kind, arg, items, count, nx, wait, need, done, seg_rows,
+                                    nseg};
+    items += count;
+    return count;
+  };
+  for (int k = 0; k < nw; ++k) {
+    const LaunchArgs& a = walk_sorted[k];
+    inv[order[k]] = k;
+    largs[nl] = a;
+    walk_ctr[k] = nctr;
+    nctr += a.n_seg;
+    stage(flr::BI_WALK, nl++, a.tiles_x * a.n_seg, 0, -1, 0, walk_ctr[k], a.seg_rows, a.n_seg);
+  }
+  const int fc = (Q + 1) * C;
+  int jbox_items[FLR_BATCH_MAX], jsolve_items[FLR_BATCH_MAX], jmean_items[FLR_BATCH_MAX];
+  int jctr[FLR_BATCH_MAX], jbox_arg[FLR_BATCH_MAX], jmean_arg[FLR_BATCH_MAX];
+  for (int j = 0; j < nj; ++j) {
+    flr::AdjBoxArgs b = {};
+    b.guides = out_plan->joint_guides[j];
+    b.noisy = out_plan->joint_noisy[j];
+    b.dst = out_plan->joint_sums[j];
+    b.H = out_plan->joint_height[j];
+    b.W = out_plan->joint_width[j];
+    b.r = p->radius;
+    b.Q = Q;
+    b.C = C;
+    b.count_first = 1;
+    const int nx = flr::box_plan(b);
+    bargs[nb] = b;
+    jbox_arg[j] = nb++;
+    jctr[j] = nctr;
+    nctr += 3;
+    jbox_items[j] = stage(flr::BI_JBOX, jbox_arg[j], nx * (1 + flr::num_sums(Q, C)), nx, -1, 0,
+                          jctr[j], 0, 0);
+  }
+  for (int j = 0; j < nj; ++j) {
+    LaunchArgs a = base_args(p);
+    a.H = a.Hl = out_plan->joint_height[j];
+    a.W = a.Wl = out_plan->joint_width[j];
+    a.guides = out_plan->joint_guides[j];
+    a.fin = out_plan->joint_sums[j];
+    a.fout = out_plan->joint_models[j];
+    largs[nl] = a;
+    jsolve_items[j] = stage(flr::BI_JSOLVE, nl++, (int)(((int64_t)a.H * a.W + 255) / 256), 0,
+                            jctr[j], jbox_items[j], jctr[j] + 1, 0, 0);
+  }
+  for (int j = 0; j < nj; ++j) {
+    flr::AdjBoxArgs b = {};
+    b.src = out_plan->joint_models[j];
+    b.dst = out_plan->joint_mean[j];
+    b.count_first = 1;
+    b.H = out_plan->joint_height[j];
+    b.W = out_plan->joint_width[j];
+    b.r = p->radius;
+    const int nx = flr::box_plan(b);
+    bargs[nb] = b;
+    jmean_arg[j] = nb++;
+    jmean_items[j] = stage(flr::BI_JMEAN, jmean_arg[j], nx * fc, nx, jctr[j] + 1,
+                           jsolve_items[j], jctr[j] + 2, 0, 0);
+  }
+  for (int i = 0; i < np; ++i) {
+    const LaunchArgs& a = apply[i];
+    const LaunchArgs& w = walk_sorted[inv[i]];
+    largs[nl] = a;
+    stage(flr::BI_AVG, nl++, a.tiles_x * a.n_seg, 0, walk_ctr[inv[i]], w.tiles_x, -1,
+          w.seg_rows, w.n_seg);
+  }
+  for (int j = 0; j < nj; ++j) {
+    const LaunchArgs& a = up[j];
+    largs[nl] = a;
+    stage(flr::BI_UP, nl++, (int)(((int64_t)a.H * a.W + 255) / 256), 0, jctr[j] + 2,
+          jmean_items[j], -1, 0, 0);
+  }
+  flr::BatchPlanDev pd = {};
+  pd.stages = reinterpret_cast<const flr::BatchStage*>(ws + L.stages);
+  pd.nstages = nst;
+  pd.nitems = items;
+  pd.ncounters = nctr;
+  pd.largs = reinterpret_cast<const LaunchArgs*>(ws + L.largs);
+  pd.bargs = reinterpret_cast<const flr::AdjBoxArgs*>(ws + L.bargs);
+  pd.ctl = reinterpret_cast<int*>(ws + L.ctl);
+  pd.counters = reinterpret_cast<int*>(ws + L.counters);
+  if ((size_t)nctr > L.ncounters) return FLR_ERR_WORKSPACE;  // never: the layout's bound
+  if (hipMemcpy(ws + L.largs, largs, nl * sizeof(LaunchArgs), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      (nb && hipMemcpy(ws + L.bargs, bargs, nb * sizeof(flr::AdjBoxArgs),
+                       hipMemcpyHostToDevice) != hipSuccess) ||
+      hipMemcpy(ws + L.stages, stages, nst * sizeof(flr::BatchStage), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(ws + L.pdev, &pd, sizeof pd, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(ws + L.ctl, 0, 4 * sizeof(int)) != hipSuccess ||
+      hipMemset(ws + L.counters, 0, L.ncounters * sizeof(int)) != hipSuccess)
+    return FLR_ERR_HIP;
+  out_plan->num_items = items;
+  out_plan->persistent_blocks = items < flr::kCUs ? items : flr::kCUs;
+  out_plan->persistent_plan = ws + L.pdev;
+
+  // tables of the per-stage launches: launch arguments, then the three
+  // workgroup offset arrays
   int starts[3 * (FLR_BATCH_MAX + 1)];
   for (int k = 0; k <= n; ++k) {
     starts[k] = k <= nw ? ws_walk[k] : 0;
@@ -668,6 +797,17 @@ flr_status flr_batch_plan(const flr_params* p, const flr_frame* frames, int32_t 
   return FLR_OK;
 }
 
+flr_status flr_batch_failed(const flr_batch* b, int32_t* failed) {
+  if (!b || !failed || !b->persistent_plan) return FLR_ERR_NULL;
+  flr::BatchPlanDev pd;
+  int flag = 0;
+  if (hipMemcpy(&pd, b->persistent_plan, sizeof pd, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(&flag, pd.ctl + 2, sizeof flag, hipMemcpyDeviceToHost) != hipSuccess)
+    return FLR_ERR_HIP;
+  *failed = flag != 0;
+  return FLR_OK;
+}
+
 flr_status flr_batch_run(const flr_batch* b, void* stream) {
   if (!b || !b->walk_table) return FLR_ERR_NULL;
   const flr_params* p = &b->params;
@@ -677,6 +817,13 @@ flr_status flr_batch_run(const flr_batch* b, void* stream) {
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   flr_status st;
   LaunchArgs a = base_args(p);
+  if (b->persistent_blocks < 0) return FLR_ERR_MODE;
+  if (b->persistent_blocks > 0) {
+    if (!b->persistent_plan) return FLR_ERR_NULL;
+    a.bplan = static_cast<const flr::BatchPlanDev*>(b->persistent_plan);
+    a.batch_blocks = b->persistent_blocks;
+    return dispatch(Q, C, flr::K_BATCH_PERSISTENT, a, stream);
+  }
   if (np > 0) {
     a.frames = static_cast<const LaunchArgs*>(b->walk_table);
     a.wg_start = starts;

@@ -621,10 +621,10 @@ __device__ __forceinline__ const LaunchArgs& batch_frame(const LaunchArgs& ain, 
   return ain.frames[f];
 }
 
-template <int Q, int C, int MODE, bool WIDE, int POFF = 0, int PCNT = -1, bool BATCH = false>
-__global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs ain) {
-  int bid = blockIdx.x;
-  const LaunchArgs a = BATCH ? batch_frame(ain, &bid) : ain;
+// One workgroup's tile (strip sx = bid % tiles_x, segment bid / tiles_x) of
+// frame a.
+template <int Q, int C, int MODE, bool WIDE, int POFF = 0, int PCNT = -1>
+__device__ __forceinline__ void walk_tile(const LaunchArgs a, const int bid) {
   using D = Dims<Q, C>;
   using T = solve_t;
   constexpr int NPQ = D::NP + D::NQC;              // product channels
@@ -985,6 +985,13 @@ __global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs ain) {
   }
 }
 
+template <int Q, int C, int MODE, bool WIDE, int POFF = 0, int PCNT = -1, bool BATCH = false>
+__global__ void __launch_bounds__(kThreads, 1) walk_kernel(LaunchArgs ain) {
+  int bid = blockIdx.x;
+  const LaunchArgs a = BATCH ? batch_frame(ain, &bid) : ain;
+  walk_tile<Q, C, MODE, WIDE, POFF, PCNT>(a, bid);
+}
+
 // ---------------------------------------------------------------------------
 // flr_solve: one lane per pixel, central-moment planes -> coefficient planes.
 template <int Q, int C>
@@ -1058,10 +1065,8 @@ __host__ __device__ constexpr int avg_variant(int r, int C) {
   return (r == 8 && C <= 3) ? AV_BLOCK8 : (wide_segments(r) ? AV_STREAM64 : AV_STREAM16);
 }
 
-template <int Q, int C, int AV, bool BATCH = false>
-__global__ void __launch_bounds__(kThreads, 2) apply_avg_kernel(LaunchArgs ain) {
-  int bid = blockIdx.x;
-  const LaunchArgs a = BATCH ? batch_frame(ain, &bid) : ain;
+template <int Q, int C, int AV>
+__device__ __forceinline__ void apply_avg_tile(const LaunchArgs a, const int bid) {
   using T = solve_t;
   constexpr bool WIDE = AV == AV_STREAM64;
   constexpr int TH = kAvgTileRows;
@@ -1241,12 +1246,116 @@ __global__ void __launch_bounds__(kThreads, 2) apply_avg_kernel(LaunchArgs ain) 
   }
 }
 
+template <int Q, int C, int AV, bool BATCH = false>
+__global__ void __launch_bounds__(kThreads, 2) apply_avg_kernel(LaunchArgs ain) {
+  int bid = blockIdx.x;
+  const LaunchArgs a = BATCH ? batch_frame(ain, &bid) : ain;
+  apply_avg_tile<Q, C, AV>(a, bid);
+}
+
 }  // namespace flr
 
 #include "flr_adjoint.hpp"
+#include "flr_box.hpp"
 #include "flr_lowres.hpp"
 
 namespace flr {
+
+// ---------------------------------------------------------------------------
+// The persistent batch kernel (see BatchStage). Thread 0 takes the next item
+// and waits for what it depends on; the workgroup runs the item's tile
+// function; finished items bump their counter after a release fence. The
+// last workgroup to leave resets the queue and the counters for the next
+// run (no clearing launch, nothing recorded into a graph but this kernel).
+// Waits until *c >= need; gives up (false) after kBatchSpinLimit sleeps, or
+// at once when an earlier wait of the run has given up (*failed set), so
+// that a broken run ends instead of waiting once per item.
+__device__ __forceinline__ bool batch_wait(const int* c, int need, const int* failed) {
+  for (int k = 0; k < kBatchSpinLimit; ++k) {
+    if (__hip_atomic_load(c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= need) return true;
+    if (__hip_atomic_load(failed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return false;
+}
+
+template <int Q, int C, bool WIDE, int AV>
+__global__ void __launch_bounds__(kThreads, 1) batch_kernel(LaunchArgs ain) {
+  const BatchPlanDev* P = ain.bplan;
+  __shared__ int s_item, s_stage;
+  for (;;) {
+    __syncthreads();  // the previous item is done with LDS and s_item
+    if (threadIdx.x == 0) {
+      const int it = atomicAdd(&P->ctl[0], 1);
+      int st = -1;
+      if (it < P->nitems)
+        for (int k = 0; k < P->nstages; ++k)
+          if (it >= P->stages[k].first && it < P->stages[k].first + P->stages[k].count) st = k;
+      s_item = it;
+      s_stage = st;
+      if (st >= 0) {  // dependencies
+        const BatchStage& S = P->stages[st];
+        const int b = it - S.first;
+        bool ok = true;
+        if (S.kind == BI_AVG) {
+          const LaunchArgs& f = P->largs[S.arg];
+          const int y0 = (b / f.tiles_x) * f.seg_rows;
+          const int y1 = min(y0 + f.seg_rows, f.H);
+          const int s0 = max(y0 - f.r, 0) / S.seg_rows;
+          const int s1 = min((min(y1 + f.r, f.H) - 1) / S.seg_rows, S.nseg - 1);
+          for (int sg = s0; sg <= s1 && ok; ++sg)
+            ok = batch_wait(&P->counters[S.wait + sg], S.need, &P->ctl[2]);
+        } else if (S.wait >= 0) {
+          ok = batch_wait(&P->counters[S.wait], S.need, &P->ctl[2]);
+        }
+        if (!ok) atomicOr(&P->ctl[2], 1);
+      }
+    }
+    __syncthreads();
+    // uniform across the workgroup: scalar registers
+    const int st = __builtin_amdgcn_readfirstlane(s_stage);
+    if (st < 0) break;
+    // every lane sees the writes the item depends on
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const BatchStage S = P->stages[st];
+    const int b = __builtin_amdgcn_readfirstlane(s_item) - S.first;
+    switch (S.kind) {
+      case BI_WALK:
+        walk_tile<Q, C, W_COEFFS, WIDE>(P->largs[S.arg], b);
+        break;
+      case BI_JBOX:
+        box_tile<BOX_PRODUCTS>(P->bargs[S.arg], b % S.nx, b / S.nx);
+        break;
+      case BI_JSOLVE:
+        lr_solve_item<Q, C>(P->largs[S.arg], b);
+        break;
+      case BI_JMEAN:
+        box_tile<BOX_MEAN64>(P->bargs[S.arg], b % S.nx, b / S.nx);
+        break;
+      case BI_AVG:
+        apply_avg_tile<Q, C, AV>(P->largs[S.arg], b);
+        break;
+      default:
+        up_apply_item<Q, C>(P->largs[S.arg], b);
+        break;
+    }
+    if (S.done >= 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this lane's stores
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const int c = S.kind == BI_WALK ? S.done + b / P->largs[S.arg].tiles_x : S.done;
+        __hip_atomic_fetch_add(&P->counters[c], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+  if (threadIdx.x == 0) {
+    if (atomicAdd(&P->ctl[1], 1) == (int)gridDim.x - 1) {
+      for (int k = 0; k < P->ncounters; ++k) P->counters[k] = 0;
+      P->ctl[0] = 0;
+      P->ctl[1] = 0;
+    }
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Host-side launch of one kernel kind for a fixed (Q, C).
@@ -1365,6 +1474,23 @@ hipError_t launch_qc(int kind, const LaunchArgs& a, hipStream_t s) {
     case K_UP_APPLY_BATCH:
       hipLaunchKernelGGL((up_apply_kernel<Q, C, true>), dim3(a.batch_blocks), dim3(256), 0, s, a);
       return hipGetLastError();
+    case K_BATCH_PERSISTENT:
+      if constexpr (!split_walk(Q, C)) {
+        // LDS: the larger of the walk's and the averaging kernel's (the box
+        // passes need two FP64 rows)
+        const size_t l = lds_of(K_COEFFS) > lds_of(K_APPLY_AVG) ? lds_of(K_COEFFS)
+                                                                : lds_of(K_APPLY_AVG);
+        const int av = avg_variant(a.r, C);
+        if (av == AV_BLOCK8) {
+          if constexpr (C <= 3) return launch_with_lds(batch_kernel<Q, C, false, AV_BLOCK8>,
+                                                       a.batch_blocks, l, a, s);
+          return hipErrorInvalidValue;
+        }
+        if (av == AV_STREAM64)
+          return launch_with_lds(batch_kernel<Q, C, true, AV_STREAM64>, a.batch_blocks, l, a, s);
+        return launch_with_lds(batch_kernel<Q, C, false, AV_STREAM16>, a.batch_blocks, l, a, s);
+      }
+      return hipErrorInvalidValue;
     case K_LR_APPLY:
       if (a.lr_rows > 0) {
         const size_t l = lr_apply_lds_bytes(Q, C, a.block, a.lr_rows);

@@ -87,7 +87,69 @@ enum Kind : int {
   K_COEFFS_BATCH = 15,     // K_COEFFS over the tiles of several frames
   K_APPLY_AVG_BATCH = 16,  // K_APPLY_AVG over the tiles of several frames
   K_UP_APPLY_BATCH = 17,   // bilinear upsampling of coefficient planes + reconstruction
+  K_BATCH_PERSISTENT = 18, // every stage of a batch in one launch over a work queue
 };
+
+// One persistent launch for a batch (flr_batch_run): workgroups take items
+// from a queue counter in order; an item is one workgroup's tile of one
+// stage of one frame. Stages, in queue order: the coefficient walk of the
+// plain frames; per joint frame the FP64 window sums of its products, the
+// per-pixel solve and the window mean of the models; the averaging and
+// reconstruction of the plain frames; the upsampling of the joint frames.
+// An item only waits on items earlier in the queue (taken by workgroups
+// that are running), through counters that finished items increment.
+enum BatchItemKind : int {
+  BI_WALK = 0, BI_JBOX = 1, BI_JSOLVE = 2, BI_JMEAN = 3, BI_AVG = 4, BI_UP = 5
+};
+struct BatchStage {
+  int kind;      // BatchItemKind
+  int arg;       // index into the launch-argument table (largs) or, box passes, bargs
+  int first;     // first queue item of the stage
+  int count;     // its items
+  int nx;        // box passes: workgroups per plane
+  int wait;      // counter its items wait on (-1: none); BI_AVG: the frame's
+                 // first walk-segment counter
+  int need;      // the value that counter must reach (BI_AVG: strips per walk segment)
+  int done;      // counter a finished item increments (-1: none); BI_WALK: the
+                 // frame's first walk-segment counter (one per segment)
+  int seg_rows;  // BI_WALK, BI_AVG: rows per walk segment of the frame
+  int nseg;      // BI_AVG: walk segments of the frame
+};
+// Arguments of one box pass (flr_box.hpp).
+struct AdjBoxArgs {
+  const float* srcf;   // BOX_MEAN32: FP32 planes, averaged into dstf
+  float* dstf;
+  const double* src;   // FP64 planes, or NULL for the product channels below
+  const float* guides; // product channels: guides [Q][H][W]
+  const float* noisy;  // product channels: noisy [C][H][W]
+  double* dst;
+  int64_t plane;  // elements per plane
+  int H, W, r, seg_rows, tiles_x;
+  int Q, C;
+  int count_first;  // BOX_PRODUCTS: plane 0 is the window pixel count, channels follow
+};
+
+// Rows per workgroup segment of a box pass, and its tiling: sets plane,
+// seg_rows, tiles_x; returns the workgroups per plane.
+constexpr int kBoxSegRows = 64;
+inline int box_plan(AdjBoxArgs& a) {
+  a.plane = (int64_t)a.H * a.W;
+  a.seg_rows = kBoxSegRows < a.H ? kBoxSegRows : a.H;
+  a.tiles_x = (a.W + (kThreads - 2 * a.r) - 1) / (kThreads - 2 * a.r);
+  return a.tiles_x * ((a.H + a.seg_rows - 1) / a.seg_rows);
+}
+
+struct BatchPlanDev {
+  const BatchStage* stages;
+  int nstages, nitems, ncounters, pad;
+  const struct LaunchArgs* largs;
+  const AdjBoxArgs* bargs;
+  int* ctl;       // [0] queue head, [1] workgroups finished, [2] waits given up (kept)
+  int* counters;  // [ncounters]
+};
+// Longest wait of an item before it gives up and flags the run as failed
+// (iterations of a short sleep; far beyond any item's duration).
+constexpr int kBatchSpinLimit = 1 << 24;
 
 // Longest Gaussian of the downsampled-moment variant (taps -R..R).
 constexpr int kMaxLowresRadius = 8;
@@ -122,6 +184,7 @@ struct LaunchArgs {
   // and runs as workgroup b - wg_start[f] of frames[f]
   const struct LaunchArgs* frames;
   const int* wg_start;
+  const BatchPlanDev* bplan;  // K_BATCH_PERSISTENT
   int nframes;
   int batch_blocks;  // total workgroups of the launch
   int up;            // K_UP_APPLY: upsampling factor (coefficient grid = H / up)

@@ -137,11 +137,11 @@ __global__ void __launch_bounds__(256) lr_block_kernel(LaunchArgs a) {
 // Regularised solve of each low-resolution pixel from the blurred planes
 // (a.fin: count, then the channel sums) -> models b~ (C), a (Q*C) in a.fout.
 template <int Q, int C>
-__global__ void __launch_bounds__(256) lr_solve_kernel(LaunchArgs a) {
+__device__ __forceinline__ void lr_solve_item(const LaunchArgs a, const int bid) {
   using T = double;
   constexpr int NP = Dims<Q, C>::NP;
   const int64_t pll = (int64_t)a.Hl * a.Wl;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t idx = (int64_t)bid * 256 + threadIdx.x;
   if (idx >= pll) return;
   const int64_t pl = (int64_t)a.H * a.W;
   const double* S = a.fin + idx;
@@ -162,6 +162,10 @@ __global__ void __launch_bounds__(256) lr_solve_kernel(LaunchArgs a) {
   }
 #pragma unroll
   for (int k = 0; k < Q * C; ++k) o[(C + k) * pll] = R_[k];
+}
+template <int Q, int C>
+__global__ void __launch_bounds__(256) lr_solve_kernel(LaunchArgs a) {
+  lr_solve_item<Q, C>(a, blockIdx.x);
 }
 
 // Bilinear interpolation of the models at each full-resolution pixel
@@ -305,15 +309,13 @@ __global__ void __launch_bounds__(256) lr_apply_staged_kernel(LaunchArgs a) {
 // pixel (half-pixel centres, clamped) and applied to the full-resolution
 // guides with the anchors of the fit (pixel (0, 0) of the low-resolution
 // guides and of the noisy input). Batched over frames.
-template <int Q, int C, bool BATCH>
-__global__ void __launch_bounds__(256) up_apply_kernel(LaunchArgs ain) {
+template <int Q, int C>
+__device__ __forceinline__ void up_apply_item(const LaunchArgs a, const int bid) {
   using T = double;
   constexpr int FC = (Q + 1) * C;
-  int bid = blockIdx.x;
-  const LaunchArgs a = BATCH ? batch_frame(ain, &bid) : ain;
   const int64_t pl = (int64_t)a.H * a.W;
   const int64_t pll = (int64_t)a.Hl * a.Wl;
-  const int64_t idx = (int64_t)bid * blockDim.x + threadIdx.x;
+  const int64_t idx = (int64_t)bid * 256 + threadIdx.x;
   if (idx >= pl) return;
   const int i = (int)(idx / a.W), j = (int)(idx - (int64_t)i * a.W);
   int r0, r1, c0, c1;
@@ -340,6 +342,12 @@ __global__ void __launch_bounds__(256) up_apply_kernel(LaunchArgs ain) {
     for (int q = 0; q < Q; ++q) s = fma(m[C + q * C + c], g[q], s);
     a.out[c * pl + idx] = (float)s;
   }
+}
+template <int Q, int C, bool BATCH>
+__global__ void __launch_bounds__(256) up_apply_kernel(LaunchArgs ain) {
+  int bid = blockIdx.x;
+  const LaunchArgs a = BATCH ? batch_frame(ain, &bid) : ain;
+  up_apply_item<Q, C>(a, bid);
 }
 
 }  // namespace flr

@@ -74,7 +74,7 @@ def build(force: bool = False) -> str:
     deps = srcs + [net_src, adj_src, lr_src, os.path.join(HERE, "hip", "hip_runtime.h"),
                    os.path.join(CSRC, "flr_device.hpp"), os.path.join(CSRC, "flr_launch.hpp"),
                    os.path.join(CSRC, "flr_adjoint.hpp"), os.path.join(CSRC, "flr_lowres.hpp"),
-                   os.path.join(CSRC, "flr_net_bwd.hpp"),
+                   os.path.join(CSRC, "flr_net_bwd.hpp"), os.path.join(CSRC, "flr_box.hpp"),
                    os.path.join(INCLUDE, "flr.h"), os.path.join(INCLUDE, "flr_net.h")]
     def fresh():
         return os.path.exists(SO) and \
@@ -295,9 +295,11 @@ class Emu:
                                         need, None), "flr_denoise_lowres")
         return out.copy()
 
-    def batch(self, frames, p: FlrParams):
+    def batch(self, frames, p: FlrParams, persistent_blocks=None, runs=1):
         """flr_batch_plan + flr_batch_run over frames (dicts of guides, noisy,
-        optional guides_low) -> list of outputs."""
+        optional guides_low) -> list of outputs (of the last of `runs` runs;
+        with `persistent_blocks` set, the plan's persistent grid is replaced;
+        0 runs one launch per stage). Also sets self.batch_failed."""
         from paper_2410_11625_amd._lib import FlrBatch, FlrFrame
         L = self.L
         F = ctypes.POINTER(FlrFrame)
@@ -325,7 +327,16 @@ class Emu:
         plan = FlrBatch()
         self.check(L.flr_batch_plan(ctypes.byref(p), arr, len(frames), wp, need,
                                     ctypes.byref(plan)), "flr_batch_plan")
-        self.check(L.flr_batch_run(ctypes.byref(plan), None), "flr_batch_run")
+        if persistent_blocks is not None:
+            plan.persistent_blocks = persistent_blocks
+        for _ in range(runs):
+            for o in outs:
+                o[...] = np.nan
+            self.check(L.flr_batch_run(ctypes.byref(plan), None), "flr_batch_run")
+        L.flr_batch_failed.argtypes = [Bp, ctypes.POINTER(ctypes.c_int32)]
+        flag = ctypes.c_int32(0)
+        self.check(L.flr_batch_failed(ctypes.byref(plan), ctypes.byref(flag)), "flr_batch_failed")
+        self.batch_failed = bool(flag.value)
         return [o.copy() for o in outs]
 
     def moments(self, noisy, guides, p: FlrParams):
@@ -475,8 +486,13 @@ def run_case(spec: dict) -> dict:
             lo = make_config(1, seed=40, h=jh // up, w=jw // up)
             frames.append(dict(guides=hi["guides"], guides_low=lo["guides"], noisy=lo["noisy"]))
             p = params(1, 1, 8, 3, r, 1e-3, 0, 0.0, 1, 2)
-            got = emu.batch(frames, p)
-            res = {}
+            # the persistent launch (run twice: the queue and counters reset
+            # themselves), against one launch per stage, bit for bit
+            got = emu.batch(frames, p, persistent_blocks=spec.get("blocks"), runs=2)
+            res = {"persistent_not_failed": not emu.batch_failed}
+            per_stage = emu.batch(frames, p, persistent_blocks=0)
+            res["persistent_equals_stages"] = all(np.array_equal(a_, b_)
+                                                  for a_, b_ in zip(got, per_stage))
             # plain frames: the same kernels and plans as flr_denoise (two-pass)
             for k, f in enumerate(frames[:-1]):
                 h, w = f["guides"].shape[1:]

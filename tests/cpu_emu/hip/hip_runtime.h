@@ -5,6 +5,8 @@
 #pragma once
 
 #include <algorithm>
+#include <chrono>
+#include <thread>
 #include <cmath>
 #include <cstddef>
 #include <cstdint>
@@ -88,6 +90,7 @@ inline __amdgpu_buffer_rsrc_t __builtin_amdgcn_make_buffer_rsrc(void* p, short s
 unsigned __builtin_amdgcn_raw_buffer_load_b32(__amdgpu_buffer_rsrc_t r, int vo, int so, int aux);
 
 inline void __builtin_amdgcn_sched_barrier(int) {}
+inline int __builtin_amdgcn_readfirstlane(int v) { return v; }
 
 // v_mfma_f32_16x16x16_bf16 of a 64-lane wavefront: D = C + A B with A 16x16
 // (lane l: row l%16, k = 4*(l/16)..+3), B 16x16 (lane l: k = 4*(l/16)..+3,
@@ -113,11 +116,28 @@ typedef void* hipStream_t;
 enum hipFuncAttribute { hipFuncAttributeMaxDynamicSharedMemorySize = 0 };
 inline hipError_t hipFuncSetAttribute(const void*, hipFuncAttribute, int) { return hipSuccess; }
 hipError_t hipGetLastError();
-enum hipMemcpyKind { hipMemcpyHostToDevice = 1 };
+enum hipMemcpyKind { hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2 };
 inline hipError_t hipMemcpy(void* dst, const void* src, size_t n, hipMemcpyKind) {
   std::memcpy(dst, src, n);
   return hipSuccess;
 }
+inline hipError_t hipMemset(void* dst, int v, size_t n) {
+  std::memset(dst, v, n);
+  return hipSuccess;
+}
+// Device atomics and fences of the persistent kernels: workgroups run on
+// several host threads, so these are real (sequentially consistent) atomics.
+#define __HIP_MEMORY_SCOPE_AGENT 3
+inline int atomicAdd(int* p, int v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
+inline int atomicOr(int* p, int v) { return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST); }
+inline int __hip_atomic_load(const int* p, int, int) { return __atomic_load_n(p, __ATOMIC_SEQ_CST); }
+inline int __hip_atomic_fetch_add(int* p, int v, int, int) {
+  return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST);
+}
+inline void __builtin_amdgcn_fence(int, const char*) { __atomic_thread_fence(__ATOMIC_SEQ_CST); }
+// a short real sleep: emulated workgroups are slow, and a spin-wait's
+// iteration limit must outlast them
+inline void __builtin_amdgcn_s_sleep(int) { std::this_thread::sleep_for(std::chrono::microseconds(20)); }
 
 // Runs a kernel over the grid on host threads (defined by the emulator):
 // `tramp(kernel, arg)` executes one lane.

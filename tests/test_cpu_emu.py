@@ -137,20 +137,25 @@ def test_emulated_lowres_matches_oracle(spec):
     assert res["rel"] <= 1e-6, res
 
 
-# Batched serving: plain frames of uneven size in one launch per stage must
-# equal flr_denoise (two-pass) frame by frame, bit for bit (same kernels,
-# same tiles); a joint frame (noisy input and guides on a grid `up` times
-# coarser) against the oracle's low-resolution fit, window-averaged and
-# bilinearly upsampled, with the FP32 eps the ABI carries.
+# Batched serving: plain frames of uneven size must equal flr_denoise
+# (two-pass) frame by frame, bit for bit (same tile functions, same tiles);
+# a joint frame (noisy input and guides on a grid `up` times coarser)
+# against the oracle's low-resolution fit, window-averaged and bilinearly
+# upsampled, with the FP32 eps the ABI carries. The persistent launch (a
+# work queue over every stage's tiles, run twice) must equal one launch per
+# stage bit for bit and report no failed wait; with fewer workgroups than
+# compute units too (items wait on items other workgroups took).
 @pytest.mark.parametrize("spec", [
     dict(kind="batch", H=0, W=0, Q=8, C=3, r=8, sizes=[[20, 280], [25, 70], [1, 260]],
          joint=[32, 300]),
     dict(kind="batch", H=0, W=0, Q=8, C=3, r=8, sizes=[[33, 270]], joint=[64, 600], up=4,
          tile_rows=7),
-], ids=["three-plain-one-joint", "tile7-joint-up4"])
+    dict(kind="batch", H=0, W=0, Q=8, C=3, r=8, sizes=[[40, 530], [9, 30]], joint=[24, 40],
+         tile_rows=5, blocks=3),
+], ids=["three-plain-one-joint", "tile7-joint-up4", "three-workgroups"])
 def test_emulated_batch(spec):
     res = run_in_subprocess(spec)
     for k, v in res.items():
-        if k.endswith("_equal"):
+        if k.endswith("_equal") or k.startswith("persistent_"):
             assert v, (k, res)
     assert res["joint_rel"] <= 1e-6, res

@@ -11,6 +11,10 @@
   it, and those on coarse inputs within 2r, so a 2r + 2 coarse margin is
   exact.
 * The run is captured in a graph and replayed, each replay checked.
+* The run is one persistent launch over a work queue; it must equal one
+  launch per stage bit for bit, with the default grid and with a few
+  workgroups (items then wait on items other workgroups took), and report
+  no failed wait.
 * The autotuner's schedule changes tiles, not results.
 """
 import numpy as np
@@ -111,6 +115,23 @@ def test_batch_graph_replay():
             assert torch.equal(o, e)
 
 
+@pytest.mark.parametrize("blocks", [None, 7])
+def test_persistent_equals_per_stage(blocks):
+    frames = [_plain(150, 700, 11), _plain(40, 1100, 12), _plain(9, 300, 13),
+              _joint(80, 600, 2, 14)[0]]
+    per_stage = [o.clone() for o in flr.Batch(frames, persistent_blocks=0).run()]
+    b = flr.Batch(frames, persistent_blocks=blocks)
+    assert b.plan.num_items > 0 and b.plan.persistent_blocks > 0
+    for _ in range(2):  # the second run starts from the queue the first reset
+        for o in b.outs:
+            o.fill_(float("nan"))
+        outs = b.run()
+        torch.cuda.synchronize()
+        for o, e in zip(outs, per_stage):
+            assert torch.equal(o, e)
+    assert not b.failed()
+
+
 def test_workload_sizes_sampled():
     """The serving workload's frame sizes (720p, 1080p, 1440p and a joint
     1080p frame from 960x540): plain frames against flr_denoise, the joint
@@ -127,12 +148,29 @@ def test_workload_sizes_sampled():
         assert _rel(got[:, y0:y1, x0:x1], _joint_oracle(hi, lo, 2, crop=crop)) <= 1e-6
 
 
-def test_autotuned_schedule():
+def test_autotuned_schedule(tmp_path, monkeypatch):
+    """The tuner's schedules (walk segment length, averaging tile height,
+    batch launch schedule) change tiles, not what is computed: the batch
+    equals the coefficient walk and the averaging run with the same tiles,
+    bit for bit; the choices are persisted in the JSON cache and reused."""
     from paper_2410_11625_amd import autotune
+    monkeypatch.setenv("FLR_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    monkeypatch.setattr(autotune, "_MEM", {})
     rows, times = autotune.tune_tile_rows(200, 700, reps=2)
     assert rows in autotune.candidate_rows(200) and rows in times
     frames = autotune.tune_frames([_plain(200, 700, 9), _plain(120, 300, 10)])
-    outs = flr.Batch(frames).run()
+    sched = autotune.tune_batch(frames, reps=2)
+    assert sched["persistent_blocks"] >= 0 and len(sched["ms"]) == 2
+    b = flr.Batch(frames, persistent_blocks=sched["persistent_blocks"])
+    outs = b.run()
     for f, out in zip(frames, outs):
-        one = flr.denoise(f["noisy"], f["guides"], fused="two_pass", tile_rows=f["tile_rows"])
+        tr, ar = f["tile_rows"], f["apply_rows"]
+        co = flr.coefficients(f["guides"], f["noisy"], 8, tile_rows=tr)
+        one = flr.apply(f["guides"], co, 8, tile_rows=ar if ar else tr)
         assert torch.equal(out, one)
+    import json
+    data = json.load(open(tmp_path / "tune.json"))
+    key = autotune.frame_key(200, 700, 8, 3, 8)
+    assert data[key]["tile_rows"] == frames[0]["tile_rows"]
+    monkeypatch.setattr(autotune, "_MEM", {})  # a new process: read back from the file
+    assert autotune.tune_frame(200, 700) == data[key]
