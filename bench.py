@@ -304,6 +304,69 @@ def time_train(flr, torch, np, dev, stream, args):
             "steps": args.train_steps}
 
 
+def flnr_quality(flr, torch, np, dev, args):
+    """What FLNR's guides buy: the guide network trained with FLNRTrainer
+    (AdamW, lr 1e-3, FLR eps fixed at 1e-3) on the training workload --
+    ``args.quality_steps`` steps cycling over four batches of 8 crops of
+    256 x 256 (frame seeds 100..131) -- then plain FLR, FLNR with the
+    untrained network and FLNR with the trained one on held-out 1080p RGB
+    frames (seeds 500, 501), each against the frame's clean shading: mean
+    absolute error, relative MSE (mean of (out - clean)^2 / (clean^2 +
+    0.01), the paper's rMSE form) and PSNR of both clamped to [0, 1]."""
+    from synth import make_config, make_training_batch
+    from synth.net_weights import flatten_net_weights, make_net_weights
+    batches = []
+    for k in range(4):
+        crops = []
+        for c in make_training_batch(seed=3 + k, frame_seed0=100 + 8 * k):
+            g12 = torch.zeros((12,) + c["guides"].shape[1:], dtype=torch.float32, device=dev)
+            g12[:8].copy_(torch.from_numpy(c["guides"]))
+            crops.append({"guides12": g12, "noisy": torch.from_numpy(c["noisy"]).to(dev),
+                          "target": torch.from_numpy(c["target"]).to(dev)})
+        batches.append(crops)
+    params0 = torch.from_numpy(flatten_net_weights(make_net_weights(2))).to(dev)
+    params = params0.clone()
+    tr = flr.FLNRTrainer(params, lr=1e-3)
+    losses = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.quality_steps):
+        losses.append(tr.step(batches[k % 4]).sum())
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    losses = [float(x) for x in torch.stack(losses).cpu()]
+
+    def metrics(out, clean):
+        d = out - clean
+        l1 = float(d.abs().mean())
+        rmse = float((d * d / (clean * clean + 0.01)).mean())
+        mse01 = float(((out.clamp(0, 1) - clean.clamp(0, 1)) ** 2).mean())
+        return {"l1": round(l1, 6), "rmse": round(rmse, 6),
+                "psnr_db": round(10 * float(np.log10(1.0 / max(mse01, 1e-20))), 3)}
+
+    res = {"flr": [], "flnr_untrained": [], "flnr_trained": []}
+    packed0, packed = flr.net_pack(params0), flr.net_pack(params)
+    for seed in (500, 501):
+        fr = make_config(1, seed=seed)
+        y = torch.from_numpy(fr["noisy"]).to(dev)
+        g = torch.from_numpy(fr["guides"]).to(dev)
+        clean = torch.from_numpy(fr["clean"].astype(np.float32)).to(dev)
+        res["flr"].append(metrics(flr.denoise(y, g, radius=R, eps=EPS, fused="two_pass"), clean))
+        for name, pk in (("flnr_untrained", packed0), ("flnr_trained", packed)):
+            g12 = torch.zeros((12, H, W), dtype=torch.float32, device=dev)
+            g12[:8] = g
+            out = flr.flnr_denoise(y, g12, pk, radius=R, eps=EPS, fused="two_pass")
+            res[name].append(metrics(out, clean))
+    mean = {k: {m: round(float(np.mean([v[m] for v in vs])), 6) for m in vs[0]}
+            for k, vs in res.items()}
+    return {"train_steps": args.quality_steps, "train_s": round(train_s, 2),
+            "loss_first": round(losses[0], 6), "loss_last": round(losses[-1], 6),
+            "heldout_frames": 2, "mean": mean, "per_frame": res,
+            "config": "FLNRTrainer (AdamW lr 1e-3, batch 8 crops of 256x256, 4 batches from "
+                      "frame seeds 100..131, FLR eps 1e-3 fixed) then FLR vs FLNR on held-out "
+                      "1080p RGB frames (seeds 500, 501) against the clean shading"}
+
+
 def time_lowres(flr, torch, np, sets, nsets, dev, stream, args):
     """The paper's fast variant on the FLR workload's frames: 8x8 block
     moments, Gaussian sigma 1.25 (taps -4..4) at the low resolution, solve,
@@ -563,6 +626,9 @@ def main(argv=None):
     ap.add_argument("--lowres-steps", type=int, default=50)
     ap.add_argument("--adjoint-steps", type=int, default=10)
     ap.add_argument("--no-train", action="store_true", help="skip the training-step timing")
+    ap.add_argument("--no-quality", action="store_true",
+                    help="skip training the guide network and measuring FLNR's quality")
+    ap.add_argument("--quality-steps", type=int, default=300)
     ap.add_argument("--train-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter reference)")
@@ -645,6 +711,12 @@ def main(argv=None):
     if not args.no_train:
         train = time_train(flr, torch, np, dev, stream, args)
 
+    quality = None
+    if not args.no_quality:
+        quality = flnr_quality(flr, torch, np, dev, args)
+        if flnr is not None:
+            quality["flnr_minus_flr_ms_per_frame"] = flnr["vs_flr_ms"]
+
     if args.copy_calibration:
         src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -695,6 +767,7 @@ def main(argv=None):
         "lowres": lowres,
         "batch": batch,
         "train": train,
+        "flnr_quality": quality,
     }
     print(json.dumps(line))
     return 0

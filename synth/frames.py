@@ -160,10 +160,11 @@ def random_frame(h: int, w: int, q: int, c: int, seed: int, *, smooth: float = 0
 
 
 def make_training_batch(n: int = 8, crop: int = 256, seed: int = 3, frame_h: int = 512,
-                        frame_w: int = 512, samples: int = 256):
+                        frame_w: int = 512, samples: int = 256, frame_seed0: int = 100):
     """The FLNR training workload: ``n`` random crop x crop windows, one from
-    each of ``n`` frames in the style of configuration 1 (frame seeds 100,
-    101, ..., generated at frame_h x frame_w), each with a target that is the
+    each of ``n`` frames in the style of configuration 1 (frame seeds
+    frame_seed0, frame_seed0 + 1, ..., default 100, 101, ..., generated at
+    frame_h x frame_w), each with a target that is the
     mean of ``samples`` independent Exponential(1) noise draws times the clean
     shading. That mean is drawn directly from its distribution,
     Gamma(samples, 1 / samples). Returns a list of dicts with ``guides``
@@ -171,7 +172,7 @@ def make_training_batch(n: int = 8, crop: int = 256, seed: int = 3, frame_h: int
     rng = np.random.default_rng(seed)
     out = []
     for k in range(n):
-        fr = make_frame(frame_h, frame_w, 100 + k, rgb=True, fireflies=True)
+        fr = make_frame(frame_h, frame_w, frame_seed0 + k, rgb=True, fireflies=True)
         y0 = int(rng.integers(0, frame_h - crop + 1))
         x0 = int(rng.integers(0, frame_w - crop + 1))
         sl = (slice(None), slice(y0, y0 + crop), slice(x0, x0 + crop))
