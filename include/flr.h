@@ -127,6 +127,12 @@ typedef struct {
   int32_t fused;           /* flr_denoise: an flr_path */
   uint32_t flags;          /* FLR_FLAG_* */
   int32_t tile_rows;       /* rows per workgroup segment; 0 = automatic */
+  const float* eps_device; /* optional: device float[2] holding (eps, eps_mul), read by the
+                              kernels when they run in place of the two fields above, so
+                              that a training loop can update the regularisers on the
+                              device (flr_reg_adam_step, flr_train.h) without a host read;
+                              the values must stay finite and >= 0 (not checked). NULL:
+                              eps and eps_mul above. 4-byte aligned. */
 } flr_params;
 
 /* Number of moment planes M = 1 + Q + C + Q(Q+1)/2 + Q*C (0 if out of range). */

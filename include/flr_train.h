@@ -68,6 +68,28 @@ flr_status flr_adamw_step(int64_t n, float* params, const float* grads, float* m
                           int32_t step, float lr, float beta1, float beta2, float eps,
                           float weight_decay, void* stream);
 
+/* Adam on the logarithms of FLR's regularisers, on the device (the
+ * Appendix learns its regularisers by backpropagation; the logarithm keeps
+ * them positive): reg = device float[2] (eps, eps_mul), updated in place and
+ * read by the FLR kernels through flr_params.eps_device, so a training loop
+ * needs no host read; state = device double[6], zero before the first
+ * step: Adam moments of log eps (0, 1) and of log eps_mul (2, 3), and the
+ * step count (4; its own count, independent of the network's optimizer);
+ * dreg = the adjoint's per-crop gradients [n][2] (dL/deps, dL/deps_mul, as
+ * flr_denoise_backward writes them), summed in crop order. With g the sum
+ * times e (the derivative with respect to log e) and t the new step count:
+ *   m <- beta1 m + (1 - beta1) g,   v <- beta2 v + (1 - beta2) g^2
+ *   e <- e exp(-lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + adam_eps))
+ * for eps, and for eps_mul when learn_mul is 1 and eps_mul > 0 (a zero
+ * eps_mul stays zero). FP64 arithmetic, one thread. FLR_ERR_NULL,
+ * FLR_ERR_ALIGN (reg 4-byte, state and dreg 8-byte aligned), FLR_ERR_SHAPE
+ * for n < 1, FLR_ERR_MODE for learn_mul not 0 or 1, FLR_ERR_EPS for a
+ * negative or non-finite hyperparameter or beta >= 1, FLR_ERR_ALIAS when two
+ * of the arrays overlap. */
+flr_status flr_reg_adam_step(float* reg, double* state, const double* dreg, int32_t n,
+                             float lr, float beta1, float beta2, float adam_eps,
+                             int32_t learn_mul, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,12 +10,15 @@ leg may use this module; the product path never imports it.
 * AdamW (Adam with weight decay decoupled from the gradient, Loshchilov and
   Hutter): the update of the FP32 master weights, written from its published
   definition with bias-corrected first and second moments.
+* Adam on the logarithm of a positive regulariser (the Appendix learns its
+  regularisers by backpropagation): the parameter is log e, its gradient e
+  times dL/de, and e the exponential of the updated logarithm.
 """
 from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["l1_loss_grad", "adamw_step"]
+__all__ = ["l1_loss_grad", "adamw_step", "log_adam_step"]
 
 
 def l1_loss_grad(out, target, scale: float):
@@ -40,3 +43,12 @@ def adamw_step(p, g, m, v, step: int, lr: float, beta1: float = 0.9, beta2: floa
     p = p * (1.0 - lr * weight_decay)
     p = p - lr * m_hat / (np.sqrt(v_hat) + eps)
     return p, m, v
+
+
+def log_adam_step(e: float, grad_e: float, m: float, v: float, step: int, lr: float,
+                  beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-12):
+    """One Adam update of log(e) for a loss gradient grad_e = dL/de; returns
+    (new e, m, v). The update of log e is an AdamW update without decay of
+    the parameter log e with gradient e * grad_e."""
+    logp, m2, v2 = adamw_step(np.log(e), e * grad_e, m, v, step, lr, beta1, beta2, eps, 0.0)
+    return float(np.exp(logp)), float(m2), float(v2)

@@ -39,7 +39,7 @@ EXPORTED = ("flr_num_moment_planes", "flr_num_coeff_planes", "flr_denoise_worksp
             "flr_net_trace_tensor", "flr_net_forward_trace",
             # include/flr_train.h
             "flr_l1_workspace_bytes", "flr_l1_loss_grad", "flr_adamw_step",
-            "flr_l1_loss_grad_noalloc")
+            "flr_l1_loss_grad_noalloc", "flr_reg_adam_step")
 
 
 class FlrParams(ctypes.Structure):
@@ -56,6 +56,7 @@ class FlrParams(ctypes.Structure):
         ("fused", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
         ("tile_rows", ctypes.c_int32),
+        ("eps_device", ctypes.c_void_p),
     ]
 
 
@@ -197,6 +198,9 @@ def lib() -> ctypes.CDLL:
     L.flr_l1_loss_grad.restype = ctypes.c_int
     L.flr_l1_loss_grad_noalloc.argtypes = [ctypes.c_int64, vp, vp, ctypes.c_float, vp, vp, vp]
     L.flr_l1_loss_grad_noalloc.restype = ctypes.c_int
+    L.flr_reg_adam_step.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float, ctypes.c_float, ctypes.c_int32, vp]
+    L.flr_reg_adam_step.restype = ctypes.c_int
     f = ctypes.c_float
     L.flr_adamw_step.argtypes = [ctypes.c_int64, vp, vp, vp, vp, ctypes.c_int32, f, f, f, f, f, vp]
     L.flr_adamw_step.restype = ctypes.c_int

@@ -47,15 +47,31 @@ def _stream(t: torch.Tensor) -> ctypes.c_void_p:
     return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
 
 
+def _eps_device_ptr(eps_device):
+    """Device address of a float32 tensor of 2 (eps, eps_mul), or None."""
+    if eps_device is None:
+        return None
+    if not isinstance(eps_device, torch.Tensor) or eps_device.dtype != torch.float32 or \
+            eps_device.device.type != "cuda" or eps_device.numel() < 2 or \
+            not eps_device.is_contiguous():
+        raise ValueError("eps_device must be a contiguous float32 device tensor of 2 elements")
+    return eps_device.data_ptr()
+
+
 def make_params(H: int, W: int, Q: int, C: int, radius: int, eps: float = 1e-3,
                 mode: str = "ridge", eps_mul: float = 0.0, average: bool = True,
-                fused=True, raw: bool = False, tile_rows: int = 0) -> FlrParams:
+                fused=True, raw: bool = False, tile_rows: int = 0,
+                eps_device: torch.Tensor | None = None) -> FlrParams:
+    """flr_params; ``eps_device`` (float32 device tensor (eps, eps_mul)) makes
+    the kernels read the regularisers from the device instead of eps and
+    eps_mul."""
     if mode not in _MODES:
         raise ValueError(f"mode must be one of {sorted(_MODES)}")
     return FlrParams(height=H, width=W, num_guides=Q, num_channels=C, radius=radius,
                      eps=eps, eps_mul=eps_mul, reg_mode=_MODES[mode],
                      average_coeffs=int(bool(average)), fused=_path(fused),
-                     flags=FLR_FLAG_RAW_MOMENTS if raw else 0, tile_rows=tile_rows)
+                     flags=FLR_FLAG_RAW_MOMENTS if raw else 0, tile_rows=tile_rows,
+                     eps_device=_eps_device_ptr(eps_device))
 
 
 def num_moment_planes(Q: int, C: int) -> int:
@@ -145,11 +161,12 @@ def apply(guides: torch.Tensor, coeffs: torch.Tensor, radius: int, average: bool
 def denoise(noisy: torch.Tensor, guides: torch.Tensor, radius: int = 8, eps: float = 1e-3,
             mode: str = "ridge", eps_mul: float = 0.0, average: bool = True,
             fused=True, tile_rows: int = 0, out: torch.Tensor | None = None,
-            workspace: torch.Tensor | None = None) -> torch.Tensor:
+            workspace: torch.Tensor | None = None,
+            eps_device: torch.Tensor | None = None) -> torch.Tensor:
     """The whole FLR path -> [C,H,W]. ``fused``: True (one kernel), False
     (three stages) or a path name from ``PATHS``. ``workspace`` is a uint8
     device tensor of at least ``workspace_bytes`` bytes; it is allocated when
-    omitted."""
+    omitted. ``eps_device``: see make_params."""
     _need(guides, "guides")
     _need(noisy, "noisy")
     Q, H, W = guides.shape
@@ -157,7 +174,7 @@ def denoise(noisy: torch.Tensor, guides: torch.Tensor, radius: int = 8, eps: flo
     if noisy.shape[1:] != guides.shape[1:]:
         raise ValueError("noisy and guides must have the same height and width")
     p = make_params(H, W, Q, C, radius, eps=eps, mode=mode, eps_mul=eps_mul, average=average,
-                    fused=fused, tile_rows=tile_rows)
+                    fused=fused, tile_rows=tile_rows, eps_device=eps_device)
     need = workspace_bytes(p)
     if need == 0 and lib().flr_validate_params(ctypes.byref(p)) != 0:
         check(lib().flr_validate_params(ctypes.byref(p)), "flr_denoise")
@@ -303,11 +320,12 @@ def denoise_backward(noisy: torch.Tensor, guides: torch.Tensor, grad_out: torch.
                      workspace: torch.Tensor | None = None,
                      grad_noisy: torch.Tensor | None = None,
                      grad_guides: torch.Tensor | None = None,
-                     grad_reg: torch.Tensor | None = None):
+                     grad_reg: torch.Tensor | None = None,
+                     eps_device: torch.Tensor | None = None):
     """Gradients of ``denoise`` for dL/d(out) = ``grad_out`` [C,H,W]:
     (dL/d(noisy) [C,H,W], dL/d(guides) [Q,H,W], [dL/d(eps), dL/d(eps_mul)]
     as a float64 device tensor of 2). Moments are recomputed; the forward
-    call's results are not needed."""
+    call's results are not needed. ``eps_device``: see make_params."""
     _need(guides, "guides")
     _need(noisy, "noisy")
     _need(grad_out, "grad_out")
@@ -316,7 +334,8 @@ def denoise_backward(noisy: torch.Tensor, guides: torch.Tensor, grad_out: torch.
     if noisy.shape[1:] != guides.shape[1:] or grad_out.shape != noisy.shape:
         raise ValueError("noisy, guides and grad_out must share height and width; "
                          "grad_out must have the shape of noisy")
-    p = make_params(H, W, Q, C, radius, eps=eps, mode=mode, eps_mul=eps_mul, average=average)
+    p = make_params(H, W, Q, C, radius, eps=eps, mode=mode, eps_mul=eps_mul, average=average,
+                    eps_device=eps_device)
     check(lib().flr_validate_params(ctypes.byref(p)), "flr_denoise_backward")
     need = backward_workspace_bytes(p)
     dev = guides.device
@@ -567,6 +586,24 @@ def adamw_step(params: torch.Tensor, grads: torch.Tensor, m: torch.Tensor, v: to
                                _stream(params)), "flr_adamw_step")
 
 
+def reg_adam_step(reg: torch.Tensor, state: torch.Tensor, dreg: torch.Tensor, lr: float,
+                  betas=(0.9, 0.999), adam_eps: float = 1e-12, learn_mul: bool = False) -> None:
+    """Adam on log eps (and log eps_mul) on the device: ``reg`` float32 (2),
+    ``state`` float64 (6, zeros before the first step), ``dreg`` float64
+    [n, 2] per-crop regulariser gradients; reg and state in place."""
+    for t, dt, n, name in ((reg, torch.float32, 2, "reg"), (state, torch.float64, 6, "state")):
+        if not isinstance(t, torch.Tensor) or t.dtype != dt or t.device.type != "cuda" or \
+                t.numel() != n or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {dt} device tensor of {n}")
+    if dreg.dtype != torch.float64 or dreg.device.type != "cuda" or not dreg.is_contiguous() or \
+            dreg.numel() % 2:
+        raise ValueError("dreg must be a contiguous float64 device tensor [n, 2]")
+    check(lib().flr_reg_adam_step(reg.data_ptr(), state.data_ptr(), dreg.data_ptr(),
+                                  dreg.numel() // 2, float(lr), float(betas[0]), float(betas[1]),
+                                  float(adam_eps), int(bool(learn_mul)), _stream(reg)),
+          "flr_reg_adam_step")
+
+
 class FLNRTrainer:
     """Training of the guide network through FLR (Sec. 3.3): per crop the
     network writes guide planes 8..11, FLR (two-pass path) denoises over the
@@ -574,38 +611,57 @@ class FLNRTrainer:
     gives dL/d(guides) and the network backward accumulates dL/d(weights);
     then one AdamW step updates the FP32 master weights. ``params`` (FP32
     device vector) is updated in place. Buffers are allocated once per crop
-    size and reused."""
+    size and reused.
+
+    FLR's regularisers live on the device (``reg``: eps, eps_mul) and every
+    FLR call reads them from there. With ``learn_eps`` they are learned with
+    the network, as the Appendix learns its regularisers by backpropagation:
+    Adam on their logarithms from the adjoint's gradients summed over the
+    batch, in a device kernel with its own step count (no host read per
+    step); ``mode="paper"`` with ``flr_eps_mul > 0`` learns eps_mul too."""
 
     def __init__(self, params: torch.Tensor, lr: float = 1e-3, betas=(0.9, 0.999),
                  eps: float = 1e-8, weight_decay: float = 0.0, radius: int = 8,
-                 flr_eps: float = 1e-3, learn_eps: bool = False, eps_lr: float = 1e-2):
+                 flr_eps: float = 1e-3, learn_eps: bool = False, eps_lr: float = 1e-2,
+                 mode: str = "ridge", flr_eps_mul: float = 0.0):
         _need(params, "params", ndim=1)
         if params.numel() != net_num_params():
             raise ValueError(f"expected {net_num_params()} parameters")
+        if mode not in _MODES:
+            raise ValueError(f"mode must be one of {sorted(_MODES)}")
         self.params = params
+        dev = params.device
         self.grad = torch.zeros_like(params)
         self.m = torch.zeros_like(params)
         self.v = torch.zeros_like(params)
         self.t = 0
         self.lr, self.betas, self.eps, self.wd = lr, betas, eps, weight_decay
-        self.radius, self.flr_eps = radius, flr_eps
-        # learn_eps: FLR's regulariser learned with the network (the paper
-        # learns its regularisers by backpropagation), by Adam on log(eps)
-        # from the adjoint's dL/d(eps) summed over the batch; one host read
-        # per step
+        self.radius, self.mode = radius, mode
+        self.reg = torch.tensor([flr_eps, flr_eps_mul], dtype=torch.float32, device=dev)
+        self.reg_state = torch.zeros(6, dtype=torch.float64, device=dev)
         self.learn_eps, self.eps_lr = learn_eps, eps_lr
-        self.eps_m = self.eps_v = 0.0
-        self.last_deps = None
+        self.last_dreg = None
         self._bufs = {}
+
+    @property
+    def flr_eps(self) -> float:
+        """The current eps of FLR (a host read of the device value)."""
+        return float(self.reg[0].item())
+
+    @property
+    def flr_eps_mul(self) -> float:
+        return float(self.reg[1].item())
 
     def state_dict(self) -> dict:
         """Checkpoint: the FP32 master weights, the AdamW moments and step
-        count, and the hyperparameters (tensors copied to the host)."""
+        count, FLR's regularisers with their optimizer state, and the
+        hyperparameters (tensors copied to the host)."""
         return {"params": self.params.detach().cpu().clone(), "m": self.m.cpu().clone(),
                 "v": self.v.cpu().clone(), "step": int(self.t), "lr": self.lr,
                 "betas": tuple(self.betas), "eps": self.eps, "weight_decay": self.wd,
-                "radius": self.radius, "flr_eps": self.flr_eps, "learn_eps": self.learn_eps,
-                "eps_lr": self.eps_lr, "eps_m": self.eps_m, "eps_v": self.eps_v}
+                "radius": self.radius, "mode": self.mode, "reg": self.reg.cpu().clone(),
+                "reg_state": self.reg_state.cpu().clone(), "learn_eps": self.learn_eps,
+                "eps_lr": self.eps_lr}
 
     def load_state_dict(self, state: dict) -> None:
         """Resume from state_dict(): the next step equals the one the saved
@@ -620,15 +676,21 @@ class FLNRTrainer:
         self.t = int(state["step"])
         self.lr, self.betas, self.eps, self.wd = (state["lr"], tuple(state["betas"]),
                                                   state["eps"], state["weight_decay"])
-        self.radius, self.flr_eps = state["radius"], state["flr_eps"]
+        self.radius = state["radius"]
+        self.mode = state.get("mode", "ridge")
+        if "reg" in state:
+            self.reg.copy_(state["reg"])
+            self.reg_state.copy_(state["reg_state"])
+        else:  # a checkpoint that kept eps on the host
+            self.reg.copy_(torch.tensor([state["flr_eps"], 0.0]))
+            self.reg_state.zero_()
         self.learn_eps = state.get("learn_eps", False)
         self.eps_lr = state.get("eps_lr", self.eps_lr)
-        self.eps_m, self.eps_v = state.get("eps_m", 0.0), state.get("eps_v", 0.0)
 
     def _buffers(self, H, W, dev):
         key = (H, W)
         if key not in self._bufs:
-            p = make_params(H, W, 12, 3, self.radius, eps=self.flr_eps, fused="two_pass")
+            p = make_params(H, W, 12, 3, self.radius, mode=self.mode, fused="two_pass")
             b = dict(
                 g12=torch.empty((12, H, W), dtype=torch.float32, device=dev),
                 out=torch.empty((3, H, W), dtype=torch.float32, device=dev),
@@ -649,9 +711,9 @@ class FLNRTrainer:
         """One step on a batch: crops is a list of dicts with device tensors
         ``guides`` [8,H,W] (or ``guides12`` [12,H,W] with the 8 guides in
         planes 0..7; the network overwrites 8..11), ``noisy`` and ``target``
-        [3,H,W]. Returns the
-        per-crop losses (float64 device tensor; their sum is the batch mean
-        absolute error)."""
+        [3,H,W]. Returns the per-crop losses (float64 device tensor; their
+        sum is the batch mean absolute error). Nothing is read back to the
+        host."""
         dev = self.params.device
         packed = net_pack(self.params)
         losses = torch.empty(len(crops), dtype=torch.float64, device=dev)
@@ -667,33 +729,27 @@ class FLNRTrainer:
                 g12[:NET_IN_GUIDES].copy_(c["guides"])
             net_forward(g12[:NET_IN_GUIDES], c["noisy"], packed, out=g12[NET_IN_GUIDES:],
                         workspace=b["ws_net"])
-            denoise(c["noisy"], g12, self.radius, self.flr_eps, fused="two_pass", out=b["out"],
-                    workspace=b["ws_fwd"])
+            denoise(c["noisy"], g12, self.radius, mode=self.mode, fused="two_pass",
+                    out=b["out"], workspace=b["ws_fwd"], eps_device=self.reg)
             l1_loss_grad(b["out"], c["target"], 1.0 / total, grad=b["G"], loss=losses[k:k + 1],
                          workspace=b["ws_l1"])
-            denoise_backward(c["noisy"], g12, b["G"], self.radius, self.flr_eps,
+            denoise_backward(c["noisy"], g12, b["G"], self.radius, mode=self.mode,
                              workspace=b["ws_bwd"], grad_noisy=b["dy"], grad_guides=b["dg"],
-                             grad_reg=dregs[k])
+                             grad_reg=dregs[k], eps_device=self.reg)
             net_backward(g12[:NET_IN_GUIDES], c["noisy"], self.params, packed,
                          b["dg"][NET_IN_GUIDES:], grad_params=self.grad, accumulate=k > 0,
                          workspace=b["ws_net"])
         self.t += 1
         adamw_step(self.params, self.grad, self.m, self.v, self.t, self.lr, self.betas, self.eps,
                    self.wd)
+        self.last_dreg = dregs
         if self.learn_eps:
-            deps = float(dregs[:, 0].sum().item())
-            self.last_deps = deps
-            g = deps * self.flr_eps  # d loss / d log(eps)
-            b1, b2 = self.betas
-            self.eps_m = b1 * self.eps_m + (1 - b1) * g
-            self.eps_v = b2 * self.eps_v + (1 - b2) * g * g
-            mh = self.eps_m / (1 - b1 ** self.t)
-            vh = self.eps_v / (1 - b2 ** self.t)
-            self.flr_eps = float(self.flr_eps * math.exp(-self.eps_lr * mh / (math.sqrt(vh) + 1e-12)))
+            reg_adam_step(self.reg, self.reg_state, dregs, self.eps_lr, self.betas,
+                          learn_mul=self.mode == "paper")
         return losses
 
 
 __all__ = ["FLRError", "PATHS", "make_params", "num_moment_planes", "num_coeff_planes",
            "workspace_bytes", "moments", "solve", "coefficients", "apply", "denoise",
            "net_num_params", "net_pack", "net_forward", "net_backward", "flnr_workspace_bytes",
-           "flnr_denoise", "l1_loss_grad", "adamw_step", "FLNRTrainer"]
+           "flnr_denoise", "l1_loss_grad", "adamw_step", "reg_adam_step", "FLNRTrainer"]

@@ -107,7 +107,7 @@ __global__ void __launch_bounds__(256) adj_coef_kernel(LaunchArgs a) {
   centred_moments<Q, C>(a.sums + idx, pl, inv_n, mu, nu, Hm, R, C);
 #pragma unroll
   for (int q = 0; q < Q; ++q) mo[q] = mu[q] + cg[q];
-  regularise<Q, T>(Hm, mo, (T)a.eps, (T)a.eps_mul, a.reg_mode);
+  regularise<Q, T>(Hm, mo, (T)arg_eps(a), (T)arg_eps_mul(a), a.reg_mode);
   chol_solve<Q, C, T>(Hm, R);
   double* o = a.fout + idx;
   T gn[C];
@@ -176,7 +176,7 @@ __global__ void __launch_bounds__(256) adj_solve_kernel(LaunchArgs a) {
 #pragma unroll
       for (int c = 0; c < C; ++c) R[q * C2 + C + c] = fma(-mu[q], B[c], A[q * C + c]);
     }
-    regularise<Q, T>(Hm, mo, (T)a.eps, (T)a.eps_mul, a.reg_mode);
+    regularise<Q, T>(Hm, mo, (T)arg_eps(a), (T)arg_eps_mul(a), a.reg_mode);
     T hd[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) hd[q] = Hm[tri<Q>(q, q)];
@@ -205,7 +205,7 @@ __global__ void __launch_bounds__(256) adj_solve_kernel(LaunchArgs a) {
 #pragma unroll
       for (int q = 0; q < Q; ++q) de += dW[tri<Q>(q, q)];
     } else {
-      const T eps = a.eps, em = a.eps_mul, s1 = T(1) + eps;
+      const T eps = arg_eps(a), em = arg_eps_mul(a), s1 = T(1) + eps;
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         de = fma(dW[tri<Q>(q, q)], hd[q] / s1, de);  // Gs_qq W^_qq

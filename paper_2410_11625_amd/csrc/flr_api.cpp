@@ -38,6 +38,7 @@ LaunchArgs base_args(const flr_params* p) {
   a.r = p->radius;
   a.eps = p->eps;
   a.eps_mul = p->eps_mul;
+  a.eps_dev = p->eps_device;
   a.reg_mode = p->reg_mode;
   a.raw = (p->flags & FLR_FLAG_RAW_MOMENTS) ? 1 : 0;
   return a;
@@ -297,6 +298,7 @@ flr_status flr_validate_params(const flr_params* p) {
     return FLR_ERR_MODE;
   if (p->flags & ~(uint32_t)FLR_FLAG_RAW_MOMENTS) return FLR_ERR_MODE;
   if (p->tile_rows < 0) return FLR_ERR_SHAPE;
+  if (reinterpret_cast<uintptr_t>(p->eps_device) & 3u) return FLR_ERR_ALIGN;
   return FLR_OK;
 }
 

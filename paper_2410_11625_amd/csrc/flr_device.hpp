@@ -102,6 +102,15 @@ __device__ __forceinline__ void regularise(T (&Hm)[Q * (Q + 1) / 2], const T (&m
   }
 }
 
+// The regularisers of a launch: its arguments, or the device pair (eps,
+// eps_mul) when the caller keeps them on the device.
+__device__ __forceinline__ float arg_eps(const LaunchArgs& a) {
+  return a.eps_dev ? a.eps_dev[0] : a.eps;
+}
+__device__ __forceinline__ float arg_eps_mul(const LaunchArgs& a) {
+  return a.eps_dev ? a.eps_dev[1] : a.eps_mul;
+}
+
 // f(std::integral_constant<int, I>) for I = B .. E-1: loop bodies with
 // compile-time indices, whatever the trip count (the compiler otherwise
 // keeps short inner loops of the larger systems as loops over arrays in
@@ -885,7 +894,7 @@ __device__ __forceinline__ void walk_tile(const LaunchArgs a, const int bid) {
             mu_o[q] = mu[q] + (T)cg[q];
             mu_c[q] = (chol_t)mu_o[q];
           }
-          regularise<Q, chol_t>(Hm, mu_c, (chol_t)a.eps, (chol_t)a.eps_mul, a.reg_mode);
+          regularise<Q, chol_t>(Hm, mu_c, (chol_t)arg_eps(a), (chol_t)arg_eps_mul(a), a.reg_mode);
           chol_solve<Q, C, chol_t>(Hm, R);
           if (MODE == W_COEFFS) {
             // b = nu - a^T mu in original units
@@ -1011,7 +1020,7 @@ __global__ void __launch_bounds__(256) solve_kernel(LaunchArgs a) {
   for (int k = 0; k < NP; ++k) Hm[k] = m[(1 + Q + C + k) * pl];
 #pragma unroll
   for (int k = 0; k < Q * C; ++k) R[k] = m[(1 + Q + C + NP + k) * pl];
-  regularise<Q, T>(Hm, mu, (T)a.eps, (T)a.eps_mul, a.reg_mode);
+  regularise<Q, T>(Hm, mu, (T)arg_eps(a), (T)arg_eps_mul(a), a.reg_mode);
   chol_solve<Q, C, T>(Hm, R);
   float* o = a.out + idx;
 #pragma unroll

@@ -164,6 +164,7 @@ struct LaunchArgs {
   int seg_rows, tiles_x, n_seg;
   int hchunk_m, hchunk_a;  // horizontal-pass chunk lengths (moments, averaging)
   float eps, eps_mul;
+  const float* eps_dev;  // when set: (eps, eps_mul) read from device memory instead
   int reg_mode;
   int raw;
   // adjoint kernels only

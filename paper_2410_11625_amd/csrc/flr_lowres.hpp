@@ -150,7 +150,7 @@ __device__ __forceinline__ void lr_solve_item(const LaunchArgs a, const int bid)
   centred_from<Q, C>([&](int ch) { return S[(1 + ch) * pll]; }, inv_n, mu, nu, Hm, R_, C);
 #pragma unroll
   for (int q = 0; q < Q; ++q) mo[q] = mu[q] + (T)a.guides[q * pl];
-  regularise<Q, T>(Hm, mo, (T)a.eps, (T)a.eps_mul, a.reg_mode);
+  regularise<Q, T>(Hm, mo, (T)arg_eps(a), (T)arg_eps_mul(a), a.reg_mode);
   chol_solve<Q, C, T>(Hm, R_);
   double* o = a.fout + idx;
 #pragma unroll

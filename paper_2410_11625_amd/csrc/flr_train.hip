@@ -93,6 +93,41 @@ __global__ void __launch_bounds__(kBlock) adamw_kernel(AdamWArgs a) {
   a.p[i] = p - a.step_size * (m / denom);
 }
 
+// Adam on the logarithms of FLR's regularisers (eps, eps_mul), one thread:
+// the adjoint's per-crop FP64 gradients summed in crop order, the chain
+// factor of the logarithm (dL/dlog e = e dL/de), then Adam with its own
+// step count t (state[4]) and moments (state[0..1] for eps, [2..3] for
+// eps_mul); e <- e exp(-lr mhat / (sqrt(vhat) + adam_eps)).
+struct RegAdamArgs {
+  float* reg;
+  double* state;
+  const double* dreg;
+  int n;
+  int learn_mul;
+  double lr, beta1, beta2, adam_eps;
+};
+__global__ void __launch_bounds__(64) reg_adam_kernel(RegAdamArgs a) {
+  if (threadIdx.x != 0) return;
+  double ge = 0.0, gm = 0.0;
+  for (int k = 0; k < a.n; ++k) {
+    ge += a.dreg[2 * k];
+    gm += a.dreg[2 * k + 1];
+  }
+  const double t = a.state[4] + 1.0;
+  a.state[4] = t;
+  const double bc1 = 1.0 - pow(a.beta1, t), bc2 = 1.0 - pow(a.beta2, t);
+  for (int j = 0; j < 2; ++j) {
+    const double e = (double)a.reg[j];
+    if (j == 1 && !(a.learn_mul && e > 0.0)) break;
+    const double g = (j == 0 ? ge : gm) * e;
+    const double m = a.beta1 * a.state[2 * j] + (1.0 - a.beta1) * g;
+    const double v = a.beta2 * a.state[2 * j + 1] + (1.0 - a.beta2) * g * g;
+    a.state[2 * j] = m;
+    a.state[2 * j + 1] = v;
+    a.reg[j] = (float)(e * exp(-a.lr * (m / bc1) / (sqrt(v / bc2) + a.adam_eps)));
+  }
+}
+
 inline int l1_blocks(int64_t n) {
   const int64_t b = (n + kBlock - 1) / kBlock;
   return (int)(b < kMaxBlocks ? (b < 1 ? 1 : b) : kMaxBlocks);
@@ -203,6 +238,29 @@ flr_status flr_l1_loss_grad_noalloc(int64_t n, const float* out, const float* ta
   double* part = nullptr;
   if (scratch_address(&part) != hipSuccess) return FLR_ERR_HIP;
   return l1_launch(n, out, target, scale, grad, loss, part, reinterpret_cast<hipStream_t>(stream));
+}
+
+flr_status flr_reg_adam_step(float* reg, double* state, const double* dreg, int32_t n,
+                             float lr, float beta1, float beta2, float adam_eps,
+                             int32_t learn_mul, void* stream) {
+  if (!reg || !state || !dreg) return FLR_ERR_NULL;
+  if ((reinterpret_cast<uintptr_t>(reg) & 3u) || (reinterpret_cast<uintptr_t>(state) & 7u) ||
+      (reinterpret_cast<uintptr_t>(dreg) & 7u))
+    return FLR_ERR_ALIGN;
+  if (n < 1) return FLR_ERR_SHAPE;
+  if (learn_mul != 0 && learn_mul != 1) return FLR_ERR_MODE;
+  const float hp[4] = {lr, beta1, beta2, adam_eps};
+  for (float x : hp)
+    if (!(x >= 0.f) || x == __builtin_huge_valf()) return FLR_ERR_EPS;
+  if (!(beta1 < 1.f) || !(beta2 < 1.f)) return FLR_ERR_EPS;
+  if (overlaps(reg, 2 * sizeof(float), state, 6 * sizeof(double)) ||
+      overlaps(reg, 2 * sizeof(float), dreg, 2 * (size_t)n * sizeof(double)) ||
+      overlaps(state, 6 * sizeof(double), dreg, 2 * (size_t)n * sizeof(double)))
+    return FLR_ERR_ALIAS;
+  const RegAdamArgs a = {reg, state, dreg, n, learn_mul, lr, beta1, beta2, adam_eps};
+  hipLaunchKernelGGL(reg_adam_kernel, dim3(1), dim3(64), 0, reinterpret_cast<hipStream_t>(stream),
+                     a);
+  return hipGetLastError() == hipSuccess ? FLR_OK : FLR_ERR_HIP;
 }
 
 flr_status flr_adamw_step(int64_t n, float* params, const float* grads, float* m, float* v,

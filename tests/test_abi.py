@@ -93,15 +93,36 @@ def test_train_entry_points_validate_before_launch(L):
     assert ad(4, a16, a16, a16, a16, 1, 1e-3, 0.9, 0.999, 1e-8, 0.0, None) == 6    # ALIAS
 
 
-def test_params_struct_layout_matches_header():
-    # 12 four-byte fields, no padding
-    assert ctypes.sizeof(FlrParams) == 48
+def test_params_struct_layout_matches_header(tmp_path):
+    """Field names in header order, and sizeof and offsets compiled from the
+    header with the host C compiler, against the ctypes mirror (12 four-byte
+    fields, then the eight-byte eps_device pointer)."""
+    import shutil
+    import subprocess
+    assert ctypes.sizeof(FlrParams) == 56
     hdr = open(os.path.join(ROOT, "include", "flr.h")).read()
     body = hdr[hdr.index("typedef struct {"):hdr.index("} flr_params;")]
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     names = re.findall(r"(\w+)(?:,\s*(\w+))?;", body)
     flat = [n for pair in names for n in pair if n]
     assert flat == [f[0] for f in FlrParams._fields_]
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "flr.h"', "int main(void) {",
+             'printf("size %zu\\n", sizeof(flr_params));']
+    lines += [f'printf("{n} %zu\\n", offsetof(flr_params, {n}));' for n, _ in FlrParams._fields_]
+    lines.append("return 0; }")
+    src = tmp_path / "p.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "p"
+    subprocess.run([cc, f"-I{os.path.join(ROOT, 'include')}", str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                 check=True).stdout.splitlines())
+    assert int(got["size"]) == ctypes.sizeof(FlrParams)
+    for n, _ in FlrParams._fields_:
+        assert int(got[n]) == getattr(FlrParams, n).offset, n
 
 
 def test_plane_counts(L):

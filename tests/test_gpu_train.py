@@ -109,16 +109,63 @@ def test_trainer_step_equals_its_parts():
 
 
 def test_trainer_learns_eps():
-    """learn_eps: the step's dL/d(eps) is the crops' adjoint sums, and Adam's
-    first step on log(eps) moves it by eps_lr against that gradient's sign."""
+    """learn_eps: the step's dL/d(eps) is the crops' adjoint sums, and the
+    device Adam step on log(eps) (its own step count) matches the oracle;
+    the first step moves log eps by eps_lr against the gradient's sign."""
     crops = _crops()
     p0 = _t(flatten_net_weights(make_net_weights(2)))
     tr = flr.FLNRTrainer(p0.clone(), learn_eps=True, eps_lr=0.1)
     tr.step(crops)
     _, _, deps = _parts(crops, p0.clone())
     assert deps != 0.0
-    assert abs(tr.last_deps - deps) <= 1e-12 * abs(deps)
+    got = float(tr.last_dreg[:, 0].sum().item())
+    assert abs(got - deps) <= 1e-12 * abs(deps)
+    e_ref, _, _ = train_ref.log_adam_step(float(np.float32(1e-3)), got, 0.0, 0.0, 1,
+                                          float(np.float32(0.1)), float(np.float32(0.9)),
+                                          float(np.float32(0.999)), float(np.float32(1e-12)))
+    assert abs(tr.flr_eps - e_ref) <= 1e-6 * e_ref
     assert abs(np.log(tr.flr_eps / 1e-3) + 0.1 * np.sign(deps)) <= 1e-6
+    assert float(tr.reg_state[4].item()) == 1.0
+
+
+def test_reg_adam_step_matches_oracle():
+    """Several device steps of Adam on (log eps, log eps_mul) against the
+    oracle, with FP32 hyperparameters as the ABI carries them."""
+    f32 = lambda x: float(np.float32(x))  # noqa: E731
+    reg = torch.tensor([2e-3, 0.3], dtype=torch.float32, device=_dev())
+    state = torch.zeros(6, dtype=torch.float64, device=_dev())
+    e, em = f32(2e-3), f32(0.3)
+    me = ve = mm = vm = 0.0
+    rng = np.random.default_rng(4)
+    for t in range(1, 6):
+        dreg = rng.standard_normal((3, 2)) * [50.0, 0.2]
+        flr.reg_adam_step(reg, state, torch.from_numpy(dreg).to(_dev()), 0.05, learn_mul=True)
+        e, me, ve = train_ref.log_adam_step(e, float(dreg[:, 0].sum()), me, ve, t, f32(0.05),
+                                            f32(0.9), f32(0.999), f32(1e-12))
+        em, mm, vm = train_ref.log_adam_step(em, float(dreg[:, 1].sum()), mm, vm, t, f32(0.05),
+                                             f32(0.9), f32(0.999), f32(1e-12))
+        e, em = f32(e), f32(em)  # the device keeps (eps, eps_mul) in FP32
+        got = reg.cpu().numpy().astype(np.float64)
+        assert abs(got[0] - e) <= 1e-6 * e and abs(got[1] - em) <= 1e-6 * em, t
+    assert float(state[4].item()) == 5.0
+
+
+@pytest.mark.parametrize("path", ["two_pass", "fused", "stages"])
+def test_regularisers_read_from_the_device(path):
+    """flr_params.eps_device: the same results, bit for bit, as the same
+    values passed as arguments, forward and backward."""
+    fr = make_training_batch(n=1, crop=64, frame_h=96, frame_w=128)[0]
+    y, g = _t(fr["noisy"]), _t(fr["guides"])
+    reg = torch.tensor([3e-3, 0.2], dtype=torch.float32, device=_dev())
+    for mode in ("ridge", "paper"):
+        a = flr.denoise(y, g, 8, 3e-3, mode=mode, eps_mul=0.2, fused=path)
+        b = flr.denoise(y, g, 8, 123.0, mode=mode, eps_mul=7.0, fused=path, eps_device=reg)
+        assert torch.equal(a, b), mode
+    G = _t(np.random.default_rng(1).standard_normal(fr["noisy"].shape))
+    ra = flr.denoise_backward(y, g, G, 8, 3e-3, mode="paper", eps_mul=0.2)
+    rb = flr.denoise_backward(y, g, G, 8, 1.0, mode="paper", eps_mul=1.0, eps_device=reg)
+    for x, z in zip(ra, rb):
+        assert torch.equal(x, z)
 
 
 def test_training_reduces_the_loss():
@@ -130,19 +177,27 @@ def test_training_reduces_the_loss():
     assert np.isfinite(last) and last < first, (first, last)
 
 
-def test_checkpoint_resume(tmp_path):
+@pytest.mark.parametrize("learn", [False, True])
+def test_checkpoint_resume(tmp_path, learn):
+    """A resumed run's next step equals the uninterrupted one bit for bit,
+    with FLR's regularisers learned (Appendix mode, eps and eps_mul) too."""
     from safetensors.torch import load_file, save_file
     crops = _crops(n=2, crop=48)
     p0 = _t(flatten_net_weights(make_net_weights(2)))
-    a = flr.FLNRTrainer(p0.clone(), lr=1e-3)
+    kw = dict(learn_eps=True, mode="paper", flr_eps_mul=0.1, eps_lr=0.05) if learn else {}
+    a = flr.FLNRTrainer(p0.clone(), lr=1e-3, **kw)
     a.step(crops)
     a.step(crops)
     st = a.state_dict()
     f = tmp_path / "ckpt.safetensors"
-    save_file({k: st[k] for k in ("params", "m", "v")}, str(f))
-    meta = {k: v for k, v in st.items() if k not in ("params", "m", "v")}
+    tensors = ("params", "m", "v", "reg", "reg_state")
+    save_file({k: st[k] for k in tensors}, str(f))
+    meta = {k: v for k, v in st.items() if k not in tensors}
     b = flr.FLNRTrainer(torch.zeros_like(p0), lr=0.5)
     b.load_state_dict({**load_file(str(f)), **meta})
     la = a.step(crops)
     lb = b.step(crops)
     assert torch.equal(la, lb) and torch.equal(a.params, b.params) and b.t == a.t == 3
+    assert torch.equal(a.reg, b.reg) and torch.equal(a.reg_state, b.reg_state)
+    if learn:
+        assert a.flr_eps != 1e-3 and a.flr_eps_mul != 0.1

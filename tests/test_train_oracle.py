@@ -99,3 +99,19 @@ def _sign_slip(p, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_de
                          ids=lambda f: f.__name__)
 def test_planted_optimizer_mistake_is_caught(fn):
     assert not _adamw_ok(fn)
+
+
+def test_log_adam_matches_library_adam_on_the_logarithm():
+    """Adam on log e against torch's Adam optimizer on a log-parameter whose
+    loss gradient (by the chain rule) is e * dL/de, over several steps of
+    varying gradients."""
+    torch = pytest.importorskip("torch")
+    e, m, v = 1e-3, 0.0, 0.0
+    logp = torch.tensor([np.log(1e-3)], dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([logp], lr=0.05, betas=(0.9, 0.999), eps=1e-12)
+    for t, ge in enumerate([3.0, -1.0, 2.5, 0.5, -4.0], start=1):
+        e, m, v = train_ref.log_adam_step(e, ge, m, v, t, 0.05)
+        opt.zero_grad()
+        logp.grad = torch.tensor([float(np.exp(logp.item())) * ge], dtype=torch.float64)
+        opt.step()
+        assert abs(np.log(e) - logp.item()) <= 1e-12 * abs(logp.item()), t
