@@ -315,7 +315,12 @@ __global__ void __launch_bounds__(256) dgrad_kernel(DgradArgs a) {
 inline size_t dgrad_lds_bytes(const Layer& L, int cpt) {
   return (size_t)L.k * L.k * L.cout * cpt * sizeof(float);
 }
-constexpr size_t kDgWidePx = (size_t)1 << 18;  // grids from 2^18 pixels take 16 channels
+// grids from 2^18 pixels take 16 channels per thread (the sum order per
+// channel is the same either way; a build may lower the threshold)
+#ifndef FLR_DGRAD_WIDE_PX
+#define FLR_DGRAD_WIDE_PX (1 << 18)
+#endif
+constexpr size_t kDgWidePx = (size_t)(FLR_DGRAD_WIDE_PX);
 
 // low[(i,j)][c] = sum of fine[(2i+di, 2j+dj)][c] over the fine pixels in the
 // H x W grid, channels c < nc of a fine tensor with channel stride cs.

@@ -458,6 +458,17 @@ def run_case(spec: dict) -> dict:
             plain = emu.net(fr["guides"], fr["noisy"], flatten_net_weights(wts))
             report, _ = check_network(acts, out, fr["guides"], fr["noisy"], wts)
             return {"report": report, "trace_equals_forward": bool(np.array_equal(out, plain))}
+        if kind == "net_bwd_digest":
+            # digest of the raw FP32 parameter gradients (to compare builds)
+            import hashlib
+            from synth.net_weights import flatten_net_weights, make_net_weights
+            fr = make_config(1, h=H, w=W)
+            wts = make_net_weights(spec.get("seed", 2))
+            G = np.random.default_rng(spec.get("seed", 2) + 1).standard_normal((4, H, W))
+            got = emu.net_backward(fr["guides"], fr["noisy"], flatten_net_weights(wts),
+                                   G.astype(np.float32))
+            return {"sha256": hashlib.sha256(np.ascontiguousarray(got, np.float32).tobytes())
+                    .hexdigest(), "finite": bool(np.all(np.isfinite(got)))}
         if kind == "net_bwd":
             from oracle import net_adjoint, net_ref
             from synth.net_weights import flatten_net_weights, make_net_weights

@@ -84,6 +84,18 @@ def test_emulated_net_backward_matches_oracle():
     assert max(res.values()) <= 1e-4, res
 
 
+# The network backward's data-gradient kernel takes 16 input channels per
+# thread on grids of 2^18 pixels or more and 8 below, with the same sum order
+# per channel: a build with the threshold at one pixel (16 everywhere) must
+# give the default build's gradients bit for bit on a small frame.
+def test_emulated_dgrad_variants_bit_equal(monkeypatch):
+    spec = dict(kind="net_bwd_digest", H=9, W=13, Q=8, C=3, r=0)
+    default = run_in_subprocess(spec)
+    monkeypatch.setenv("FLR_EMU_VARIANT", "FLR_DGRAD_WIDE_PX=1")
+    wide = run_in_subprocess(spec)
+    assert default["finite"] and default["sha256"] == wide["sha256"]
+
+
 # The adjoint (flr_denoise_backward) against the FP64 adjoint oracle given
 # the same FP32 eps and eps_mul. Its arithmetic is FP64 throughout (moments
 # from FP64 window sums of anchored products, FP64 fields and sums), so the
