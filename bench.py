@@ -731,6 +731,7 @@ def main(argv=None):
     errs = {k: oracle_sampled_error(v) for k, v in outputs.items()}
     if other is not None:
         other["max_rel_err_vs_fp64_sampled"] = errs[other["path"]]
+        other["roofline"]["traffic"] = load_traffic(other["path"])
     roof = dict(main_path["roofline"])
     roof["traffic"] = load_traffic(args.path)
     line = {
@@ -744,7 +745,7 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32-io/f64-sums/f32-cholesky",
+        "dtype": "f32-io/f64-sums/f64-cholesky",
         "data": "synthetic",
         "config": {"workload": "FLR 1920x1080 RGB frame, 8 guides + constant, radius 8, "
                                "eps 1e-3, ridge, window-averaged coefficients",
@@ -752,8 +753,8 @@ def main(argv=None):
                             "two_pass": "two kernels (moments+solve, average+reconstruct)",
                             "stages": "three stages (moments, solve, apply)"}[args.path],
                    "io_dtype": "f32",
-                   "accumulate_dtype": "f64 window sums, centring, intercepts and average; "
-                                       "f32 Cholesky factorisation and substitution",
+                   "accumulate_dtype": "f64 window sums, centring, Cholesky factorisation and "
+                                       "substitution, intercepts and average",
                    "buffer_sets": nsets,
                    "ms_per_frame_p10_p50_p90": main_path["ms_per_frame_p10_p50_p90"],
                    "second_kernel_ms": main_path["second_kernel_ms"],
