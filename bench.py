@@ -78,7 +78,7 @@ def kernel_source_digest() -> str:
     launch (the counters are void once any of them changes)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2410_11625_amd", "csrc")
-    for f in ("flr_device.hpp", "flr_launch.hpp", "flr_q08.hip"):
+    for f in ("flr_device.hpp", "flr_launch.hpp", "flr_prefix.hpp", "flr_q08.hip"):
         h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -2,23 +2,21 @@
 //
 // The adjoint recomputes the window moments as FP64 sums of anchored input
 // products, and sums its per-pixel fields over the same clipped window (the
-// window sum is its own adjoint). One workgroup owns
-// a strip of kThreads input columns (kThreads - 2r output columns) of one
-// plane and walks down a segment of rows: each lane keeps the running
-// vertical sum of its column (add the row entering the window, subtract the
-// row leaving it), stages it in LDS, and the lanes that own output columns
-// add the 2r+1 staged values of their window. Columns outside the image
-// stage 0, which clips the window at the left and right borders.
+// window sum is its own adjoint). The window-sum tile is box_tile
+// (flr_box.hpp): one workgroup per strip of kThreads input columns of one
+// plane and segment of rows, running vertical sums per lane, horizontal sums
+// by segmented prefixes.
 #include <hip/hip_runtime.h>
 
 #include "flr_box.hpp"
 #include "flr_launch.hpp"
+#include "flr_prefix.hpp"
 
 namespace flr {
 
-template <int SRC>
+template <int SRC, bool WIDE, bool RING>
 __global__ void __launch_bounds__(256) adj_box_kernel(AdjBoxArgs a) {
-  box_tile<SRC>(a, blockIdx.x, blockIdx.y);
+  box_tile<SRC, WIDE, RING>(a, blockIdx.x, blockIdx.y);
 }
 
 struct AdjPairArgs {
@@ -52,19 +50,37 @@ __global__ void __launch_bounds__(256) adj_pair_sum_kernel(AdjPairArgs a) {
   }
 }
 
-static hipError_t box_launch(AdjBoxArgs a, int planes, hipStream_t s) {
-  if (planes <= 0 || planes > 65535 || a.H < 1 || a.W < 1 || a.r < 0 || 2 * a.r >= kThreads)
-    return hipErrorInvalidValue;
-  const dim3 grid(box_plan(a), planes);
-  const size_t lds = 2 * kThreads * sizeof(double);
+template <bool WIDE, bool RING>
+static void box_dispatch(const AdjBoxArgs& a, dim3 grid, size_t lds, hipStream_t s) {
   if (a.srcf)
-    hipLaunchKernelGGL(adj_box_kernel<BOX_MEAN32>, grid, dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL((adj_box_kernel<BOX_MEAN32, WIDE, RING>), grid, dim3(kThreads), lds, s, a);
   else if (a.src && a.count_first)  // count_first marks a mean of FP64 planes here
-    hipLaunchKernelGGL(adj_box_kernel<BOX_MEAN64>, grid, dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL((adj_box_kernel<BOX_MEAN64, WIDE, RING>), grid, dim3(kThreads), lds, s, a);
   else if (a.src)
-    hipLaunchKernelGGL(adj_box_kernel<BOX_SUM64>, grid, dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL((adj_box_kernel<BOX_SUM64, WIDE, RING>), grid, dim3(kThreads), lds, s, a);
   else
-    hipLaunchKernelGGL(adj_box_kernel<BOX_PRODUCTS>, grid, dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL((adj_box_kernel<BOX_PRODUCTS, WIDE, RING>), grid, dim3(kThreads), lds, s,
+                       a);
+}
+
+static hipError_t box_launch(AdjBoxArgs a, int planes, hipStream_t s) {
+  // windows of up to 2r + 1 = 65 columns: at most two 64-lane prefix segments
+  if (planes <= 0 || planes > 65535 || a.H < 1 || a.W < 1 || a.r < 0 || a.r > 32)
+    return hipErrorInvalidValue;
+  const dim3 grid(box_plan(a, planes), planes);
+  a.ring = box_lds_bytes(a.r, true) <= kBoxLdsMax ? 1 : 0;
+  const size_t lds = box_lds_bytes(a.r, a.ring != 0);
+  if (wide_segments(a.r)) {
+    if (a.ring)
+      box_dispatch<true, true>(a, grid, lds, s);
+    else
+      box_dispatch<true, false>(a, grid, lds, s);
+  } else {
+    if (a.ring)
+      box_dispatch<false, true>(a, grid, lds, s);
+    else
+      box_dispatch<false, false>(a, grid, lds, s);
+  }
   return hipGetLastError();
 }
 

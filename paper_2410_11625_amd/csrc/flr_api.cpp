@@ -699,7 +699,10 @@ flr_status flr_batch_plan(const flr_params* p, const flr_frame* frames, int32_t 
     b.Q = Q;
     b.C = C;
     b.count_first = 1;
-    const int nx = flr::box_plan(b);
+    // the per-stage run's tiling (same segments: same sums), and the ring
+    // where it fits in the persistent kernel's LDS
+    const int nx = flr::box_plan(b, 1 + flr::num_sums(Q, C));
+    b.ring = flr::box_lds_bytes(b.r, true) <= flr::batch_lds_bytes(Q, C) ? 1 : 0;
     bargs[nb] = b;
     jbox_arg[j] = nb++;
     jctr[j] = nctr;
@@ -726,7 +729,8 @@ flr_status flr_batch_plan(const flr_params* p, const flr_frame* frames, int32_t 
     b.H = out_plan->joint_height[j];
     b.W = out_plan->joint_width[j];
     b.r = p->radius;
-    const int nx = flr::box_plan(b);
+    const int nx = flr::box_plan(b, fc);
+    b.ring = flr::box_lds_bytes(b.r, true) <= flr::batch_lds_bytes(Q, C) ? 1 : 0;
     bargs[nb] = b;
     jmean_arg[j] = nb++;
     jmean_items[j] = stage(flr::BI_JMEAN, jmean_arg[j], nx * fc, nx, jctr[j] + 1,

@@ -26,6 +26,7 @@
 
 #include "flr.h"
 #include "flr_launch.hpp"
+#include "flr_prefix.hpp"
 
 namespace flr {
 
@@ -257,106 +258,6 @@ __device__ __forceinline__ void hbox(const E* __restrict__ src, E* __restrict__ 
   }
 }
 
-// ---------------------------------------------------------------------------
-// Horizontal window sums by segmented prefix sums. Lane l holds the value x_l
-// of its column. An inclusive prefix over aligned segments of L lanes (L = 16,
-// one DPP row, when 2r <= 16; else L = 64, the wavefront) is formed in
-// registers with DPP lane moves, log2(L) add steps, and staged through LDS
-// once. A window [j, j + 2r] with 2r <= L touches at most two segments, so its
-// sum is P[j + 2r] - P[j - 1] + (P[end of j's segment] if it crosses), with
-// P[j - 1] dropped when j starts a segment: three independent LDS reads in
-// place of a serial slide. Segments never cross a wavefront.
-
-// DPP control codes (GFX9 encoding): row_shr:k, row_bcast:15, row_bcast:31.
-constexpr int kDppRowShr = 0x110;
-constexpr int kDppRowBcast15 = 0x142;
-constexpr int kDppRowBcast31 = 0x143;
-constexpr int kDppWaveShr1 = 0x138;
-
-// x of the DPP source lane (0 where the source is outside the row, or the
-// lane's row is masked off), 64-bit values as two 32-bit moves.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double dpp_move(double x) {
-  const long long v = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xf, true);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, ROW_MASK, 0xf, true);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ float dpp_move(float x) {
-  return __int_as_float(
-      __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, true));
-}
-
-// Inclusive prefix of x over its 16-lane row, or over the wavefront (WIDE).
-// Every lane of the wavefront must take part.
-template <bool WIDE, typename E>
-__device__ __forceinline__ E seg_prefix(E x) {
-  x += dpp_move<kDppRowShr + 1, 0xf>(x);
-  x += dpp_move<kDppRowShr + 2, 0xf>(x);
-  x += dpp_move<kDppRowShr + 4, 0xf>(x);
-  x += dpp_move<kDppRowShr + 8, 0xf>(x);
-  if (WIDE) {
-    x += dpp_move<kDppRowBcast15, 0xa>(x);  // row totals 0 -> 1, 2 -> 3
-    x += dpp_move<kDppRowBcast31, 0xc>(x);  // rows 0..1 total -> 2, 3
-  }
-  return x;
-}
-
-// Value of the lane to the left within the prefix segment (0 at its start).
-template <bool WIDE, typename E>
-__device__ __forceinline__ E seg_left(E x) {
-  return WIDE ? dpp_move<kDppWaveShr1, 0xf>(x) : dpp_move<kDppRowShr + 1, 0xf>(x);
-}
-
-// seg_prefix of N values at once, step by step across the values, so that
-// independent moves and adds overlap each other's latency.
-template <int CTRL, int ROW_MASK, int N, typename E>
-__device__ __forceinline__ void seg_step(E (&x)[N]) {
-  E t[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) t[i] = dpp_move<CTRL, ROW_MASK>(x[i]);
-  // keep the N moves ahead of their adds (independent work between a
-  // move and the add that reads it)
-  __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-  for (int i = 0; i < N; ++i) x[i] += t[i];
-}
-template <bool WIDE, int N, typename E>
-__device__ __forceinline__ void seg_prefix_n(E (&x)[N]) {
-  seg_step<kDppRowShr + 1, 0xf>(x);
-  seg_step<kDppRowShr + 2, 0xf>(x);
-  seg_step<kDppRowShr + 4, 0xf>(x);
-  seg_step<kDppRowShr + 8, 0xf>(x);
-  if (WIDE) {
-    seg_step<kDppRowBcast15, 0xa>(x);  // row totals 0 -> 1, 2 -> 3
-    seg_step<kDppRowBcast31, 0xc>(x);  // rows 0..1 total -> 2, 3
-  }
-}
-
-// Prefix segments of 16 lanes serve windows up to 2r + 1 = 17 columns wide.
-__host__ __device__ constexpr bool wide_segments(int r) { return r > 8; }
-
-// LDS columns whose prefixes give the sum of window [j, j + 2r]:
-// P[ib] - P[ia] + P[it]. Terms that do not apply point at the row's pad
-// column kThreads, which holds zero.
-struct HWin {
-  int ib, ia, it;
-};
-template <bool WIDE>
-__device__ __forceinline__ HWin hwin(int j, int r) {
-  constexpr int lm = WIDE ? 63 : 15;
-  HWin h;
-  h.ib = min(j + 2 * r, kThreads - 1);
-  h.ia = (j & lm) != 0 ? j - 1 : kThreads;
-  h.it = (h.ib & ~lm) != (j & ~lm) ? (j | lm) : kThreads;
-  return h;
-}
-template <typename E>
-__device__ __forceinline__ E hwin_sum(const E* row, const HWin& h) {
-  return (row[h.ib] - row[h.ia]) + row[h.it];
-}
-
 // Buffer descriptor of one FP32 plane of `bytes` bytes (raw: stride 0,
 // GFX9 dword-3 format word), and a dword load at vector offset `vo` plus
 // scalar offset `so`.
@@ -484,16 +385,50 @@ __device__ __forceinline__ void group_deltas(int g0, int gn, const sum_t (&ga)[Q
   }
 }
 
+// LDS byte addresses of the three prefix terms of a window (HWin) in a
+// group of prefix rows starting at P: for channels 0..31 of the group and,
+// through a second base with the same immediates, for channels 32 and up, so
+// that every read is a base register plus an immediate offset below 64 KB.
+// The bases pass through lane_opaque so that they are formed once per row
+// rather than hoisted out of the row loop as one address per channel. Every
+// lane of the wavefront must call it (DPP).
+constexpr int kGroupBase = 32;  // channels per base
+struct GroupAddr {
+  int b[2], a[2], t[2];
+};
+__device__ __forceinline__ GroupAddr group_addr(const sum_t* P, const HWin& h) {
+  extern __shared__ float lds[];
+  const int o0 = (int)(reinterpret_cast<const char*>(P) - reinterpret_cast<const char*>(lds));
+  constexpr int RB = kLdsStride * (int)sizeof(sum_t);  // bytes per prefix row
+  constexpr int E = (int)sizeof(sum_t);
+  GroupAddr g;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int o = o0 + j * kGroupBase * RB;
+    g.b[j] = lane_opaque(o + h.ib * E);
+    g.a[j] = lane_opaque(o + h.ia * E);
+    g.t[j] = lane_opaque(o + h.it * E);
+  }
+  return g;
+}
+__device__ __forceinline__ sum_t group_read(const int (&base)[2], int m) {
+  extern __shared__ float lds[];
+  constexpr int RB = kLdsStride * (int)sizeof(sum_t);
+  return *reinterpret_cast<const sum_t*>(reinterpret_cast<const char*>(lds) +
+                                         base[m / kGroupBase] + (m % kGroupBase) * RB);
+}
+
 // Fold the window sums of channels [g0, g0 + gn) (one LDS group of segment
-// prefixes, row stride kLdsStride, read through `h`) into the central
-// moments: mu~, nu, the guide covariance Hm and the guide/channel covariance
-// R. Channel order: sum g | sum y | sum g_p g_q (p <= q) | sum g_q y_c
-// (shifted guides). Groups arrive in increasing order and the first holds all
-// Q + C first moments, so the means are complete before any covariance needs
-// them. All loops unroll and every group test folds at compile time.
+// prefixes, row stride kLdsStride, read through the addresses `ga`) into the
+// central moments: mu~, nu, the guide covariance Hm and the guide/channel
+// covariance R. Channel order: sum g | sum y | sum g_p g_q (p <= q) |
+// sum g_q y_c (shifted guides). Groups arrive in increasing order and the
+// first holds all Q + C first moments, so the means are complete before any
+// covariance needs them. All loops unroll and every group test folds at
+// compile time.
 template <int Q, int C, int MG, int POFF, int PCNT, typename T, typename U>
-__device__ __forceinline__ void centre_group(int g0, int gn, const sum_t* P, const HWin& h,
-                                             T inv_n, T (&mu)[Q], T (&nu)[C],
+__device__ __forceinline__ void centre_group(int g0, int gn, const GroupAddr& ga, T inv_n,
+                                             T (&mu)[Q], T (&nu)[C],
                                              U (&Hm)[Q * (Q + 1) / 2], U (&R)[Q * C]) {
   constexpr int NP = Q * (Q + 1) / 2;
   // window sums of the group: the three prefix reads of four channels are
@@ -506,10 +441,9 @@ __device__ __forceinline__ void centre_group(int g0, int gn, const sum_t* P, con
 #pragma unroll
     for (int i = 0; i < B; ++i) {
       if (k0 + i < gn) {
-        const sum_t* row = P + (k0 + i) * kLdsStride;
-        rb[i] = row[h.ib];
-        ra[i] = row[h.ia];
-        rt[i] = row[h.it];
+        rb[i] = group_read(ga.b, k0 + i);
+        ra[i] = group_read(ga.a, k0 + i);
+        rt[i] = group_read(ga.t, k0 + i);
       }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -814,10 +748,13 @@ __device__ __forceinline__ void walk_tile(const LaunchArgs a, const int bid) {
       // barrier per group separates its prefix writes from its window reads
       // and the reads of the group before last from this group's writes.
       // With an odd group count the first buffer of a row is the one the
-      // previous row's last group read, hence the extra barrier.
+      // previous row's last group read, hence the extra barrier. (Writing
+      // both groups before reading either was measured in the assembly: the
+      // compiler then keeps more values live and spills more.)
       if (NG % 2 == 1) __syncthreads();
-#pragma unroll
-      for (int gi = 0; gi < NG; ++gi) {
+      const HWin hr = hwin_opaque(hw);  // this row's window addresses
+      // prefixes of group gi's channels into its buffer
+      auto walk_group = [&](const int gi) {
         const int g0 = gi * MG;
         const int gn = NS - g0 < MG ? NS - g0 : MG;
         sum_t* P = (gi & 1) ? S1 : S0;
@@ -856,7 +793,13 @@ __device__ __forceinline__ void walk_tile(const LaunchArgs a, const int bid) {
           for (int i = 0; i < IL; ++i)
             if (m0 + i < gn) P[(m0 + i) * kLdsStride + tid] = x[i];
         }
-        __syncthreads();
+      };
+      // window sums of group gi's channels: written out, or centred
+      auto read_group = [&](const int gi) {
+        const int g0 = gi * MG;
+        const int gn = NS - g0 < MG ? NS - g0 : MG;
+        const sum_t* P = (gi & 1) ? S1 : S0;
+        const GroupAddr gad = group_addr(P, hw);  // every lane (DPP)
         if (cvalid) {
           if (MODE == W_MOMENTS && a.raw) {
 #pragma unroll
@@ -864,12 +807,18 @@ __device__ __forceinline__ void walk_tile(const LaunchArgs a, const int bid) {
               const int l = g0 + m;  // local channel -> global channel
               const int gch = l < Q + C ? l : l + POFF;
               if (POFF == 0 || l >= Q + C)
-                a.out[(1 + gch) * pl + off] = (float)hwin_sum(P + m * kLdsStride, hw);
+                a.out[(1 + gch) * pl + off] = (float)hwin_sum(P + m * kLdsStride, hr);
             }
           } else {
-            centre_group<Q, C, MG, POFF, PC, T, chol_t>(g0, gn, P, hw, inv_n, mu, nu, Hm, R);
+            centre_group<Q, C, MG, POFF, PC, T, chol_t>(g0, gn, gad, inv_n, mu, nu, Hm, R);
           }
         }
+      };
+#pragma unroll
+      for (int gi = 0; gi < NG; ++gi) {
+        walk_group(gi);
+        __syncthreads();
+        read_group(gi);
       }
       if (cvalid) {
         if (MODE == W_MOMENTS) {
@@ -1333,13 +1282,13 @@ __global__ void __launch_bounds__(kThreads, 1) batch_kernel(LaunchArgs ain) {
         walk_tile<Q, C, W_COEFFS, WIDE>(P->largs[S.arg], b);
         break;
       case BI_JBOX:
-        box_tile<BOX_PRODUCTS>(P->bargs[S.arg], b % S.nx, b / S.nx);
+        box_tile_any<BOX_PRODUCTS, WIDE>(P->bargs[S.arg], b % S.nx, b / S.nx);
         break;
       case BI_JSOLVE:
         lr_solve_item<Q, C>(P->largs[S.arg], b);
         break;
       case BI_JMEAN:
-        box_tile<BOX_MEAN64>(P->bargs[S.arg], b % S.nx, b / S.nx);
+        box_tile_any<BOX_MEAN64, WIDE>(P->bargs[S.arg], b % S.nx, b / S.nx);
         break;
       case BI_AVG:
         apply_avg_tile<Q, C, AV>(P->largs[S.arg], b);
@@ -1485,10 +1434,7 @@ hipError_t launch_qc(int kind, const LaunchArgs& a, hipStream_t s) {
       return hipGetLastError();
     case K_BATCH_PERSISTENT:
       if constexpr (!split_walk(Q, C)) {
-        // LDS: the larger of the walk's and the averaging kernel's (the box
-        // passes need two FP64 rows)
-        const size_t l = lds_of(K_COEFFS) > lds_of(K_APPLY_AVG) ? lds_of(K_COEFFS)
-                                                                : lds_of(K_APPLY_AVG);
+        const size_t l = batch_lds_bytes(Q, C);
         const int av = avg_variant(a.r, C);
         if (av == AV_BLOCK8) {
           if constexpr (C <= 3) return launch_with_lds(batch_kernel<Q, C, false, AV_BLOCK8>,

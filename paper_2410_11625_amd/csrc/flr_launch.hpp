@@ -127,15 +127,32 @@ struct AdjBoxArgs {
   int H, W, r, seg_rows, tiles_x;
   int Q, C;
   int count_first;  // BOX_PRODUCTS: plane 0 is the window pixel count, channels follow
+  int ring;         // 1: the leaving rows come from an LDS ring of 2r + 1 rows
 };
 
+// LDS bytes of a box pass: two FP64 prefix rows of kThreads + 1, and with
+// the ring 2r + 1 FP64 rows of kThreads.
+inline size_t box_lds_bytes(int r, bool ring) {
+  return (size_t)(2 * (kThreads + 1) + (ring ? (2 * r + 1) * kThreads : 0)) * sizeof(double);
+}
+// Largest LDS of a standalone box launch with the ring (so that several
+// workgroups share a CU); larger radii load the leaving row again.
+constexpr size_t kBoxLdsMax = 64 * 1024;
+
 // Rows per workgroup segment of a box pass, and its tiling: sets plane,
-// seg_rows, tiles_x; returns the workgroups per plane.
-constexpr int kBoxSegRows = 64;
-inline int box_plan(AdjBoxArgs& a) {
+// seg_rows, tiles_x; returns the workgroups per plane. Segments of up to
+// kBoxSegRows rows (each repeats 2r warm-up rows), halved while the
+// `planes` planes of the pass would give fewer than kBoxMinGroups
+// workgroups.
+constexpr int kBoxSegRows = 128;
+constexpr int kBoxMinGroups = 2048;
+inline int box_plan(AdjBoxArgs& a, int planes = 1) {
   a.plane = (int64_t)a.H * a.W;
-  a.seg_rows = kBoxSegRows < a.H ? kBoxSegRows : a.H;
   a.tiles_x = (a.W + (kThreads - 2 * a.r) - 1) / (kThreads - 2 * a.r);
+  int seg = kBoxSegRows;
+  while (seg > 16 && (int64_t)a.tiles_x * ((a.H + seg - 1) / seg) * planes < kBoxMinGroups)
+    seg /= 2;
+  a.seg_rows = seg < a.H ? seg : a.H;
   return a.tiles_x * ((a.H + a.seg_rows - 1) / a.seg_rows);
 }
 
@@ -392,6 +409,13 @@ __host__ __device__ constexpr WalkLayout walk_layout(int Q, int C, int kind, int
 inline size_t walk_lds_bytes(int kind, int Q, int C, int ns_walk = -1) {
   const WalkLayout L = walk_layout(Q, C, kind, ns_walk);
   return L.a + L.b + L.va;
+}
+
+// LDS of the persistent batch kernel: the larger of the walk's and the
+// averaging kernel's (its box items use the ring where it fits in that).
+inline size_t batch_lds_bytes(int Q, int C) {
+  const size_t w = walk_lds_bytes(K_COEFFS, Q, C), v = walk_lds_bytes(K_APPLY_AVG, Q, C);
+  return w > v ? w : v;
 }
 
 // Split walks: when a moment walker's channels exceed what stays resident in

@@ -75,6 +75,7 @@ def build(force: bool = False) -> str:
                    os.path.join(CSRC, "flr_device.hpp"), os.path.join(CSRC, "flr_launch.hpp"),
                    os.path.join(CSRC, "flr_adjoint.hpp"), os.path.join(CSRC, "flr_lowres.hpp"),
                    os.path.join(CSRC, "flr_net_bwd.hpp"), os.path.join(CSRC, "flr_box.hpp"),
+                   os.path.join(CSRC, "flr_prefix.hpp"),
                    os.path.join(INCLUDE, "flr.h"), os.path.join(INCLUDE, "flr_net.h")]
     def fresh():
         return os.path.exists(SO) and \
