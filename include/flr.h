@@ -179,8 +179,9 @@ flr_status flr_denoise(const flr_params* p, const float* guides, const float* no
                        float* out, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Workspace bytes of flr_denoise_backward (0 if invalid): FP64 images of
- * the window moments and of the adjoint's per-pixel fields, about
- * (2*(M - 1) + (2 if averaging, else 1)*(C + 2*Q*C))*8 bytes per pixel. */
+ * the window moments, the coefficients, the adjoint's per-pixel fields and,
+ * with averaging, the window sums of the averaging fields, about
+ * (2*(M - 1) + Q*C + (C + 2*Q*C if averaging))*8 bytes per pixel. */
 size_t flr_denoise_backward_workspace_bytes(const flr_params* p);
 
 /* Gradients of flr_denoise (its adjoint; Sec. 3.3 trains the guide network

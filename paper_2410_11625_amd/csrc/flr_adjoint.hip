@@ -58,6 +58,9 @@ static void box_dispatch(const AdjBoxArgs& a, dim3 grid, size_t lds, hipStream_t
     hipLaunchKernelGGL((adj_box_kernel<BOX_MEAN64, WIDE, RING>), grid, dim3(kThreads), lds, s, a);
   else if (a.src)
     hipLaunchKernelGGL((adj_box_kernel<BOX_SUM64, WIDE, RING>), grid, dim3(kThreads), lds, s, a);
+  else if (a.gout)
+    hipLaunchKernelGGL((adj_box_kernel<BOX_AVGFIELDS, WIDE, RING>), grid, dim3(kThreads), lds, s,
+                       a);
   else
     hipLaunchKernelGGL((adj_box_kernel<BOX_PRODUCTS, WIDE, RING>), grid, dim3(kThreads), lds, s,
                        a);
@@ -121,6 +124,21 @@ hipError_t launch_box_products(const float* guides, const float* noisy, int Q, i
   a.C = C;
   a.count_first = with_count ? 1 : 0;
   return box_launch(a, num_sums(Q, C) + a.count_first, s);
+}
+
+hipError_t launch_box_avgfields(const float* guides, const float* gout, int Q, int C, int H,
+                                int W, int r, double* dst, hipStream_t s) {
+  if (!guides || !gout || !dst) return hipErrorInvalidValue;
+  AdjBoxArgs a = {};
+  a.guides = guides;
+  a.gout = gout;
+  a.dst = dst;
+  a.H = H;
+  a.W = W;
+  a.r = r;
+  a.Q = Q;
+  a.C = C;
+  return box_launch(a, C + Q * C, s);
 }
 
 hipError_t launch_mean_planes64(const double* src, double* dst, int planes, int H, int W, int r,

@@ -88,10 +88,11 @@ __device__ __forceinline__ void centred_moments(const double* S, int64_t pl, dou
   centred_from<Q, C>([&](int ch) { return S[ch * pl]; }, inv_n, mu, nu, Hm, V, vstride);
 }
 
-// Coefficients a of pixel j (FP64, from the moment sums) and the averaging
-// fields G_c / n_j, g~_q G_c / n_j, a_qc: their window sums give B, A~ and
-// n abar; without averaging A~ and B are formed where needed and only a is
-// read back.
+// Coefficients a of pixel j (FP64, from the moment sums), a.fout [Q*C]: with
+// averaging their window sums give n abar (the window sums of the averaging
+// products G_c / n_j and g~_q G_c / n_j, which give B and A~, are formed from
+// the inputs by the window-sum pass); without averaging A~ and B are formed
+// where needed and a is read back.
 template <int Q, int C>
 __global__ void __launch_bounds__(256) adj_coef_kernel(LaunchArgs a) {
   using T = double;
@@ -110,20 +111,8 @@ __global__ void __launch_bounds__(256) adj_coef_kernel(LaunchArgs a) {
   regularise<Q, T>(Hm, mo, (T)arg_eps(a), (T)arg_eps_mul(a), a.reg_mode);
   chol_solve<Q, C, T>(Hm, R);
   double* o = a.fout + idx;
-  T gn[C];
 #pragma unroll
-  for (int c = 0; c < C; ++c) {
-    gn[c] = (T)a.gout[c * pl + idx] * inv_n;
-    o[c * pl] = gn[c];
-  }
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const T g = (T)a.guides[q * pl + idx] - cg[q];
-#pragma unroll
-    for (int c = 0; c < C; ++c) o[(C + q * C + c) * pl] = g * gn[c];
-  }
-#pragma unroll
-  for (int k = 0; k < Q * C; ++k) o[(C + Q * C + k) * pl] = R[k];
+  for (int k = 0; k < Q * C; ++k) o[k * pl] = R[k];
 }
 
 // Solve adjoint of pixel k from its moment sums (a.sums) and A~, B (window
@@ -268,7 +257,8 @@ __global__ void __launch_bounds__(256) adj_solve_kernel(LaunchArgs a) {
 
 // dL/dg and dL/dy of pixel j: the window sums of the solve fields (a.fin)
 // contracted with the anchored g~_j, y~_j, plus abar_j G_j with abar the
-// window sums of a (a.fin2) divided by n_j, or a itself without averaging.
+// window sums of a (a.fin2, Q*C planes) divided by n_j, or a itself without
+// averaging.
 template <int Q, int C>
 __global__ void __launch_bounds__(256) adj_gather_kernel(LaunchArgs a) {
   using T = double;
@@ -289,7 +279,7 @@ __global__ void __launch_bounds__(256) adj_gather_kernel(LaunchArgs a) {
     G[c] = a.gout[c * pl + idx];
   }
   const double* S = a.fin + idx;
-  const double* Ab = a.fin2 + (C + Q * C) * pl + idx;
+  const double* Ab = a.fin2 + idx;
 #pragma unroll
   for (int p = 0; p < Q; ++p) {
     T s = S[(NP + Q * C + p) * pl];

@@ -92,9 +92,10 @@ size_t unfused_coeff_offset(const flr_params* p) {
 
 // Workspace of flr_denoise_backward, byte offsets of 256-aligned FP64
 // regions: the window sums of the anchored input products (later reused for
-// the window sums of the solve fields), the averaging fields, their window
-// sums (with averaging only), the solve fields, and the per-workgroup sums
-// of the regulariser gradients.
+// the window sums of the solve fields), the coefficients a, the window sums
+// of the averaging fields (with averaging only: the averaging products and
+// a), the solve fields, and the per-workgroup sums of the regulariser
+// gradients.
 struct BackwardLayout {
   size_t sums, f1, s1, f2, red, total;
 };
@@ -104,15 +105,15 @@ BackwardLayout backward_layout(const flr_params* p) {
   const size_t pl = (size_t)p->height * p->width;
   const size_t pblocks = (pl + 255) / 256;
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
-  const size_t ns = (size_t)flr::num_sums(Q, C), nf1 = (size_t)flr::num_avg_fields(Q, C);
+  const size_t ns = (size_t)flr::num_sums(Q, C), ns1 = (size_t)flr::num_avg_fields(Q, C);
   BackwardLayout L{};
   size_t o = 0;
   L.sums = o;
   o += al(ns * pl * sizeof(double));
   L.f1 = o;
-  o += al(nf1 * pl * sizeof(double));
+  o += al((size_t)Q * C * pl * sizeof(double));
   L.s1 = o;
-  if (p->average_coeffs) o += al(nf1 * pl * sizeof(double));
+  if (p->average_coeffs) o += al(ns1 * pl * sizeof(double));
   L.f2 = o;
   o += al(ns * pl * sizeof(double));
   L.red = o;
@@ -488,8 +489,13 @@ flr_status flr_denoise_backward(const flr_params* p, const float* guides, const 
   a.average = p->average_coeffs;
   a.fout = f1;
   if ((st = dispatch(Q, C, flr::K_ADJ_COEF, a, stream)) != FLR_OK) return st;
+  // with averaging, s1 = window sums of G / n and g~ G / n (formed from the
+  // inputs), then of the coefficients a
+  const size_t pl = (size_t)H * W;
+  double* s1a = s1 + (size_t)(C + Q * C) * pl;
   if (p->average_coeffs) {
-    if (flr::launch_box(f1, s1, flr::num_avg_fields(Q, C), H, W, r, s) != hipSuccess)
+    if (flr::launch_box_avgfields(guides, grad_out, Q, C, H, W, r, s1, s) != hipSuccess ||
+        flr::launch_box(f1, s1a, Q * C, H, W, r, s) != hipSuccess)
       return FLR_ERR_HIP;
     a.fin = s1;
   }
@@ -499,7 +505,7 @@ flr_status flr_denoise_backward(const flr_params* p, const float* guides, const 
   if (flr::launch_box(f2, s2, flr::num_sums(Q, C), H, W, r, s) != hipSuccess) return FLR_ERR_HIP;
   a.sums = nullptr;
   a.fin = s2;
-  a.fin2 = p->average_coeffs ? s1 : f1;
+  a.fin2 = p->average_coeffs ? s1a : f1;
   a.fout = nullptr;
   a.out = grad_guides;
   a.out2 = grad_noisy;

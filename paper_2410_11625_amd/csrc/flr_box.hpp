@@ -44,8 +44,11 @@ __device__ __forceinline__ void channel_factors(int ch, int Q, int C, int* u, in
 
 // Window sums of FP64 planes (BOX_SUM64), of the anchored products of the
 // inputs (BOX_PRODUCTS: channel `by` is (x_u - c_u)(x_v - c_v) or
-// x_u - c_u, with c the plane's value at pixel (0, 0)), or window means of
-// FP32 planes (BOX_MEAN32: FP64 sums divided by the pixel count).
+// x_u - c_u, with c the plane's value at pixel (0, 0)), of the adjoint's
+// averaging products (BOX_AVGFIELDS: plane `by` is G_c / n or
+// (g_q - c_q) G_c / n, n the pixel's window count), or window means of
+// FP32 or FP64 planes (BOX_MEAN32, BOX_MEAN64: FP64 sums divided by the
+// pixel count).
 //
 // One workgroup: a strip of kThreads input columns (kThreads - 2r output
 // columns) of one plane, walking down a segment of rows. Each lane keeps
@@ -56,11 +59,17 @@ __device__ __forceinline__ void channel_factors(int ch, int Q, int C, int* u, in
 // vertical sums (DPP moves) staged in LDS, three reads per output. Columns
 // outside the image contribute 0, which clips the window at the left and
 // right borders. WIDE: 64-lane prefix segments (r > 8).
-enum BoxSource : int { BOX_SUM64 = 0, BOX_PRODUCTS = 1, BOX_MEAN32 = 2, BOX_MEAN64 = 3 };
+enum BoxSource : int {
+  BOX_SUM64 = 0,
+  BOX_PRODUCTS = 1,
+  BOX_MEAN32 = 2,
+  BOX_MEAN64 = 3,
+  BOX_AVGFIELDS = 4
+};
 
 template <int SRC, bool WIDE, bool RING>
 __device__ __forceinline__ void box_tile(const AdjBoxArgs a, const int bx, const int by) {
-  constexpr bool PRODUCTS = SRC == BOX_PRODUCTS;
+  constexpr bool PRODUCTS = SRC == BOX_PRODUCTS || SRC == BOX_AVGFIELDS;
   constexpr bool F64 = SRC == BOX_SUM64 || SRC == BOX_MEAN64;
   using raw_t = typename std::conditional<F64, double, float>::type;
   extern __shared__ float lds[];
@@ -83,7 +92,18 @@ __device__ __forceinline__ void box_tile(const AdjBoxArgs a, const int bx, const
   const raw_t* pu;
   const raw_t* pv = nullptr;
   double cu = 0.0, cv = 0.0, ku = 1.0, kv = 1.0;
-  if constexpr (PRODUCTS) {
+  if constexpr (SRC == BOX_AVGFIELDS) {
+    // plane by < C: 1 * G_by; else g~_q * G_c with by = C + q C + c
+    const bool ones = by < a.C;
+    const int q = ones ? 0 : (by - a.C) / a.C;
+    const int c = ones ? by : (by - a.C) % a.C;
+    const float* fu = a.guides + (int64_t)q * a.plane;
+    const float* fv = a.gout + (int64_t)c * a.plane;
+    cu = fu[0];
+    ku = ones ? 0.0 : 1.0;
+    pu = fu + col;
+    pv = fv + col;
+  } else if constexpr (PRODUCTS) {
     int u, v;
     const int ch = by - a.count_first;
     const bool ones = ch < 0;  // the pixel count: every factor is 1
@@ -102,15 +122,26 @@ __device__ __forceinline__ void box_tile(const AdjBoxArgs a, const int bx, const
   } else {  // BOX_SUM64, BOX_MEAN64
     pu = a.src + (int64_t)by * a.plane + col;
   }
-  // value of a loaded row: ((u - cu) ku + 1 - ku) ((v - cv) kv + 1 - kv)
-  // for products (no branch on the channel kind), the plane value otherwise
-  auto value = [&](raw_t u, raw_t v) -> double {
-    if constexpr (PRODUCTS) {
+  // the window count of this lane's column (BOX_AVGFIELDS)
+  const int ncx0 = (x + r < W - 1 ? x + r : W - 1) - (x - r > 0 ? x - r : 0) + 1;
+  const int ncx = ncx0 > 0 ? ncx0 : 1;  // lanes right of the image (masked) stay finite
+  // value of a loaded row yy: ((u - cu) ku + 1 - ku) ((v - cv) kv + 1 - kv)
+  // for products (no branch on the channel kind), u ((v / n) for the
+  // averaging products), the plane value otherwise
+  auto value = [&](raw_t u, raw_t v, int yy) -> double {
+    if constexpr (SRC == BOX_AVGFIELDS) {
+      const int ncy = (yy + r < H - 1 ? yy + r : H - 1) - (yy - r > 0 ? yy - r : 0) + 1;
+      const double inv_n = 1.0 / (double)(ncy * ncx);
+      const double t = ((double)u - cu) * ku + (1.0 - ku);
+      return t * ((double)v * inv_n);
+    } else if constexpr (PRODUCTS) {
+      (void)yy;
       const double t = ((double)u - cu) * ku + (1.0 - ku);
       const double w = ((double)v - cv) * kv + (1.0 - kv);
       return t * w;
     } else {
       (void)v;
+      (void)yy;
       return (double)u;
     }
   };
@@ -142,7 +173,7 @@ __device__ __forceinline__ void box_tile(const AdjBoxArgs a, const int bx, const
 #pragma unroll
       for (int u = 0; u < kRowBatch; ++u) {
         const int yy = yb + u;
-        const double m = (inx && yy >= 0 && yy < H) ? value(tu[u], tv[u]) : 0.0;
+        const double m = (inx && yy >= 0 && yy < H) ? value(tu[u], tv[u], yy) : 0.0;
         if (yy <= hi) {
           v += m;
           if constexpr (RING) ring[(yy - lo) * kThreads] = m;
@@ -165,7 +196,7 @@ __device__ __forceinline__ void box_tile(const AdjBoxArgs a, const int bx, const
       const int y = yc + u;
       if (y >= y1) break;  // uniform across the workgroup
       if (y > y0) {
-        const double e = (inx && y + r < H) ? value(eu[u], ev[u]) : 0.0;
+        const double e = (inx && y + r < H) ? value(eu[u], ev[u], y + r) : 0.0;
         double l;
         if constexpr (RING) {
           double* rs = ring + slot * kThreads;
@@ -173,7 +204,7 @@ __device__ __forceinline__ void box_tile(const AdjBoxArgs a, const int bx, const
           *rs = e;
           slot = slot + 1 == R2 ? 0 : slot + 1;
         } else {
-          l = (inx && y - r - 1 >= 0) ? value(lu[u], lv[u]) : 0.0;
+          l = (inx && y - r - 1 >= 0) ? value(lu[u], lv[u], y - r - 1) : 0.0;
         }
         v += e - l;
       }

@@ -1205,7 +1205,7 @@ __device__ __forceinline__ void apply_avg_tile(const LaunchArgs a, const int bid
 }
 
 template <int Q, int C, int AV, bool BATCH = false>
-__global__ void __launch_bounds__(kThreads, 2) apply_avg_kernel(LaunchArgs ain) {
+__global__ void __launch_bounds__(kThreads, kAvgPerCU) apply_avg_kernel(LaunchArgs ain) {
   int bid = blockIdx.x;
   const LaunchArgs a = BATCH ? batch_frame(ain, &bid) : ain;
   apply_avg_tile<Q, C, AV>(a, bid);

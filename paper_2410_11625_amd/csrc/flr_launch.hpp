@@ -122,6 +122,7 @@ struct AdjBoxArgs {
   const double* src;   // FP64 planes, or NULL for the product channels below
   const float* guides; // product channels: guides [Q][H][W]
   const float* noisy;  // product channels: noisy [C][H][W]
+  const float* gout;   // BOX_AVGFIELDS: dL/d(output) [C][H][W]
   double* dst;
   int64_t plane;  // elements per plane
   int H, W, r, seg_rows, tiles_x;
@@ -233,7 +234,8 @@ hipError_t launch_lr_blur(const double* src, double* dst, int planes, int Hl, in
                           const double* taps, hipStream_t s);
 
 // Adjoint field planes (FP64, [planes][H][W]).
-//  averaging fields, K_ADJ_COEF: G_c / n (C), g~_q G_c / n (Q*C), a_qc (Q*C);
+//  averaging fields: G_c / n (C), g~_q G_c / n (Q*C), a_qc (Q*C) (K_ADJ_COEF
+//  writes the a_qc; the window-sum pass forms the others from the inputs);
 //  solve fields, K_ADJ_SOLVE: 2 dW / n (upper triangle), Gv / n (Q*C),
 //  e (Q), f (C) -- num_sums(Q, C) planes.
 __host__ __device__ constexpr int num_avg_fields(int Q, int C) { return C + 2 * Q * C; }
@@ -256,6 +258,12 @@ hipError_t launch_mean_planes64(const double* src, double* dst, int planes, int 
 hipError_t launch_box_products(const float* guides, const float* noisy, int Q, int C, int H,
                                int W, int r, double* dst, hipStream_t s,
                                bool with_count = false);
+// FP64 clipped window sums of the adjoint's averaging products, formed from
+// the inputs: G_c / n (C planes) then g~_q G_c / n (Q*C planes), with G =
+// dL/d(output), n the pixel's window count and g~ each guide shifted by its
+// value at pixel (0, 0).
+hipError_t launch_box_avgfields(const float* guides, const float* gout, int Q, int C, int H,
+                                int W, int r, double* dst, hipStream_t s);
 // dst[0..1] = sums over n entries of the interleaved pairs src[2i], src[2i+1]
 // (fixed order; one workgroup).
 hipError_t launch_pair_sum(const double* src, int n, double* dst, hipStream_t s);
@@ -272,13 +280,18 @@ inline int strip_out_cols(int kind, int r) {
 
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
-// Workgroups of a walker kernel resident per CU (LDS and registers allow two
-// for the coefficient-averaging kernel, one for the others).
-inline int workgroups_per_cu(int kind) { return kind == K_APPLY_AVG ? 2 : 1; }
-
 // Output rows per tile of the coefficient-averaging kernel (sizes its
-// per-lane register arrays).
-constexpr int kAvgTileRows = 17;
+// per-lane register arrays and its LDS), and the workgroups of it that
+// registers and LDS let a CU hold.
+#ifndef FLR_AVG_TILE_ROWS
+#define FLR_AVG_TILE_ROWS 17
+#endif
+constexpr int kAvgTileRows = FLR_AVG_TILE_ROWS;
+constexpr int kAvgPerCU = kAvgTileRows <= 8 ? 4 : (kAvgTileRows <= 12 ? 3 : 2);
+
+// Workgroups of a walker kernel resident per CU (the coefficient-averaging
+// kernel's kAvgPerCU, one for the others).
+inline int workgroups_per_cu(int kind) { return kind == K_APPLY_AVG ? kAvgPerCU : 1; }
 
 // Rows of coefficient halo a walker recomputes above and below its segment.
 inline int row_halo(int kind, int r) { return kind == K_FUSED1 ? r : 0; }

@@ -210,10 +210,11 @@ def test_backward_validates_before_launch(L):
     g, y, go = 0x10000000, 0x20000000, 0x30000000
     dg, dy, reg, ws = 0x40000000, 0x50000000, 0x60000000, 0x70000000
     need = L.flr_denoise_backward_workspace_bytes(ctypes.byref(p))
-    # FP64 moment sums and solve fields (num_sums planes each) plus the
-    # averaging fields and their sums (C + 2QC planes each)
+    # FP64 moment sums and solve fields (num_sums planes each), the
+    # coefficients (QC planes) and the window sums of the averaging fields
+    # (C + 2QC planes)
     ns, nf1 = Q + C + Q * (Q + 1) // 2 + Q * C, C + 2 * Q * C
-    assert need >= (2 * ns + 2 * nf1) * H * W * 8
+    assert need >= (2 * ns + Q * C + nf1) * H * W * 8
     p0 = _params(average_coeffs=0)
     assert L.flr_denoise_backward_workspace_bytes(ctypes.byref(p0)) < need
     assert L.flr_denoise_backward_workspace_bytes(ctypes.byref(_params(radius=-1))) == 0
