@@ -646,7 +646,7 @@ flr_status flr_batch_plan(const flr_params* p, const flr_frame* frames, int32_t 
       a.planes = reinterpret_cast<const float*>(ws + L.coef[i]);
       plan(&q, flr::K_APPLY_AVG, &a);
       apply[np] = a;
-      ws_apply[np + 1] = ws_apply[np] + a.tiles_x * a.n_seg;
+      ws_apply[np + 1] = ws_apply[np] + flr::avg_groups(a.tiles_x * a.n_seg);
       ++np;
     } else {
       a.fin = reinterpret_cast<const double*>(ws + L.mean[i]);

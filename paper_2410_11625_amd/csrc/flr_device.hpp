@@ -1024,7 +1024,7 @@ __host__ __device__ constexpr int avg_variant(int r, int C) {
 }
 
 template <int Q, int C, int AV>
-__device__ __forceinline__ void apply_avg_tile(const LaunchArgs a, const int bid) {
+__device__ __forceinline__ void apply_avg_tile(const LaunchArgs a, const int sx, const int sy) {
   using T = solve_t;
   constexpr bool WIDE = AV == AV_STREAM64;
   constexpr int TH = kAvgTileRows;
@@ -1037,8 +1037,6 @@ __device__ __forceinline__ void apply_avg_tile(const LaunchArgs a, const int bid
   const int W = a.W;
   const int64_t pl = (int64_t)H * W;
   const int tout = kThreads - 2 * r;
-  const int sx = bid % a.tiles_x;
-  const int sy = bid / a.tiles_x;
   const int X0 = sx * tout;
   const int Y0 = sy * a.seg_rows;
   const int th = min(a.seg_rows, H - Y0);
@@ -1204,11 +1202,30 @@ __device__ __forceinline__ void apply_avg_tile(const LaunchArgs a, const int bid
   }
 }
 
+// Tile of averaging workgroup b of a frame's launch range. Workgroups are
+// dealt to the XCDs round-robin, and a frame's range starts at a multiple
+// of kXcds and has avg_groups(tiles) workgroups, so XCD k runs the frame's
+// workgroups k, k + kXcds, ... in order; it gets the k-th run of
+// ceil(tiles / kXcds) tiles in strip-major order. Vertically adjacent tiles
+// of a strip share 2r rows of every coefficient plane, which then stay in
+// that XCD's L2. False for the padding workgroups.
+__device__ __forceinline__ bool avg_tile_xcd(int b, int tiles_x, int n_seg, int* sx, int* sy) {
+  const int tiles = tiles_x * n_seg;
+  const int m = (tiles + kXcds - 1) / kXcds;
+  const int t = (b % kXcds) * m + b / kXcds;
+  if (t >= tiles) return false;
+  *sx = t / n_seg;
+  *sy = t - *sx * n_seg;
+  return true;
+}
+
 template <int Q, int C, int AV, bool BATCH = false>
 __global__ void __launch_bounds__(kThreads, kAvgPerCU) apply_avg_kernel(LaunchArgs ain) {
   int bid = blockIdx.x;
   const LaunchArgs a = BATCH ? batch_frame(ain, &bid) : ain;
-  apply_avg_tile<Q, C, AV>(a, bid);
+  int sx, sy;
+  if (!avg_tile_xcd(bid, a.tiles_x, a.n_seg, &sx, &sy)) return;  // padding
+  apply_avg_tile<Q, C, AV>(a, sx, sy);
 }
 
 }  // namespace flr
@@ -1291,7 +1308,8 @@ __global__ void __launch_bounds__(kThreads, 1) batch_kernel(LaunchArgs ain) {
         box_tile_any<BOX_MEAN64, WIDE>(P->bargs[S.arg], b % S.nx, b / S.nx);
         break;
       case BI_AVG:
-        apply_avg_tile<Q, C, AV>(P->largs[S.arg], b);
+        apply_avg_tile<Q, C, AV>(P->largs[S.arg], b % P->largs[S.arg].tiles_x,
+                                 b / P->largs[S.arg].tiles_x);
         break;
       default:
         up_apply_item<Q, C>(P->largs[S.arg], b);
@@ -1376,11 +1394,15 @@ hipError_t launch_qc(int kind, const LaunchArgs& a, hipStream_t s) {
       switch (avg_variant(a.r, C)) {
         case AV_BLOCK8:
           if constexpr (C <= 3)
-            return launch_with_lds(apply_avg_kernel<Q, C, AV_BLOCK8>, wblocks, lds, a, s);
+            return launch_with_lds(apply_avg_kernel<Q, C, AV_BLOCK8>, avg_groups(wblocks), lds, a,
+                                   s);
           return hipErrorInvalidValue;
         case AV_STREAM64:
-          return launch_with_lds(apply_avg_kernel<Q, C, AV_STREAM64>, wblocks, lds, a, s);
-        default: return launch_with_lds(apply_avg_kernel<Q, C, AV_STREAM16>, wblocks, lds, a, s);
+          return launch_with_lds(apply_avg_kernel<Q, C, AV_STREAM64>, avg_groups(wblocks), lds, a,
+                                 s);
+        default:
+          return launch_with_lds(apply_avg_kernel<Q, C, AV_STREAM16>, avg_groups(wblocks), lds, a,
+                                 s);
       }
     case K_SOLVE:
       hipLaunchKernelGGL((solve_kernel<Q, C>), dim3(pblocks), dim3(256), 0, s, a);

@@ -289,6 +289,12 @@ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 constexpr int kAvgTileRows = FLR_AVG_TILE_ROWS;
 constexpr int kAvgPerCU = kAvgTileRows <= 8 ? 4 : (kAvgTileRows <= 12 ? 3 : 2);
 
+// XCDs of the GPU (workgroups are dealt to them round-robin), and the
+// workgroups of an averaging launch over `tiles` tiles: whole rounds of the
+// XCDs, so that each XCD runs a contiguous run of tiles (apply_avg_kernel).
+constexpr int kXcds = 8;
+inline int avg_groups(int tiles) { return (tiles + kXcds - 1) / kXcds * kXcds; }
+
 // Workgroups of a walker kernel resident per CU (the coefficient-averaging
 // kernel's kAvgPerCU, one for the others).
 inline int workgroups_per_cu(int kind) { return kind == K_APPLY_AVG ? kAvgPerCU : 1; }

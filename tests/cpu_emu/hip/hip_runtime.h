@@ -126,14 +126,21 @@ inline hipError_t hipMemset(void* dst, int v, size_t n) {
   return hipSuccess;
 }
 // Device atomics and fences of the persistent kernels: workgroups run on
-// several host threads, so these are real (sequentially consistent) atomics.
+// several host threads, so these are real atomics. (clang has the
+// __hip_atomic_* builtins for the host too; the sanitizer build uses it.)
+#ifndef __HIP_MEMORY_SCOPE_AGENT
 #define __HIP_MEMORY_SCOPE_AGENT 3
+#endif
 inline int atomicAdd(int* p, int v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
 inline int atomicOr(int* p, int v) { return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST); }
+#if !__has_builtin(__hip_atomic_load)
 inline int __hip_atomic_load(const int* p, int, int) { return __atomic_load_n(p, __ATOMIC_SEQ_CST); }
+#endif
+#if !__has_builtin(__hip_atomic_fetch_add)
 inline int __hip_atomic_fetch_add(int* p, int v, int, int) {
   return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST);
 }
+#endif
 inline void __builtin_amdgcn_fence(int, const char*) { __atomic_thread_fence(__ATOMIC_SEQ_CST); }
 // a short real sleep: emulated workgroups are slow, and a spin-wait's
 // iteration limit must outlast them
