@@ -131,7 +131,10 @@ size_t flr_net_backward_workspace_bytes(int32_t height, int32_t width);
  * gradients are sums over all pixels, added in a fixed order (repeatable
  * bit for bit). Errors as flr_net_forward, FLR_ERR_MODE for accumulate not
  * 0 or 1, FLR_ERR_ALIAS when grad_params or the workspace overlaps an input
- * or each other. */
+ * or each other. Tuning: the data gradients take 16 input channels per
+ * thread on layers of at least FLR_DGRAD_WIDE_PX pixels (environment
+ * variable, read at each call; default 2^18) and 8 below; the result is
+ * bit-identical either way. */
 flr_status flr_net_backward(int32_t height, int32_t width, const float* guides,
                             const float* noisy, const float* params, const void* packed,
                             const float* grad_out, float* grad_params, int32_t accumulate,

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 
 #include "flr.h"
 #include "flr_net.h"
@@ -790,6 +791,20 @@ hipError_t layer_wgrad(int li, const Grids& g, const float* gout, const uint16_t
   return hipGetLastError();
 }
 
+// Pixel count from which the data gradients take 16 input channels per
+// thread: FLR_DGRAD_WIDE_PX from the environment when it holds a number (a
+// tuning knob; the gradients are bit-identical either way, the sum order per
+// channel being the same), else kDgWidePx.
+static size_t dgrad_wide_px() {
+  const char* e = getenv("FLR_DGRAD_WIDE_PX");
+  if (e && *e) {
+    char* end = nullptr;
+    const long long v = strtoll(e, &end, 10);
+    if (end && *end == 0 && v >= 0) return (size_t)v;
+  }
+  return kDgWidePx;
+}
+
 // Gradient of layer li's input (channels 0..cin-1, HWC FP32 into dx), plus
 // an optional addend tensor's channels.
 hipError_t layer_dgrad(int li, const Grids& g, const float* gout, const uint16_t* act,
@@ -797,7 +812,7 @@ hipError_t layer_dgrad(int li, const Grids& g, const float* gout, const uint16_t
                        int add_off, hipStream_t s) {
   const Layer& L = kLayers[li];
   const size_t n = (size_t)Hi * Wi;
-  const int cpt = n >= kDgWidePx ? 16 : 8;
+  const int cpt = n >= dgrad_wide_px() ? 16 : 8;
   if (L.cin % cpt) return hipErrorInvalidValue;  // whole channel groups per thread
   const int og = kOutGrid[li];
   DgradArgs a = {};

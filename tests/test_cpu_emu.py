@@ -86,12 +86,14 @@ def test_emulated_net_backward_matches_oracle():
 
 # The network backward's data-gradient kernel takes 16 input channels per
 # thread on grids of 2^18 pixels or more and 8 below, with the same sum order
-# per channel: a build with the threshold at one pixel (16 everywhere) must
-# give the default build's gradients bit for bit on a small frame.
+# per channel: with the threshold at one pixel (FLR_DGRAD_WIDE_PX=1, 16
+# everywhere) the gradients must equal the default's bit for bit on a small
+# frame.
 def test_emulated_dgrad_variants_bit_equal(monkeypatch):
     spec = dict(kind="net_bwd_digest", H=9, W=13, Q=8, C=3, r=0)
+    monkeypatch.delenv("FLR_DGRAD_WIDE_PX", raising=False)
     default = run_in_subprocess(spec)
-    monkeypatch.setenv("FLR_EMU_VARIANT", "FLR_DGRAD_WIDE_PX=1")
+    monkeypatch.setenv("FLR_DGRAD_WIDE_PX", "1")
     wide = run_in_subprocess(spec)
     assert default["finite"] and default["sha256"] == wide["sha256"]
 

@@ -153,3 +153,20 @@ def test_net_backward_accumulate_and_repeat(params):
                      accumulate=True)
     assert torch.equal(acc, ga + gb)
     assert torch.equal(gb, flr.net_backward(_t(b["guides"]), _t(b["noisy"]), p, packed, Gb))
+
+
+def test_dgrad_channel_widths_bit_equal(params, monkeypatch):
+    """The data gradients take 16 input channels per thread from
+    FLR_DGRAD_WIDE_PX pixels up (default 2^18) and 8 below, with the same
+    sum order per channel: at a threshold of one pixel (16 everywhere) the
+    gradients of a small frame equal the default's bit for bit."""
+    p, packed = params
+    fr = make_config(1, seed=13, h=37, w=70)
+    G = _t(np.random.default_rng(3).standard_normal((4, 37, 70)))
+    monkeypatch.delenv("FLR_DGRAD_WIDE_PX", raising=False)
+    narrow = flr.net_backward(_t(fr["guides"]), _t(fr["noisy"]), p, packed, G)
+    monkeypatch.setenv("FLR_DGRAD_WIDE_PX", "1")
+    wide = flr.net_backward(_t(fr["guides"]), _t(fr["noisy"]), p, packed, G)
+    torch.cuda.synchronize()
+    assert torch.isfinite(narrow).all()
+    assert torch.equal(narrow, wide)
