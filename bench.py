@@ -435,7 +435,8 @@ def time_batch(flr, torch, np, sets, nsets, dev, stream, args):
     for k in range(2):
         frames.append(dict(guides=sets[k][1], guides_low=glo.roll(k, dims=2).contiguous(),
                            noisy=ylo.roll(k, dims=2).contiguous()))
-    tuned = autotune.tune_frames(frames, radius=R, eps=EPS)
+    tuned = autotune.tune_batch_rows(autotune.tune_frames(frames, radius=R, eps=EPS),
+                                     radius=R, eps=EPS)
     sched = autotune.tune_batch(tuned, radius=R, eps=EPS)
 
     def timed(fs, blocks, graph):

@@ -10,6 +10,9 @@ of the frame's size) instead of taken from the launch planner's cost model:
 * the averaging tile height (rows per workgroup, at most 17): the 2r halo
   rows every tile re-reads against the number of tiles (candidates: the
   walk's segment length, which is flr_denoise's choice, and 4, 8, 12, 17);
+* in a batch, one segment length for every plain frame's walk (each
+  frame's own choice, or a longer one: a batch fills the GPU whatever its
+  frames' segment counts, so fewer warm-up rows can win; whole batch timed);
 * the batch schedule: one persistent launch over a work queue of every
   stage's tiles, or one launch per stage (whole batch timed both ways).
 
@@ -159,13 +162,48 @@ def tune_frames(frames: list, radius: int = 8, eps: float = 1e-3) -> list:
     return out
 
 
+def candidate_batch_rows() -> list[int]:
+    """0 (each frame keeps its own walk segment length) and fixed lengths."""
+    return [0, 48, 64, 96, 128]
+
+
+def _batch_desc(frames: list) -> str:
+    return ",".join(f"{f['noisy'].shape[1]}x{f['noisy'].shape[2]}"
+                    + ("j" if f.get("guides_low") is not None else "")
+                    + f"/{f.get('tile_rows', 0)}/{f.get('apply_rows', 0)}" for f in frames)
+
+
+def tune_batch_rows(frames: list, radius: int = 8, eps: float = 1e-3, reps: int = 5) -> list:
+    """The frames with one walk segment length for every plain frame, the
+    fastest of candidate_batch_rows() for the whole batch (one launch per
+    stage; cached). Joint frames are left as they are."""
+    Q = frames[0]["guides"].shape[0]
+    C = frames[0]["noisy"].shape[0]
+    dev = frames[0]["noisy"].device
+    key = f"{arch(dev)}|batchrows|Q{Q}|C{C}|r{radius}|{_batch_desc(frames)}"
+
+    def with_rows(rows):
+        if rows == 0:
+            return list(frames)
+        return [f if f.get("guides_low") is not None else dict(f, tile_rows=rows) for f in frames]
+
+    hit = _lookup(key)
+    if hit is None:
+        times = {}
+        for rows in candidate_batch_rows():
+            b = Batch(with_rows(rows), radius=radius, eps=eps, persistent_blocks=0)
+            times[str(rows)] = _time(b.run, reps)
+        best = min(times, key=times.get)
+        hit = {"rows": int(best), "ms": times}
+        _store(key, hit)
+    return with_rows(hit["rows"])
+
+
 def tune_batch(frames: list, radius: int = 8, eps: float = 1e-3, reps: int = 5) -> dict:
     """The faster batch schedule for these frames (sizes and kinds as the
     key): {"persistent_blocks": 0 (one launch per stage) or the persistent
     grid, "ms": {str(blocks): mean ms}} (cached)."""
-    desc = ",".join(f"{f['noisy'].shape[1]}x{f['noisy'].shape[2]}"
-                    + ("j" if f.get("guides_low") is not None else "")
-                    + f"/{f.get('tile_rows', 0)}/{f.get('apply_rows', 0)}" for f in frames)
+    desc = _batch_desc(frames)
     Q = frames[0]["guides"].shape[0]
     C = frames[0]["noisy"].shape[0]
     dev = frames[0]["noisy"].device

@@ -158,7 +158,12 @@ def test_autotuned_schedule(tmp_path, monkeypatch):
     monkeypatch.setattr(autotune, "_MEM", {})
     rows, times = autotune.tune_tile_rows(200, 700, reps=2)
     assert rows in autotune.candidate_rows(200) and rows in times
-    frames = autotune.tune_frames([_plain(200, 700, 9), _plain(120, 300, 10)])
+    own = autotune.tune_frames([_plain(200, 700, 9), _plain(120, 300, 10)])
+    frames = autotune.tune_batch_rows(own, reps=2)
+    picked = [f["tile_rows"] for f in frames]
+    # each frame's own length, or one candidate length for every frame
+    assert picked == [f["tile_rows"] for f in own] or (
+        len(set(picked)) == 1 and picked[0] in autotune.candidate_batch_rows())
     sched = autotune.tune_batch(frames, reps=2)
     assert sched["persistent_blocks"] >= 0 and len(sched["ms"]) == 2
     b = flr.Batch(frames, persistent_blocks=sched["persistent_blocks"])
