@@ -645,7 +645,7 @@ def main(argv=None):
     if args.summarize_counters:
         return summarize_counters(*args.summarize_counters, args.path)
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (a frame is not split across GPUs; "
+        print("bench.py: measures one GPU only (a frame is not split across GPUs; "
               "independent frames would be distributed one per GPU). Run with --gpus 1.",
               file=sys.stderr)
         return 2
