@@ -136,6 +136,10 @@ def test_config1_stages(cfg1_crop):
 @pytest.mark.parametrize("H,W,Q,C,r", [
     (1, 1, 1, 1, 8), (1, 300, 3, 1, 2), (70, 1, 1, 2, 3), (17, 3, 2, 2, 8), (9, 11, 2, 1, 20),
     (257, 263, 5, 1, 4), (40, 600, 12, 3, 8), (33, 250, 6, 4, 32), (50, 130, 7, 2, 0),
+    # the largest guide and channel counts with the largest radius (142 moment
+    # channels: the walk keeps its sums in registers), and the largest width
+    # and height the boundary accepts
+    (20, 90, 12, 4, 32), (3, 32768, 2, 1, 8), (32768, 4, 1, 1, 3),
 ])
 @pytest.mark.parametrize("average", [True, False])
 def test_shapes_guides_channels(H, W, Q, C, r, average):
