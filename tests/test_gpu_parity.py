@@ -133,6 +133,19 @@ def test_config1_stages(cfg1_crop):
     assert rel_err(out, oref) <= TOL
 
 
+@pytest.mark.parametrize("average", [False, True])
+def test_hand_worked_1x3(average):
+    """The 1 x 3 frame worked by hand from Sec. 3.1's closed form
+    (tests/test_oracle_pins.py): every path gives the exact values."""
+    from tests.test_oracle_pins import HAND_1X3 as h
+    fr = {"guides": np.array(h["g"], np.float32).reshape(1, 1, 3),
+          "noisy": np.array(h["y"], np.float32).reshape(1, 1, 3)}
+    want = np.array(h["averaged" if average else "plain"]).reshape(1, 1, 3)
+    for fused in PATHS:
+        got = gpu_denoise(fr, h["r"], h["eps"], average=average, fused=fused)
+        assert np.max(np.abs(got - want) / np.abs(want)) <= 1e-6, (fused, got)
+
+
 @pytest.mark.parametrize("H,W,Q,C,r", [
     (1, 1, 1, 1, 8), (1, 300, 3, 1, 2), (70, 1, 1, 2, 3), (17, 3, 2, 2, 8), (9, 11, 2, 1, 20),
     (257, 263, 5, 1, 4), (40, 600, 12, 3, 8), (33, 250, 6, 4, 32), (50, 130, 7, 2, 0),

@@ -113,6 +113,31 @@ def test_exact_rational_least_squares_tiny():
     assert _rel(got, out) < 1e-12
 
 
+# A 1 x 3 frame worked by hand from Sec. 3.1's closed form (ridge on the
+# centred system with eps added in covariance scale, reading c4): guide
+# g = (0, 1, 2), channel y = (1, 2, 4), r = 1, eps = 1/2. The clipped
+# windows are {0, 1}, {0, 1, 2}, {1, 2}; their means, variances and
+# covariances give slopes a = V / (W + eps):
+#   {0, 1}:    mu 1/2, nu 3/2, W 1/4, V 1/4 -> a 1/3, b = nu - a mu = 4/3
+#   {0, 1, 2}: mu 1,   nu 7/3, W 2/3, V 1   -> a 6/7, b = 31/21
+#   {1, 2}:    mu 3/2, nu 3,   W 1/4, V 1/2 -> a 2/3, b = 2
+# Per-pixel models give out = b + a g = (4/3, 7/3, 10/3). With the models
+# averaged over each pixel's window (reading c2): abar = (25/42, 13/21,
+# 16/21), bbar = (59/42, 101/63, 73/42), out = (59/42, 20/9, 137/42).
+HAND_1X3 = dict(g=[0.0, 1.0, 2.0], y=[1.0, 2.0, 4.0], r=1, eps=0.5,
+                plain=[4 / 3, 7 / 3, 10 / 3], averaged=[59 / 42, 20 / 9, 137 / 42])
+
+
+@pytest.mark.parametrize("average", [False, True])
+def test_hand_worked_1x3(average):
+    h = HAND_1X3
+    g = np.array(h["g"]).reshape(1, 1, 3)
+    y = np.array(h["y"]).reshape(1, 1, 3)
+    got = ref.flr_reference(y, g, h["r"], h["eps"], "ridge", average=average)
+    want = np.array(h["averaged" if average else "plain"]).reshape(1, 1, 3)
+    assert np.max(np.abs(got - want)) < 1e-14
+
+
 # --------------------------------------------------------------------------
 # Closed forms and special cases.
 
