@@ -9,6 +9,8 @@ point family runs in a subprocess with libasan preloaded. Any report
 arithmetic, invalid shifts, ...) aborts the subprocess and fails the test;
 the results must also still match the oracle.
 """
+import concurrent.futures as cf
+
 import pytest
 
 from tests.cpu_emu.harness import run_in_subprocess
@@ -28,10 +30,27 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("spec", CASES, ids=lambda s: "-".join(
-    f"{k}{v}" for k, v in s.items() if k in ("kind", "H", "W", "Q", "C")))
-def test_sanitized_emulated_case(spec):
-    res = run_in_subprocess(spec, sanitize=True, timeout=900)
+@pytest.fixture(scope="module")
+def sanitized_results():
+    """Every case's result (or its exception), the subprocesses run four at
+    a time (each is single-process; the sanitized build happens once, under
+    the harness's build lock)."""
+    def one(i):
+        try:
+            return run_in_subprocess(CASES[i], sanitize=True, timeout=900)
+        except Exception as e:  # reported by the case's own test
+            return e
+    with cf.ThreadPoolExecutor(max_workers=4) as ex:
+        return list(ex.map(one, range(len(CASES))))
+
+
+@pytest.mark.parametrize("idx", range(len(CASES)), ids=lambda i: "-".join(
+    f"{k}{v}" for k, v in CASES[i].items() if k in ("kind", "H", "W", "Q", "C")))
+def test_sanitized_emulated_case(idx, sanitized_results):
+    spec = CASES[idx]
+    res = sanitized_results[idx]
+    if isinstance(res, Exception):
+        raise res
     kind = spec["kind"]
     if kind == "abi_checks":
         # FLR_ERR_SHAPE x2, RADIUS x2, EPS x2, CHANNELS x3, MODE x3, SHAPE; then
