@@ -409,9 +409,10 @@ def time_batch(flr, torch, np, sets, nsets, dev, stream, args):
     upsampling), 8 guides + constant, r 8, eps 1e-3. Walk segment lengths,
     averaging tile heights and the batch schedule (one persistent launch or
     one launch per stage) from the autotuner; the batch captured in a HIP
-    graph and replayed; the other schedules and the planner's own choices
-    are timed beside it. Frames of one size are shifted copies of one
-    synthetic frame (distinct memory, same statistics)."""
+    graph and replayed; the other schedules, the planner's own choices and
+    the same frames one at a time (the unbatched baseline) are timed beside
+    it. Frames of one size are shifted copies of one synthetic frame
+    (distinct memory, same statistics)."""
     from paper_2410_11625_amd import autotune
     from synth import make_config
 
@@ -435,12 +436,23 @@ def time_batch(flr, torch, np, sets, nsets, dev, stream, args):
     for k in range(2):
         frames.append(dict(guides=sets[k][1], guides_low=glo.roll(k, dims=2).contiguous(),
                            noisy=ylo.roll(k, dims=2).contiguous()))
-    tuned = autotune.tune_batch_rows(autotune.tune_frames(frames, radius=R, eps=EPS),
-                                     radius=R, eps=EPS)
+    single = autotune.tune_frames(frames, radius=R, eps=EPS)
+    tuned = autotune.tune_batch_rows(single, radius=R, eps=EPS)
     sched = autotune.tune_batch(tuned, radius=R, eps=EPS)
 
+    class OneByOne:
+        """The same frames one at a time: a batch of one frame each, with
+        each frame's own tuned segments (the unbatched baseline)."""
+        def __init__(self, fs):
+            self.bs = [flr.Batch([f], radius=R, eps=EPS, persistent_blocks=0) for f in fs]
+
+        def run(self):
+            for b1 in self.bs:
+                b1.run()
+
     def timed(fs, blocks, graph):
-        b = flr.Batch(fs, radius=R, eps=EPS, persistent_blocks=blocks)
+        b = OneByOne(fs) if blocks == "one_by_one" else \
+            flr.Batch(fs, radius=R, eps=EPS, persistent_blocks=blocks)
         for _ in range(3):
             b.run()
         torch.cuda.synchronize()
@@ -475,6 +487,7 @@ def time_batch(flr, torch, np, sets, nsets, dev, stream, args):
     persistent_ms, pb = timed(tuned, None, True)
     per_stage_ms, _ = timed(tuned, 0, True)
     untuned_ms, _ = timed(frames, 0, True)
+    one_ms, _ = timed(single, "one_by_one", True)
     pix = sum(int(f["guides"].shape[1]) * int(f["guides"].shape[2]) for f in frames)
     rows = {f"{f['noisy'].shape[1]}x{f['noisy'].shape[2]}": [f["tile_rows"], f["apply_rows"]]
             for f in tuned}
@@ -488,6 +501,8 @@ def time_batch(flr, torch, np, sets, nsets, dev, stream, args):
             "persistent_items": int(pb.plan.num_items),
             "per_stage_ms_per_batch": round(per_stage_ms, 5),
             "planner_schedule_ms_per_batch": round(untuned_ms, 5),
+            "one_by_one_ms": round(one_ms, 5),
+            "one_by_one_us_per_mpixel": round(one_ms * 1e3 / (pix / 1e6), 1),
             "tile_rows_apply_rows": rows,
             "config": "4x1280x720 + 6x1920x1080 + 4x2560x1440 + 2 joint 1920x1080 from "
                       "960x540 (2x), 8 guides + constant, r 8, eps 1e-3; graph replay of the "
