@@ -418,10 +418,32 @@ flr_status flr_denoise(const flr_params* p, const float* guides, const float* no
     if ((st = flr_coefficients(p, guides, noisy, coeffs, stream)) != FLR_OK) return st;
     return flr_apply(p, guides, coeffs, out, stream);
   }
-  // Too many moment channels for one LDS-resident walk: the two-pass path
-  // takes the stage sequence, whose moment walk is split into two slices.
-  const bool stages = p->fused == FLR_PATH_STAGES ||
-                      (p->fused == FLR_PATH_TWO_PASS && p->average_coeffs);
+  if (p->fused == FLR_PATH_TWO_PASS && p->average_coeffs) {
+    // Too many moment channels for one LDS-resident walk: the walk over the
+    // first slice of the product channels writes its moment planes, the
+    // walk over the second reads them back at each pixel and solves there
+    // (no second slice of planes, no separate solve), then the averaging.
+    float* moments = static_cast<float*>(workspace);
+    float* coeffs =
+        reinterpret_cast<float*>(static_cast<char*>(workspace) + unfused_coeff_offset(p));
+    LaunchArgs a = base_args(p);
+    a.guides = guides;
+    a.noisy = noisy;
+    a.out = moments;
+    plan(p, flr::K_MOMENTS, &a);
+    if ((st = dispatch(Q, C, flr::K_MOMENTS_A, a, stream)) != FLR_OK) return st;
+    LaunchArgs b = base_args(p);
+    b.guides = guides;
+    b.noisy = noisy;
+    b.planes = moments;
+    b.out = coeffs;
+    plan(p, flr::K_COEFFS, &b);
+    if ((st = dispatch(Q, C, flr::K_SPLIT_COEFFS, b, stream)) != FLR_OK) return st;
+    return flr_apply(p, guides, coeffs, out, stream);
+  }
+  // The stage sequence (its moment walk split into two slices when there
+  // are too many moment channels for one LDS-resident walk).
+  const bool stages = p->fused == FLR_PATH_STAGES;
   if (!stages) {
     LaunchArgs a = base_args(p);
     a.guides = guides;

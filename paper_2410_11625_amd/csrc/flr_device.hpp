@@ -537,7 +537,7 @@ __device__ __forceinline__ void reconstruct(const solve_t* col, bool active, con
   }
 }
 
-enum WalkMode : int { W_MOMENTS = 0, W_FUSED0 = 1, W_FUSED1 = 2, W_COEFFS = 3 };
+enum WalkMode : int { W_MOMENTS = 0, W_FUSED0 = 1, W_FUSED1 = 2, W_COEFFS = 3, W_SPLITSOLVE = 4 };
 
 // ---------------------------------------------------------------------------
 // The walker. MODE selects what happens with the window moments of each
@@ -545,6 +545,9 @@ enum WalkMode : int { W_MOMENTS = 0, W_FUSED0 = 1, W_FUSED1 = 2, W_COEFFS = 3 };
 //   W_MOMENTS  write the moment planes (central, or raw sums with a.raw);
 //   W_FUSED0   solve and reconstruct at the same pixel;
 //   W_COEFFS   solve and write the coefficient planes (original units);
+//   W_SPLITSOLVE  (split walks, the second slice) read the first slice's
+//              central moments from the moment planes of the walk over it
+//              (a.planes), then as W_COEFFS;
 //   W_FUSED1   solve, push the coefficients through a per-workgroup ring of
 //              2r+1 rows (global workspace) to form vertical window sums,
 //              stage those through LDS for the horizontal sums, and
@@ -836,6 +839,18 @@ __device__ __forceinline__ void walk_tile(const LaunchArgs a, const int bid) {
               a.out[(1 + Q + C + k) * pl + off] = k < NP ? (float)Hm[k] : (float)R[k - NP];
           }
         } else {
+          if constexpr (MODE == W_SPLITSOLVE) {
+            // the first slice's product channels: central moments written by
+            // the walk over that slice (shift-free, so the anchors agree)
+#pragma unroll
+            for (int k = 0; k < POFF; ++k) {
+              const chol_t v = (chol_t)a.planes[(int64_t)(1 + Q + C + k) * pl + off];
+              if (k < NP)
+                Hm[k] = v;
+              else
+                R[k - NP] = v;
+            }
+          }
           T mu_o[Q];
           chol_t mu_c[Q];
 #pragma unroll
@@ -845,7 +860,7 @@ __device__ __forceinline__ void walk_tile(const LaunchArgs a, const int bid) {
           }
           regularise<Q, chol_t>(Hm, mu_c, (chol_t)arg_eps(a), (chol_t)arg_eps_mul(a), a.reg_mode);
           chol_solve<Q, C, chol_t>(Hm, R);
-          if (MODE == W_COEFFS) {
+          if (MODE == W_COEFFS || MODE == W_SPLITSOLVE) {
             // b = nu - a^T mu in original units
 #pragma unroll
             for (int c = 0; c < C; ++c) {
@@ -1388,6 +1403,16 @@ hipError_t launch_qc(int kind, const LaunchArgs& a, hipStream_t s) {
         const size_t l2 = walk_lds_bytes(K_MOMENTS, Q, C, Q + C + NPQ - PA);
         return wide ? launch_with_lds(walk_kernel<Q, C, W_MOMENTS, true, PA, NPQ - PA>, wblocks, l2, a, s)
                     : launch_with_lds(walk_kernel<Q, C, W_MOMENTS, false, PA, NPQ - PA>, wblocks, l2, a, s);
+      }
+      return hipErrorInvalidValue;
+    case K_SPLIT_COEFFS:
+      if constexpr (split_walk(Q, C)) {
+        constexpr int PA = split_first(Q, C), NPQ = num_products(Q, C);
+        const size_t l2 = walk_lds_bytes(K_COEFFS, Q, C, Q + C + NPQ - PA);
+        return wide ? launch_with_lds(walk_kernel<Q, C, W_SPLITSOLVE, true, PA, NPQ - PA>,
+                                      wblocks, l2, a, s)
+                    : launch_with_lds(walk_kernel<Q, C, W_SPLITSOLVE, false, PA, NPQ - PA>,
+                                      wblocks, l2, a, s);
       }
       return hipErrorInvalidValue;
     case K_APPLY_AVG:

@@ -88,6 +88,8 @@ enum Kind : int {
   K_APPLY_AVG_BATCH = 16,  // K_APPLY_AVG over the tiles of several frames
   K_UP_APPLY_BATCH = 17,   // bilinear upsampling of coefficient planes + reconstruction
   K_BATCH_PERSISTENT = 18, // every stage of a batch in one launch over a work queue
+  K_SPLIT_COEFFS = 19,     // split walks: the walk over the second slice, with the first
+                           // slice's moment planes read back -> solve -> coefficient planes
 };
 
 // One persistent launch for a batch (flr_batch_run): workgroups take items
