@@ -8,7 +8,7 @@ starts; several distinct input/output buffer sets (more than the 256 MB
 Infinity Cache in total) are used in rotation so that repeated steps cannot
 be served from that cache.
 
-Paths: ``two_pass`` (default; flr_coefficients then flr_apply, the fastest),
+Paths: ``two_pass`` (default; flr_coefficients then flr_apply with the intercept pair, the fastest),
 ``fused`` (one kernel) and ``stages`` (flr_moments, flr_solve, flr_apply).
 
 Prints one JSON line. Besides throughput it reports the dominant kernel's
@@ -537,17 +537,18 @@ def time_path(flr, torch, np, sets, nsets, dev, stream, path, steps, warmup):
     algorithmic HBM bytes over the frame time against the HBM peak."""
     p = flr.make_params(H, W, Q, C, R, eps=EPS, average=True, fused=path)
     ws = torch.empty(max(flr.workspace_bytes(p), 1), dtype=torch.uint8, device=dev)
-    coeffs = torch.empty((flr.num_coeff_planes(Q, C), H, W), dtype=torch.float32, device=dev)
+    # the two-pass path's coefficient image: intercepts as hi + lo pairs
+    coeffs = torch.empty((flr.num_coeff_planes(Q, C) + C, H, W), dtype=torch.float32, device=dev)
 
     def step(k, evs=None):
         noisy, guides, out = sets[k % nsets]
         if evs is not None:
             evs[0].record(stream)
         if path == "two_pass":
-            flr.coefficients(guides, noisy, R, eps=EPS, out=coeffs)
+            flr.coefficients(guides, noisy, R, eps=EPS, out=coeffs, intercept_pair=True)
             if evs is not None:
                 evs[1].record(stream)
-            flr.apply(guides, coeffs, R, average=True, out=out)
+            flr.apply(guides, coeffs, R, average=True, out=out, intercept_pair=True)
         else:
             flr.denoise(noisy, guides, radius=R, eps=EPS, average=True, fused=path, out=out,
                         workspace=ws)

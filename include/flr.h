@@ -105,7 +105,10 @@ typedef enum {
                             each workgroup's top and bottom */
   FLR_PATH_TWO_PASS = 2  /* with averaging: one kernel for moments and solve writing the
                             coefficient image to the workspace, then the averaging and
-                            reconstruction of flr_apply; without averaging: as FUSED */
+                            reconstruction of flr_apply; the image holds each intercept
+                            as an FP32 pair (hi, lo: (Q + 2) * C planes), formed in FP64
+                            from the slopes as stored (FLR_FLAG_INTERCEPT_PAIR's
+                            layout, always); without averaging: as FUSED */
 } flr_path;
 
 /* flags */
@@ -113,6 +116,17 @@ typedef enum {
                                    n | sum g | sum y | sum g_p g_q | sum g_q y_c
                                    (same plane order, nothing centred or divided).
                                    Exact for small-integer inputs. */
+#define FLR_FLAG_INTERCEPT_PAIR 2u /* flr_coefficients writes, flr_apply reads, a
+                                   coefficient image of (Q + 2) * C planes: b (hi) [C],
+                                   a [Q][C], b (lo) [C]. The intercept is formed in
+                                   FP64 from the slopes as stored (FP32) and kept as
+                                   hi + lo, so that windows whose intercept and slope
+                                   terms cancel (nearly collinear guides) keep FP64
+                                   accuracy in the output where one FP32 intercept
+                                   does not. flr_solve, flr_denoise_backward,
+                                   flr_denoise_lowres and the batch calls reject it
+                                   (FLR_ERR_MODE); flr_moments, flr_denoise and
+                                   flr_flnr_denoise ignore it. */
 
 typedef struct {
   int32_t height, width;   /* H, W in pixels */

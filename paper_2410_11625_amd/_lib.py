@@ -16,6 +16,7 @@ FLR_OK = 0
 FLR_REG_RIDGE = 0
 FLR_REG_PAPER = 1
 FLR_FLAG_RAW_MOMENTS = 1
+FLR_FLAG_INTERCEPT_PAIR = 2
 FLR_MAX_GUIDES = 12
 FLR_MAX_CHANNELS = 4
 FLR_MAX_RADIUS = 32

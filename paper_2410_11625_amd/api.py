@@ -12,7 +12,7 @@ import math
 
 import torch
 
-from ._lib import (FLR_BATCH_MAX, FLR_FLAG_RAW_MOMENTS, FLR_REG_PAPER, FLR_REG_RIDGE, FLRError,
+from ._lib import (FLR_BATCH_MAX, FLR_FLAG_INTERCEPT_PAIR, FLR_FLAG_RAW_MOMENTS, FLR_REG_PAPER, FLR_REG_RIDGE, FLRError,
                    FlrBatch, FlrFrame, FlrParams, check, lib)
 
 _MODES = {"ridge": FLR_REG_RIDGE, "paper": FLR_REG_PAPER}
@@ -61,7 +61,8 @@ def _eps_device_ptr(eps_device):
 def make_params(H: int, W: int, Q: int, C: int, radius: int, eps: float = 1e-3,
                 mode: str = "ridge", eps_mul: float = 0.0, average: bool = True,
                 fused=True, raw: bool = False, tile_rows: int = 0,
-                eps_device: torch.Tensor | None = None) -> FlrParams:
+                eps_device: torch.Tensor | None = None,
+                intercept_pair: bool = False) -> FlrParams:
     """flr_params; ``eps_device`` (float32 device tensor (eps, eps_mul)) makes
     the kernels read the regularisers from the device instead of eps and
     eps_mul."""
@@ -70,7 +71,8 @@ def make_params(H: int, W: int, Q: int, C: int, radius: int, eps: float = 1e-3,
     return FlrParams(height=H, width=W, num_guides=Q, num_channels=C, radius=radius,
                      eps=eps, eps_mul=eps_mul, reg_mode=_MODES[mode],
                      average_coeffs=int(bool(average)), fused=_path(fused),
-                     flags=FLR_FLAG_RAW_MOMENTS if raw else 0, tile_rows=tile_rows,
+                     flags=(FLR_FLAG_RAW_MOMENTS if raw else 0) |
+                     (FLR_FLAG_INTERCEPT_PAIR if intercept_pair else 0), tile_rows=tile_rows,
                      eps_device=_eps_device_ptr(eps_device))
 
 
@@ -124,16 +126,18 @@ def solve(moment_planes: torch.Tensor, num_guides: int, num_channels: int, eps: 
 
 def coefficients(guides: torch.Tensor, noisy: torch.Tensor, radius: int, eps: float = 1e-3,
                  mode: str = "ridge", eps_mul: float = 0.0, tile_rows: int = 0,
-                 out: torch.Tensor | None = None) -> torch.Tensor:
-    """Moments and solve in one pass -> coefficient planes [(Q+1)*C,H,W]."""
+                 out: torch.Tensor | None = None, intercept_pair: bool = False) -> torch.Tensor:
+    """Moments and solve in one pass -> coefficient planes [(Q+1)*C,H,W]
+    (with ``intercept_pair``: [(Q+2)*C,H,W], the intercepts' lo parts last)."""
     _need(guides, "guides")
     _need(noisy, "noisy")
     Q, H, W = guides.shape
     C = noisy.shape[0]
-    p = make_params(H, W, Q, C, radius, eps=eps, mode=mode, eps_mul=eps_mul, tile_rows=tile_rows)
+    p = make_params(H, W, Q, C, radius, eps=eps, mode=mode, eps_mul=eps_mul, tile_rows=tile_rows,
+                    intercept_pair=intercept_pair)
     if out is None:
-        out = torch.empty((num_coeff_planes(Q, C), H, W), dtype=torch.float32,
-                          device=guides.device)
+        out = torch.empty((num_coeff_planes(Q, C) + (C if intercept_pair else 0), H, W),
+                          dtype=torch.float32, device=guides.device)
     _need(out, "out")
     check(lib().flr_coefficients(ctypes.byref(p), guides.data_ptr(), noisy.data_ptr(),
                                  out.data_ptr(), _stream(guides)), "flr_coefficients")
@@ -141,15 +145,18 @@ def coefficients(guides: torch.Tensor, noisy: torch.Tensor, radius: int, eps: fl
 
 
 def apply(guides: torch.Tensor, coeffs: torch.Tensor, radius: int, average: bool = True,
-          tile_rows: int = 0, out: torch.Tensor | None = None) -> torch.Tensor:
+          tile_rows: int = 0, out: torch.Tensor | None = None,
+          intercept_pair: bool = False) -> torch.Tensor:
     """Optional window-average of the coefficients, then reconstruction -> [C,H,W]."""
     _need(guides, "guides")
     _need(coeffs, "coeffs")
     Q, H, W = guides.shape
-    if coeffs.shape[0] % (Q + 1) != 0:
-        raise ValueError("coefficient plane count must be a multiple of Q+1")
-    C = coeffs.shape[0] // (Q + 1)
-    p = make_params(H, W, Q, C, radius, average=average, tile_rows=tile_rows)
+    F = Q + 2 if intercept_pair else Q + 1
+    if coeffs.shape[0] % F != 0:
+        raise ValueError(f"coefficient plane count must be a multiple of {F}")
+    C = coeffs.shape[0] // F
+    p = make_params(H, W, Q, C, radius, average=average, tile_rows=tile_rows,
+                    intercept_pair=intercept_pair)
     if out is None:
         out = torch.empty((C, H, W), dtype=torch.float32, device=guides.device)
     _need(out, "out")

@@ -85,6 +85,14 @@ size_t ring_bytes(const flr_params* p) {
 
 // Unfused workspace: the moment image, then the coefficient image at the
 // next 256-byte boundary.
+// Bytes of a coefficient image: (Q + 1) C planes, plus C with the intercept
+// pair's lo parts.
+size_t coeff_image_bytes(const flr_params* p) {
+  const size_t planes = (size_t)(p->num_guides + 1) * p->num_channels +
+                        ((p->flags & FLR_FLAG_INTERCEPT_PAIR) ? p->num_channels : 0);
+  return planes * (size_t)p->height * p->width * sizeof(float);
+}
+
 size_t unfused_coeff_offset(const flr_params* p) {
   const size_t mb = flr_num_moment_planes(p->num_guides, p->num_channels) * plane_bytes(p);
   return (mb + 255) / 256 * 256;
@@ -206,8 +214,8 @@ BatchLayout batch_layout(const flr_params* p, const flr_frame* frames, int n) {
   for (int i = 0; i < n; ++i) {
     const size_t px = (size_t)frames[i].noisy_height * frames[i].noisy_width;
     L.coef[i] = o;
-    if (!frame_is_joint(frames[i])) {
-      o += al(fc * px * sizeof(float));
+    if (!frame_is_joint(frames[i])) {  // b (hi), a, b (lo): as flr_denoise's two-pass path
+      o += al((fc + p->num_channels) * px * sizeof(float));
     } else {  // sums, models, means
       o += al(ns1 * px * sizeof(double));
       L.models[i] = o;
@@ -297,7 +305,7 @@ flr_status flr_validate_params(const flr_params* p) {
   if (p->reg_mode != FLR_REG_RIDGE && p->reg_mode != FLR_REG_PAPER) return FLR_ERR_MODE;
   if ((p->average_coeffs != 0 && p->average_coeffs != 1) || p->fused < 0 || p->fused > 2)
     return FLR_ERR_MODE;
-  if (p->flags & ~(uint32_t)FLR_FLAG_RAW_MOMENTS) return FLR_ERR_MODE;
+  if (p->flags & ~(uint32_t)(FLR_FLAG_RAW_MOMENTS | FLR_FLAG_INTERCEPT_PAIR)) return FLR_ERR_MODE;
   if (p->tile_rows < 0) return FLR_ERR_SHAPE;
   if (reinterpret_cast<uintptr_t>(p->eps_device) & 3u) return FLR_ERR_ALIGN;
   return FLR_OK;
@@ -309,10 +317,12 @@ size_t flr_denoise_workspace_bytes(const flr_params* p) {
   if (p->fused == FLR_PATH_STAGES)
     return unfused_coeff_offset(p) + flr_num_coeff_planes(p->num_guides, p->num_channels) * pb;
   if (!p->average_coeffs) return 0;
+  // the two-pass path's coefficient image: b (hi), a, then b (lo)
+  const size_t cb = (flr_num_coeff_planes(p->num_guides, p->num_channels) + p->num_channels) * pb;
   if (p->fused == FLR_PATH_TWO_PASS && !flr::split_walk(p->num_guides, p->num_channels))
-    return flr_num_coeff_planes(p->num_guides, p->num_channels) * pb;
-  if (p->fused == FLR_PATH_TWO_PASS)  // split walks take the stage sequence
-    return unfused_coeff_offset(p) + flr_num_coeff_planes(p->num_guides, p->num_channels) * pb;
+    return cb;
+  if (p->fused == FLR_PATH_TWO_PASS)  // split walks: first slice's moment planes, coefficients
+    return unfused_coeff_offset(p) + cb;
   return ring_bytes(p);
 }
 
@@ -344,6 +354,7 @@ flr_status flr_solve(const flr_params* p, const float* moments, float* coeffs, v
   flr_status st = flr_validate_params(p);
   if (st != FLR_OK) return st;
   if ((st = check_ptrs({moments, coeffs})) != FLR_OK) return st;
+  if (p->flags & FLR_FLAG_INTERCEPT_PAIR) return FLR_ERR_MODE;
   const size_t pb = plane_bytes(p);
   if (overlaps(coeffs, flr_num_coeff_planes(p->num_guides, p->num_channels) * pb, moments,
                flr_num_moment_planes(p->num_guides, p->num_channels) * pb))
@@ -361,7 +372,7 @@ flr_status flr_coefficients(const flr_params* p, const float* guides, const floa
   if ((st = check_ptrs({guides, noisy, coeffs})) != FLR_OK) return st;
   if (p->flags & FLR_FLAG_RAW_MOMENTS) return FLR_ERR_MODE;
   const size_t pb = plane_bytes(p);
-  const size_t cb = flr_num_coeff_planes(p->num_guides, p->num_channels) * pb;
+  const size_t cb = coeff_image_bytes(p);
   if (overlaps(coeffs, cb, guides, p->num_guides * pb) ||
       overlaps(coeffs, cb, noisy, p->num_channels * pb))
     return FLR_ERR_ALIAS;
@@ -369,6 +380,7 @@ flr_status flr_coefficients(const flr_params* p, const float* guides, const floa
   a.guides = guides;
   a.noisy = noisy;
   a.out = coeffs;
+  a.coef_lo = (p->flags & FLR_FLAG_INTERCEPT_PAIR) ? 1 : 0;
   plan(p, flr::K_COEFFS, &a);
   return dispatch(p->num_guides, p->num_channels, flr::K_COEFFS, a, stream);
 }
@@ -381,21 +393,27 @@ flr_status flr_apply(const flr_params* p, const float* guides, const float* coef
   const size_t pb = plane_bytes(p);
   const size_t ob = p->num_channels * pb;
   if (overlaps(out, ob, guides, p->num_guides * pb) ||
-      overlaps(out, ob, coeffs, flr_num_coeff_planes(p->num_guides, p->num_channels) * pb))
+      overlaps(out, ob, coeffs, coeff_image_bytes(p)))
     return FLR_ERR_ALIAS;
   LaunchArgs a = base_args(p);
   a.guides = guides;
   a.planes = coeffs;
   a.out = out;
+  a.coef_lo = (p->flags & FLR_FLAG_INTERCEPT_PAIR) ? 1 : 0;
   const int kind = p->average_coeffs ? flr::K_APPLY_AVG : flr::K_APPLY_POINT;
   if (kind == flr::K_APPLY_AVG) plan(p, kind, &a);
   return dispatch(p->num_guides, p->num_channels, kind, a, stream);
 }
 
-flr_status flr_denoise(const flr_params* p, const float* guides, const float* noisy, float* out,
-                       void* workspace, size_t workspace_bytes, void* stream) {
-  flr_status st = flr_validate_params(p);
+flr_status flr_denoise(const flr_params* p_in, const float* guides, const float* noisy,
+                       float* out, void* workspace, size_t workspace_bytes, void* stream) {
+  flr_status st = flr_validate_params(p_in);
   if (st != FLR_OK) return st;
+  // the intercept-pair flag has no effect here (the two-pass path always
+  // keeps the pair, the stage sequence never)
+  flr_params pc = *p_in;
+  pc.flags &= ~(uint32_t)FLR_FLAG_INTERCEPT_PAIR;
+  const flr_params* p = &pc;
   if ((st = check_ptrs({guides, noisy, out})) != FLR_OK) return st;
   if (p->flags & FLR_FLAG_RAW_MOMENTS) return FLR_ERR_MODE;
   const size_t pb = plane_bytes(p);
@@ -413,10 +431,26 @@ flr_status flr_denoise(const flr_params* p, const float* guides, const float* no
       return FLR_ERR_ALIAS;
   }
   const int Q = p->num_guides, C = p->num_channels;
+  // two-pass: the coefficient image with hi + lo intercepts (LaunchArgs::coef_lo)
+  auto apply_lo = [&](const float* coeffs) {
+    LaunchArgs a = base_args(p);
+    a.guides = guides;
+    a.planes = coeffs;
+    a.out = out;
+    a.coef_lo = 1;
+    plan(p, flr::K_APPLY_AVG, &a);
+    return dispatch(Q, C, flr::K_APPLY_AVG, a, stream);
+  };
   if (p->fused == FLR_PATH_TWO_PASS && p->average_coeffs && !flr::split_walk(Q, C)) {
     float* coeffs = static_cast<float*>(workspace);
-    if ((st = flr_coefficients(p, guides, noisy, coeffs, stream)) != FLR_OK) return st;
-    return flr_apply(p, guides, coeffs, out, stream);
+    LaunchArgs a = base_args(p);
+    a.guides = guides;
+    a.noisy = noisy;
+    a.out = coeffs;
+    a.coef_lo = 1;
+    plan(p, flr::K_COEFFS, &a);
+    if ((st = dispatch(Q, C, flr::K_COEFFS, a, stream)) != FLR_OK) return st;
+    return apply_lo(coeffs);
   }
   if (p->fused == FLR_PATH_TWO_PASS && p->average_coeffs) {
     // Too many moment channels for one LDS-resident walk: the walk over the
@@ -437,9 +471,10 @@ flr_status flr_denoise(const flr_params* p, const float* guides, const float* no
     b.noisy = noisy;
     b.planes = moments;
     b.out = coeffs;
+    b.coef_lo = 1;
     plan(p, flr::K_COEFFS, &b);
     if ((st = dispatch(Q, C, flr::K_SPLIT_COEFFS, b, stream)) != FLR_OK) return st;
-    return flr_apply(p, guides, coeffs, out, stream);
+    return apply_lo(coeffs);
   }
   // The stage sequence (its moment walk split into two slices when there
   // are too many moment channels for one LDS-resident walk).
@@ -633,6 +668,7 @@ flr_status flr_batch_plan(const flr_params* p, const flr_frame* frames, int32_t 
     a.guides = f.guides;
     a.noisy = f.noisy;
     a.out = reinterpret_cast<float*>(ws + L.coef[i]);
+    a.coef_lo = 1;
     plan(&q, flr::K_COEFFS, &a);
     walk[nw] = a;
     blocks[nw] = a.tiles_x * a.n_seg;
@@ -666,6 +702,7 @@ flr_status flr_batch_plan(const flr_params* p, const flr_frame* frames, int32_t 
     a.out = f.out;
     if (!frame_is_joint(f)) {
       a.planes = reinterpret_cast<const float*>(ws + L.coef[i]);
+      a.coef_lo = 1;
       plan(&q, flr::K_APPLY_AVG, &a);
       apply[np] = a;
       ws_apply[np + 1] = ws_apply[np] + flr::avg_groups(a.tiles_x * a.n_seg);

@@ -862,12 +862,25 @@ __device__ __forceinline__ void walk_tile(const LaunchArgs a, const int bid) {
           chol_solve<Q, C, chol_t>(Hm, R);
           if (MODE == W_COEFFS || MODE == W_SPLITSOLVE) {
             // b = nu - a^T mu in original units
+            if (a.coef_lo) {
+              // from the slopes as stored, kept as hi + lo
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-              T b = nu[c];
+              for (int c = 0; c < C; ++c) {
+                T b = nu[c];
 #pragma unroll
-              for (int q = 0; q < Q; ++q) b = fma_t(-(T)R[q * C + c], mu_o[q], b);
-              a.out[c * pl + off] = (float)b;
+                for (int q = 0; q < Q; ++q) b = fma_t(-(T)(float)R[q * C + c], mu_o[q], b);
+                const float hi = (float)b;
+                a.out[c * pl + off] = hi;
+                a.out[((Q + 1) * C + c) * pl + off] = (float)(b - (T)hi);
+              }
+            } else {
+#pragma unroll
+              for (int c = 0; c < C; ++c) {
+                T b = nu[c];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) b = fma_t(-(T)R[q * C + c], mu_o[q], b);
+                a.out[c * pl + off] = (float)b;
+              }
             }
 #pragma unroll
             for (int k = 0; k < Q * C; ++k) a.out[(C + k) * pl + off] = (float)R[k];
@@ -1011,6 +1024,7 @@ __global__ void __launch_bounds__(256) apply_point_kernel(LaunchArgs a) {
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     T acc = a.planes[c * pl + idx];
+    if (a.coef_lo) acc += (T)a.planes[((Q + 1) * C + c) * pl + idx];
 #pragma unroll
     for (int q = 0; q < Q; ++q) acc = fma_t(g[q], (T)a.planes[((1 + q) * C + c) * pl + idx], acc);
     a.out[c * pl + idx] = (float)acc;
@@ -1038,7 +1052,7 @@ __host__ __device__ constexpr int avg_variant(int r, int C) {
   return (r == 8 && C <= 3) ? AV_BLOCK8 : (wide_segments(r) ? AV_STREAM64 : AV_STREAM16);
 }
 
-template <int Q, int C, int AV>
+template <int Q, int C, int AV, bool LO>
 __device__ __forceinline__ void apply_avg_tile(const LaunchArgs a, const int sx, const int sy) {
   using T = solve_t;
   constexpr bool WIDE = AV == AV_STREAM64;
@@ -1131,6 +1145,10 @@ __device__ __forceinline__ void apply_avg_tile(const LaunchArgs a, const int sx,
     for (int k = 0; k < TH; ++k) gf[k] = at(g, Y0 + k, xob);
   };
 
+  // planes: b (C), a (Q C), then with LO the intercepts' lo parts (C),
+  // taken as a pass q = Q that adds like the intercepts
+  constexpr int qend = LO ? Q + 1 : Q;
+  constexpr int nplanes = (qend + 1) * C;
   int buf = 0;
   if constexpr (AV == AV_BLOCK8) {
     // r = 8: the lane loads its column's rows Y0 - 8 .. Y0 + TH + 7 of a
@@ -1156,28 +1174,28 @@ __device__ __forceinline__ void apply_avg_tile(const LaunchArgs a, const int sx,
     float cur[NV];
     load_block(0, cur);
     float gf[TH];
-    for (int q = -1; q < Q; ++q) {
-      if (q >= 0) load_gf(q, gf);
+    for (int q = -1; q < qend; ++q) {
+      if (q >= 0 && q < Q) load_gf(q, gf);
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         const int f = (q + 1) * C + c;
         T vs[TH];
         slide(std::integral_constant<int, 8>{}, cur, vs);
         // the next plane's block streams in during staging and consumption
-        if (f + 1 < (Q + 1) * C) load_block(f + 1, cur);
+        if (f + 1 < nplanes) load_block(f + 1, cur);
         T* P = buf ? P1 : P0;
         buf ^= 1;
         stage(P, vs);
         __syncthreads();
-        if (active) consume(P, c, q < 0, gf);
+        if (active) consume(P, c, q < 0 || q == Q, gf);
       }
     }
   } else {
     // any r: the window of the tile's first row is summed by a running
     // loop; rows entering and leaving are loaded for each later row.
     float gf[TH];
-    for (int q = -1; q < Q; ++q) {
-      if (q >= 0) load_gf(q, gf);
+    for (int q = -1; q < qend; ++q) {
+      if (q >= 0 && q < Q) load_gf(q, gf);
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         const float* src = a.planes + (int64_t)((q + 1) * C + c) * pl;
@@ -1199,7 +1217,7 @@ __device__ __forceinline__ void apply_avg_tile(const LaunchArgs a, const int sx,
         buf ^= 1;
         stage(P, vs);
         __syncthreads();
-        if (active) consume(P, c, q < 0, gf);
+        if (active) consume(P, c, q < 0 || q == Q, gf);
       }
     }
   }
@@ -1215,6 +1233,15 @@ __device__ __forceinline__ void apply_avg_tile(const LaunchArgs a, const int sx,
       }
     }
   }
+}
+
+template <int Q, int C, int AV>
+__device__ __forceinline__ void apply_avg_tile_any(const LaunchArgs& a, const int sx,
+                                                   const int sy) {
+  if (a.coef_lo)
+    apply_avg_tile<Q, C, AV, true>(a, sx, sy);
+  else
+    apply_avg_tile<Q, C, AV, false>(a, sx, sy);
 }
 
 // Tile of averaging workgroup b of a frame's launch range. Workgroups are
@@ -1240,7 +1267,7 @@ __global__ void __launch_bounds__(kThreads, kAvgPerCU) apply_avg_kernel(LaunchAr
   const LaunchArgs a = BATCH ? batch_frame(ain, &bid) : ain;
   int sx, sy;
   if (!avg_tile_xcd(bid, a.tiles_x, a.n_seg, &sx, &sy)) return;  // padding
-  apply_avg_tile<Q, C, AV>(a, sx, sy);
+  apply_avg_tile_any<Q, C, AV>(a, sx, sy);
 }
 
 }  // namespace flr
@@ -1323,8 +1350,8 @@ __global__ void __launch_bounds__(kThreads, 1) batch_kernel(LaunchArgs ain) {
         box_tile_any<BOX_MEAN64, WIDE>(P->bargs[S.arg], b % S.nx, b / S.nx);
         break;
       case BI_AVG:
-        apply_avg_tile<Q, C, AV>(P->largs[S.arg], b % P->largs[S.arg].tiles_x,
-                                 b / P->largs[S.arg].tiles_x);
+        apply_avg_tile_any<Q, C, AV>(P->largs[S.arg], b % P->largs[S.arg].tiles_x,
+                                     b / P->largs[S.arg].tiles_x);
         break;
       default:
         up_apply_item<Q, C>(P->largs[S.arg], b);

@@ -187,6 +187,12 @@ struct LaunchArgs {
   const float* eps_dev;  // when set: (eps, eps_mul) read from device memory instead
   int reg_mode;
   int raw;
+  // K_COEFFS / K_SPLIT_COEFFS / K_APPLY_AVG (and their batched forms): the
+  // coefficient image carries each intercept as an FP32 pair, hi in plane c
+  // and lo in plane (Q + 1) C + c, formed in FP64 from the slopes as stored
+  // (FP32), so that the model's value at the window mean is kept to FP64
+  // accuracy where a fit's intercept and slope terms cancel
+  int coef_lo;
   // adjoint kernels only
   const float* gout;     // dL/d(output) [C][H][W]
   const float* coeffs;   // unaveraged coefficient planes (b | a)

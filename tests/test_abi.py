@@ -179,6 +179,14 @@ def test_null_alignment_alias_and_workspace_errors(L):
     assert L.flr_moments(ctypes.byref(p), g, y, g, None) == 6
     assert L.flr_solve(ctypes.byref(p), g, g + 64, None) == 6
     assert L.flr_apply(ctypes.byref(p), g, y, None, None) == 1
+    # the intercept-pair flag: flr_solve rejects it; flr_apply's alias check
+    # covers the (Q + 2) C planes it then reads
+    pp = _params(fused=0, flags=2)
+    assert L.flr_validate_params(ctypes.byref(pp)) == 0
+    assert L.flr_solve(ctypes.byref(pp), g, o, None) == 9
+    FC = L.flr_num_coeff_planes(4, 3)
+    assert L.flr_apply(ctypes.byref(pp), g, y, y + FC * plane, None) == 6
+    assert L.flr_validate_params(ctypes.byref(_params(flags=4))) == 9
 
 
 def test_workspace_sizes(L):
@@ -192,7 +200,8 @@ def test_workspace_sizes(L):
     pf1 = _params()
     assert L.flr_denoise_workspace_bytes(ctypes.byref(pf1)) > 0
     p2 = _params(fused=2)
-    assert L.flr_denoise_workspace_bytes(ctypes.byref(p2)) == FC * H * W * 4
+    # b (hi), a, b (lo)
+    assert L.flr_denoise_workspace_bytes(ctypes.byref(p2)) == (FC + C) * H * W * 4
     assert L.flr_denoise_workspace_bytes(ctypes.byref(_params(fused=2, average_coeffs=0))) == 0
     assert L.flr_denoise_workspace_bytes(ctypes.byref(_params(radius=-1))) == 0
 

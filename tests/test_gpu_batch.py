@@ -170,8 +170,8 @@ def test_autotuned_schedule(tmp_path, monkeypatch):
     outs = b.run()
     for f, out in zip(frames, outs):
         tr, ar = f["tile_rows"], f["apply_rows"]
-        co = flr.coefficients(f["guides"], f["noisy"], 8, tile_rows=tr)
-        one = flr.apply(f["guides"], co, 8, tile_rows=ar if ar else tr)
+        co = flr.coefficients(f["guides"], f["noisy"], 8, tile_rows=tr, intercept_pair=True)
+        one = flr.apply(f["guides"], co, 8, tile_rows=ar if ar else tr, intercept_pair=True)
         assert torch.equal(out, one)
     import json
     data = json.load(open(tmp_path / "tune.json"))
