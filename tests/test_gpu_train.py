@@ -11,10 +11,12 @@
 * Training works: on a fixed batch of the training workload the loss falls.
 * A checkpoint (state_dict through a safetensors file) resumes the run: the
   resumed trainer's next step equals the uninterrupted one, bit for bit.
+* One trainer step end to end against the oracle's loss, weight gradients
+  and dL/deps, on a target placed so that every sign of out - target is
+  decided with a wide margin (the L1 gradient's sign is a decision a
+  rounding-level difference of the 12-guide regression could flip).
 The parts' own parity is tested in test_gpu_net.py, test_gpu_adjoint.py and
-test_gpu_net_backward.py. The full step is not compared end to end with the
-oracle: the L1 gradient takes a sign of out - target, a decision that a
-rounding-level difference of the 12-guide regression flips.
+test_gpu_net_backward.py.
 """
 import numpy as np
 import pytest
@@ -201,3 +203,48 @@ def test_checkpoint_resume(tmp_path, learn):
     assert torch.equal(a.reg, b.reg) and torch.equal(a.reg_state, b.reg_state)
     if learn:
         assert a.flr_eps != 1e-3 and a.flr_eps_mul != 0.1
+
+
+# One trainer step end to end against the oracle (oracle.net_adjoint's
+# flnr_l1_gradients: the network, FLR over the 12 guides, the L1 loss, the
+# FLR adjoint and the network backward, all FP64 but the network's BF16
+# roundings). The L1 gradient takes the sign of out - target, a decision a
+# rounding-level difference could flip; the target is therefore the
+# oracle's own output moved by +-0.05 per element (seeded signs), so every
+# sign is decided with a margin far above the two sides' difference. The
+# frame is one on which the two network forwards round alike (checked:
+# within 1e-5), so that the gradients compare at the BF16 path's 2e-3 of
+# each layer's largest; dL/deps at 2e-3 relative.
+def test_trainer_step_matches_oracle_gradients():
+    from oracle import flr_ref, net_adjoint, net_ref
+    from synth import random_frame
+    from synth.net_weights import LAYERS
+    dev = _dev()
+    H, W, r = 20, 36, 8
+    fr = random_frame(H, W, 8, 3, seed=21)
+    weights = make_net_weights(3)
+    eps = float(np.float32(1e-3))  # the regulariser as the device holds it
+    extra = net_ref.net_forward(fr["guides"], fr["noisy"], weights, bf16=True)
+    out_ref = flr_ref.flr_reference(fr["noisy"], np.concatenate([fr["guides"], extra]), r, eps)
+    signs = np.where(np.random.default_rng(22).random(out_ref.shape) < 0.5, -1.0, 1.0)
+    target = out_ref + 0.05 * signs
+    loss, grads, deps = net_adjoint.flnr_l1_gradients(fr["guides"], fr["noisy"], target, weights,
+                                                      r, eps, bf16=True)
+    params = _t(flatten_net_weights(weights))
+    g, y = _t(fr["guides"]), _t(fr["noisy"])
+    net_out = flr.net_forward(g, y, flr.net_pack(params)).cpu().numpy()
+    assert np.max(np.abs(net_out - extra)) <= 1e-5  # the forwards round alike
+    tr = flr.FLNRTrainer(params.clone(), radius=r)
+    losses = tr.step([dict(guides=g, noisy=y, target=_t(target))])
+    torch.cuda.synchronize()
+    assert abs(float(losses.sum().item()) - loss) <= 2e-3 * loss
+    dreg = tr.last_dreg.cpu().numpy()
+    assert abs(dreg[0, 0] - deps) <= 2e-3 * abs(deps), (dreg[0, 0], deps)
+    got, o = tr.grad.cpu().numpy().astype(np.float64), 0
+    for name, _, _, _ in LAYERS:
+        for ref in grads[name]:
+            n = ref.size
+            err = np.max(np.abs(got[o:o + n].reshape(ref.shape) - ref))
+            assert err <= 2e-3 * max(np.max(np.abs(ref)), 1e-30), name
+            o += n
+    assert o == got.size
