@@ -158,9 +158,10 @@ size_t flr_num_coeff_planes(int32_t num_guides, int32_t num_channels);
  * FLR_PATH_STAGES: the moment and coefficient images, (M + F*C)*H*W floats
  * (the coefficient image starts at the next 256-byte boundary);
  * FLR_PATH_FUSED with averaging: a per-workgroup ring of 2r+1 coefficient rows;
- * FLR_PATH_TWO_PASS with averaging: the coefficient image, F*C*H*W floats
- * (as STAGES when Q + C + Q(Q+1)/2 + Q*C exceeds 78 moment channels: the
- * path then runs the stage sequence with its moment walk split in two);
+ * FLR_PATH_TWO_PASS with averaging: the coefficient image with intercept
+ * pairs, (F + 1)*C*H*W floats (F = Q + 1; when Q + C + Q(Q+1)/2 + Q*C
+ * exceeds 78 moment channels the walk is split in two and the image
+ * follows the first slice's M moment planes at the next 256-byte boundary);
  * without averaging: 0 (STAGES aside). Depends on the launch geometry only. */
 size_t flr_denoise_workspace_bytes(const flr_params* p);
 
@@ -293,7 +294,7 @@ typedef struct {
 } flr_batch;
 
 /* Workspace bytes of a batch (0 if invalid): the launch tables, the
- * coefficient image (FP32) of every plain frame, and for every joint frame
+ * coefficient image (FP32, intercept pairs) of every plain frame, and for every joint frame
  * FP64 images on its noisy grid: the window count and moment sums, the
  * models and their window means. */
 size_t flr_batch_workspace_bytes(const flr_params* p, const flr_frame* frames,
