@@ -160,8 +160,9 @@ size_t flr_num_coeff_planes(int32_t num_guides, int32_t num_channels);
  * FLR_PATH_FUSED with averaging: a per-workgroup ring of 2r+1 coefficient rows;
  * FLR_PATH_TWO_PASS with averaging: the coefficient image with intercept
  * pairs, (F + 1)*C*H*W floats (F = Q + 1; when Q + C + Q(Q+1)/2 + Q*C
- * exceeds 78 moment channels the walk is split in two and the image
- * follows the first slice's M moment planes at the next 256-byte boundary);
+ * exceeds 78 moment channels the walk is split in two: first a moment
+ * image of M planes, of which the first slice's are written, then the
+ * coefficient image at the next 256-byte boundary);
  * without averaging: 0 (STAGES aside). Depends on the launch geometry only. */
 size_t flr_denoise_workspace_bytes(const flr_params* p);
 
